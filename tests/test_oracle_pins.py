@@ -1,0 +1,336 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+None of these compares the oracle with itself: each one checks a closed form,
+an invariant, an exact worked example, a reduction to a textbook method, or a
+convergence rate.  They run on the CPU only.
+"""
+from __future__ import annotations
+
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from mhm_inputs import configs
+from mhm_inputs.fields import manufactured_solution, manufactured_source
+from mhm_inputs.mesh import coarse_mesh, element_vertices
+from oracle import local, skeleton
+from tests import galerkin_ref
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _ones(p):
+    return np.ones(p.shape[:-1])
+
+
+def _smooth_k(p):
+    return 1.0 + 0.5 * np.sin(3.0 * p[..., 0] + 1.0) * np.cos(2.0 * p[..., 1])
+
+
+def _rand_element(rng, s, l):
+    """A random counter-clockwise triangle with log-normal K and random f."""
+    while True:
+        v = rng.uniform(-1, 1, size=6)
+        cross = (v[2] - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (v[3] - v[1])
+        if abs(cross) > 0.2:
+            break
+    if cross < 0:
+        v = np.array([v[0], v[1], v[4], v[5], v[2], v[3]])
+    sigma = rng.choice([-1, 1], size=3).astype(np.int8)
+    flip = rng.integers(0, 2, size=3).astype(np.int8)
+    kappa = np.exp(rng.standard_normal(s * s))
+    f = rng.standard_normal(s * s)
+    return v, s, l, sigma, flip, kappa, f
+
+
+# --------------------------------------------------------------- exact s = 1
+def test_s1_exact_rational_worked_example():
+    """Oracle == exact rational derivation for one sub-triangle (s = 1, l = 2)."""
+    with open(os.path.join(GOLDEN, "s1_triangle_345.json")) as fh:
+        g = json.load(fh)
+    vert = np.array(g["vert"], dtype=np.float64).ravel()
+    r = local.local_problem(vert, 1, g["l"], np.array(g["sigma"], np.int8), np.array(g["flip"], np.int8),
+                            np.array([float(Fraction(g["kappa"]))]), np.array([float(Fraction(g["f"]))]))
+    for key in ("A", "c", "R", "b", "X", "M", "E", "B"):
+        want = np.array([[float(Fraction(x)) for x in row] if isinstance(row, list) else float(Fraction(row))
+                         for row in g["values"][key]])
+        np.testing.assert_allclose(r[key], want, rtol=1e-13, atol=1e-13, err_msg=key)
+    assert r["F"] == pytest.approx(float(Fraction(g["values"]["F"])), rel=1e-14)
+
+
+def test_golden_fixture_is_reproducible(tmp_path):
+    from tests.golden import make_s1_triangle_345 as mk
+    out = mk.main(str(tmp_path / "g.json"))
+    with open(os.path.join(GOLDEN, "s1_triangle_345.json")) as fh:
+        assert json.load(fh)["values"] == out["values"]
+
+
+# --------------------------------------------------------------------- A, c
+@pytest.mark.parametrize("s", [1, 3, 8])
+def test_stiffness_symmetric_zero_row_sum(s):
+    rng = np.random.default_rng(s)
+    v, s, l, sg, fl, kap, f = _rand_element(rng, s, 1)
+    A = local.stiffness(v, s, kap)
+    assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+    assert np.abs(A.sum(axis=1)).max() <= 1e-13 * np.abs(A).max()
+    # positive semi-definite with the constants as its only null vector
+    w = np.linalg.eigvalsh(A)
+    assert abs(w[0]) < 1e-12 * w[-1] and w[1] > 1e-8 * w[-1]
+
+
+def test_stiffness_is_five_point_stencil_for_unit_k():
+    """K = 1 on a right-isoceles parent: the P1 matrix is the 5-point stencil.
+    Couplings along the two axis directions are -1 inside the element and -1/2
+    along its boundary (one sub-triangle instead of two), couplings across the
+    hypotenuse direction vanish, interior diagonals are 4 and boundary
+    diagonals are 0.5, 1 or 2."""
+    s = 6
+    mesh = coarse_mesh(1)
+    for vert in element_vertices(mesh):
+        nodes, _ = local.submesh(vert, s)
+        A = local.stiffness(vert, s, np.ones(s * s))
+        h = 1.0 / s
+        on_face = [set(local.face_nodes(e, s)) for e in range(3)]
+        boundary = set().union(*on_face)
+        for p in range(nodes.shape[0]):
+            for q in range(nodes.shape[0]):
+                if p == q:
+                    continue
+                dist = np.hypot(*(nodes[q] - nodes[p]))
+                if abs(dist - h) < 1e-12:
+                    shared = any(p in fs and q in fs for fs in on_face)
+                    assert A[p, q] == pytest.approx(-0.5 if shared else -1.0, abs=1e-13)
+                else:
+                    assert abs(A[p, q]) < 1e-13
+            if p in boundary:
+                assert round(A[p, p], 12) in (0.5, 1.0, 2.0)
+            else:
+                assert A[p, p] == pytest.approx(4.0, abs=1e-13)
+
+
+@pytest.mark.parametrize("s", [1, 2, 5, 16])
+def test_mean_vector_closed_form(s):
+    rng = np.random.default_rng(10 + s)
+    v = _rand_element(rng, s, 0)[0]
+    c = local.mean_vector(v, s)
+    area = 0.5 * abs((v[2] - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (v[3] - v[1]))
+    assert c.sum() == pytest.approx(area, rel=1e-14)
+    unit = area / (3.0 * s * s)
+    counts = set(np.round(c / unit).astype(int).tolist())
+    assert counts <= {1, 3, 6}
+    assert np.allclose(c / unit, np.round(c / unit), atol=1e-12)
+
+
+# ----------------------------------------------------------------- face loads
+@pytest.mark.parametrize("s,l", [(1, 0), (4, 1), (7, 3)])
+def test_face_load_sum_rule_and_q0_values(s, l):
+    rng = np.random.default_rng(20 + s)
+    v, s, l, sg, fl, kap, f = _rand_element(rng, s, l)
+    R = local.face_loads(v, s, l, sg, fl)
+    for e in range(3):
+        L = local.face_length(v, e)
+        for q in range(l + 1):
+            col = R[:, e * (l + 1) + q]
+            want = -sg[e] * L if q == 0 else 0.0
+            assert col.sum() == pytest.approx(want, abs=1e-13)
+        col0 = R[:, e * (l + 1)]
+        nodes = local.face_nodes(e, s)
+        assert col0[nodes[0]] == pytest.approx(-sg[e] * L / (2 * s))
+        assert col0[nodes[-1]] == pytest.approx(-sg[e] * L / (2 * s))
+        for k in nodes[1:-1]:
+            assert col0[k] == pytest.approx(-sg[e] * L / s)
+        others = np.setdiff1d(np.arange(R.shape[0]), nodes)
+        assert np.all(R[others, e * (l + 1):(e + 1) * (l + 1)] == 0.0)
+
+
+@pytest.mark.parametrize("s,l", [(3, 2), (6, 3)])
+def test_face_loads_against_gauss_quadrature_moments(s, l):
+    """sum_j R[j,(e,q)] g(x_j) = -sigma int_F P_q g ds for every linear g
+    (nodal interpolation is exact for linear g); the right side is computed
+    with a 10-point Gauss rule in the global face orientation."""
+    rng = np.random.default_rng(30 + s)
+    v, s, l, sg, fl, kap, f = _rand_element(rng, s, l)
+    R = local.face_loads(v, s, l, sg, fl)
+    nodes, _ = local.submesh(v, s)
+    gx, gw = np.polynomial.legendre.leggauss(10)
+    for a_vec in ([1.0, 0.0], [0.0, 1.0], [0.3, -0.7]):
+        g = nodes @ np.array(a_vec) + 0.25
+        for e in range(3):
+            p_start = v[2 * ((e + 1) % 3): 2 * ((e + 1) % 3) + 2]
+            p_end = v[2 * ((e + 2) % 3): 2 * ((e + 2) % 3) + 2]
+            L = np.hypot(*(p_end - p_start))
+            lo, hi = (p_end, p_start) if fl[e] else (p_start, p_end)   # t = -1 at 'lo'
+            pts = lo[None, :] + 0.5 * (gx[:, None] + 1.0) * (hi - lo)[None, :]
+            gval = pts @ np.array(a_vec) + 0.25
+            for q in range(l + 1):
+                Pq = np.polynomial.legendre.legval(gx, [0] * q + [1])
+                want = -sg[e] * 0.5 * L * np.sum(gw * Pq * gval)
+                got = R[:, e * (l + 1) + q] @ g
+                assert got == pytest.approx(want, abs=1e-13)
+
+
+def test_sigma_flip_match_geometric_definition():
+    """The generator's sign n.n^K_F and orientation flags, re-derived from the
+    coordinates: +1 where the element's outward normal agrees with the face's
+    global normal (taken outward on the boundary, else pointing out of the
+    lower-indexed neighbour)."""
+    mesh = coarse_mesh(3)
+    V = mesh["verts"]
+    for g, (a, b) in enumerate(mesh["faces"]):
+        owners = [t for t in mesh["face_elems"][g] if t >= 0]
+        t_ref = min(owners)
+        e_ref = list(mesh["elem_face"][t_ref]).index(g)
+        for t in owners:
+            e = list(mesh["elem_face"][t]).index(g)
+            tri = V[mesh["elems"][t]]
+            d = tri[(e + 2) % 3] - tri[(e + 1) % 3]
+            n_out = np.array([d[1], -d[0]])
+            tri_r = V[mesh["elems"][t_ref]]
+            dr = tri_r[(e_ref + 2) % 3] - tri_r[(e_ref + 1) % 3]
+            n_glob = np.array([dr[1], -dr[0]])
+            assert mesh["sigma"][t, e] == (1 if n_out @ n_glob > 0 else -1)
+            ia, ib = mesh["elems"][t][(e + 1) % 3], mesh["elems"][t][(e + 2) % 3]
+            assert mesh["flip"][t, e] == (1 if ia > ib else 0)
+        if len(owners) == 1:
+            mid = 0.5 * (V[a] + V[b])
+            assert np.isclose(mid, 0).any() or np.isclose(mid, 1).any()
+
+
+# ----------------------------------------------------------- local solutions
+def test_linear_reproduction_constant_k():
+    """For constant K0 and a vector a, sum_e -sigma_e K0 (a.n_e) eta^(e,0) is
+    the zero-mean linear function a.(x - centroid), exactly, at the nodes."""
+    rng = np.random.default_rng(7)
+    for s in (2, 5, 9):
+        v, s, l, sg, fl, _, f = _rand_element(rng, s, 1)
+        K0 = 3.7
+        r = local.local_problem(v, s, l, sg, fl, np.full(s * s, K0), f)
+        nodes, _ = local.submesh(v, s)
+        cen = v.reshape(3, 2).mean(axis=0)
+        for a_vec in (np.array([1.0, 0.0]), np.array([0.2, -1.3])):
+            u = np.zeros(nodes.shape[0])
+            for e in range(3):
+                p0 = v[2 * ((e + 1) % 3): 2 * ((e + 1) % 3) + 2]
+                p1 = v[2 * ((e + 2) % 3): 2 * ((e + 2) % 3) + 2]
+                d = p1 - p0
+                n_out = np.array([d[1], -d[0]]) / np.hypot(*d)
+                u += -sg[e] * K0 * (a_vec @ n_out) * r["X"][:, e * (l + 1)]
+            np.testing.assert_allclose(u, (nodes - cen) @ a_vec, atol=1e-13)
+
+
+def test_constant_source_gives_zero_eta_f():
+    rng = np.random.default_rng(8)
+    v, s, l, sg, fl, kap, _ = _rand_element(rng, 6, 2)
+    r = local.local_problem(v, s, l, sg, fl, kap, np.full(s * s, 2.5))
+    assert np.abs(r["X"][:, -1]).max() < 1e-14
+    assert np.abs(r["E"]).max() < 1e-14
+    assert r["F"] == pytest.approx(2.5 * r["area"], rel=1e-14)
+
+
+def test_solutions_zero_mean_and_galerkin_equations():
+    rng = np.random.default_rng(9)
+    v, s, l, sg, fl, kap, f = _rand_element(rng, 5, 3)
+    r = local.local_problem(v, s, l, sg, fl, kap, f)
+    X = r["X"]
+    assert np.abs(r["c"] @ X).max() < 1e-15
+    Bfull = np.column_stack([r["R"], r["b"]])
+    # A X = B - c mu with mu = (1^T B)/|K|: the equations hold for all zero-mean w
+    mu = Bfull.sum(axis=0) / r["area"]
+    np.testing.assert_allclose(r["A"] @ X, Bfull - np.outer(r["c"], mu), atol=1e-13)
+
+
+@pytest.mark.parametrize("s,l", [(3, 0), (6, 1), (8, 3)])
+def test_m_symmetric_negative_definite(s, l):
+    rng = np.random.default_rng(40 + s)
+    v, s, l, sg, fl, kap, f = _rand_element(rng, s, l)
+    r = local.local_problem(v, s, l, sg, fl, kap, f)
+    M = r["M"]
+    assert np.abs(M - M.T).max() < 1e-13 * np.abs(M).max()
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).max() < 0
+
+
+def test_rank_one_augmented_matrix_gives_same_solution_for_any_gamma():
+    """The SPD system (A + gamma c c^T) X = B - c (1^T B)/|K| has the zero-mean
+    solution for every gamma > 0; it matches the bordered (KKT) solve."""
+    rng = np.random.default_rng(11)
+    v, s, l, sg, fl, kap, f = _rand_element(rng, 7, 2)
+    r = local.local_problem(v, s, l, sg, fl, kap, f)
+    A, c = r["A"], r["c"]
+    B = np.column_stack([r["R"], r["b"]])
+    Bt = B - np.outer(c, B.sum(axis=0)) / r["area"]
+    g0 = np.trace(A) / (A.shape[0] * (c @ c))
+    scale = np.abs(r["X"]).max()
+    for gamma in (g0, 100.0 * g0, 0.01 * g0):
+        L = np.linalg.cholesky(A + gamma * np.outer(c, c))
+        X = np.linalg.solve(L.T, np.linalg.solve(L, Bt))
+        assert np.abs(X - r["X"]).max() < 1e-12 * scale
+
+
+# ------------------------------------------------------------ skeleton level
+def _solve_global(N, s, l, kfun, ffun):
+    mesh = coarse_mesh(N)
+    E = mesh["elems"].shape[0]
+    b = configs.build_batch(mesh, np.arange(E), np.full(E, s), np.full(E, l), kfun, ffun)
+    res = local.solve_batch(b)
+    lam, u0, K, rhs = skeleton.reduce_and_solve(mesh, res, np.arange(E), l)
+    return mesh, b, res, lam, u0, K
+
+
+def test_skeleton_symmetric_and_constant_null_space():
+    mesh, b, res, lam, u0, K = _solve_global(2, 4, 1, _smooth_k, manufactured_source)
+    assert np.abs(K - K.T).max() < 1e-14 * np.abs(K).max()
+    nl = mesh["faces"].shape[0] * 2
+    z = np.zeros(K.shape[0])
+    z[nl:] = 1.0                                  # lambda = 0, u0 = 1
+    Kz = K @ z
+    for g in range(mesh["faces"].shape[0]):
+        for q in range(2):
+            row = Kz[g * 2 + q]
+            if mesh["face_boundary"][g] and q == 0:
+                assert row == pytest.approx(mesh["face_len"][g], rel=1e-13)
+            else:
+                assert abs(row) < 1e-14
+    assert np.abs(Kz[nl:]).max() < 1e-14
+
+
+@pytest.mark.parametrize("N,s", [(2, 2), (2, 3), (3, 4)])
+def test_l_equals_s_reduces_to_conforming_galerkin(N, s):
+    """With m = 1 and l = s the MHM solution equals textbook P1 Galerkin on the
+    composite fine mesh (homogeneous Dirichlet), node by node."""
+    mesh, b, res, lam, u0, K = _solve_global(N, s, s, _smooth_k, manufactured_source)
+    uh = skeleton.reconstruct(mesh, res, np.arange(b["n_elem"]), s, lam, u0)
+    nodes_l, tris_l, kap_l, f_l = [], [], [], []
+    for e in range(b["n_elem"]):
+        nodes, tris = local.submesh(b["vert"][e], s)
+        o0, o1 = b["tri_off"][e], b["tri_off"][e + 1]
+        nodes_l.append(nodes)
+        tris_l.append(tris)
+        kap_l.append(b["kappa"][o0:o1])
+        f_l.append(b["f"][o0:o1])
+    ref = galerkin_ref.fine_mesh_solve(nodes_l, tris_l, kap_l, f_l, N * s)
+    scale = max(abs(x) for x in ref.values())
+    for e in range(b["n_elem"]):
+        for p, val in zip(nodes_l[e], uh[e]):
+            k = (int(round(p[0] * N * s)), int(round(p[1] * N * s)))
+            assert abs(val - ref[k]) < 1e-11 * scale
+
+
+def test_manufactured_solution_converges_at_second_order():
+    errs = []
+    for N in (2, 4, 8):
+        mesh, b, res, lam, u0, K = _solve_global(N, 4, 1, _ones, manufactured_source)
+        uh = skeleton.reconstruct(mesh, res, np.arange(b["n_elem"]), 1, lam, u0)
+        errs.append(skeleton.l2_error(b, uh, manufactured_solution))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((rates > 1.8) & (rates < 2.3)), (errs, rates)
+
+
+def test_config_shapes():
+    b = configs.make("C1")
+    assert b["n_elem"] == 32 and set(b["s"]) == {4} and set(b["l"]) == {1}
+    assert b["tri_off"][-1] == 32 * 16
+    b2 = configs.make("C2", n_elem=8)
+    assert b2["kappa"].shape == (8 * 256,) and np.all(b2["kappa"] > 0)
