@@ -1,0 +1,173 @@
+/*
+ * mhm.h - C ABI of the MI355X (gfx950) engine for the local problems of the
+ * Multiscale Hybrid-Mixed (MHM) method.
+ *
+ * What the library computes, per coarse element K (the solveLocalProblem
+ * primitive of Algorithm 1, Section 3, for the Darcy subproblems of
+ * eqs. (8)-(9), Section 4.2), specialised to 2D, continuous P1 elements on a
+ * uniform refinement of the triangle K with s subdivisions per edge, and face
+ * multipliers of degree l on each of the three faces (m = 1, Section 2):
+ *
+ *   n   = (s+1)(s+2)/2 sub-mesh nodes,   T = s*s sub-triangles,
+ *   N_I = 3(l+1) face DoFs,              r = N_I + 1 right-hand sides.
+ *
+ *   A      n x n P1 stiffness of (kappa grad u, grad w)_K, kappa constant on
+ *          each sub-triangle.
+ *   c      c_j = integral of phi_j over K.
+ *   Ahat   = A + gamma c c^T with gamma = trace(A) / (n c^T c); symmetric
+ *          positive definite, it imposes the zero mean of V_0^perp(K).
+ *   B      n x r: columns a = e(l+1)+q hold -sigma_e (P_q, phi_j)_{F_e}
+ *          (eq. (9); P_q the Legendre polynomial on the globally oriented
+ *          face), the last column holds (f, phi_j)_K (eq. (8)).
+ *   Btilde = B - c (1^T B) / |K|   (compatible right-hand sides).
+ *   X      n x r: Ahat X = Btilde, then X -= 1 (c^T X)/|K|; the coefficient
+ *          vectors d_i and c of eq. (5), face DoFs first, source last.
+ *   M, E, B, F: the element's blocks of the skeleton system eq. (6):
+ *          M[a][b] = (sigma psi_a, eta^b)_{dK} (N_I x N_I, symmetric,
+ *          negative definite), E[a] = -(sigma psi_a, eta^f)_{dK},
+ *          B[a] = (sigma psi_a, 1)_{dK}, F = (f, 1)_K.
+ *
+ * Sub-mesh numbering: node (i,j), i,j >= 0, i+j <= s, lies at
+ * v0 + (i/s)(v1-v0) + (j/s)(v2-v0) with index j(s+1) - j(j-1)/2 + i.
+ * Sub-triangles are in row strips j = 0..s-1: up triangle (i,j) (nodes
+ * (i,j),(i+1,j),(i,j+1)) at j(2s-j)+2i, down triangle (i,j) (nodes
+ * (i+1,j+1),(i,j+1),(i+1,j)) at j(2s-j)+2i+1.  Face e is opposite vertex e
+ * and runs v[e+1] -> v[e+2]; flip[e] = 1 when that direction goes from the
+ * higher to the lower global vertex id (face polynomials use t = -1 at the
+ * lower id).  sigma[e] = +1 or -1 is the sign n . n^K_F.
+ *
+ * Memory: every array pointer in mhm_batch and in the calls below is a
+ * DEVICE pointer owned by the caller (the library never frees it).  Matrices
+ * are column-major per element at the element's prefix offset.  Calls are
+ * asynchronous on the context's HIP stream; outputs are valid once the
+ * stream (or mhm_sync) has completed.
+ *
+ * Errors, two levels:
+ *  - call level: the returned mhm_status (argument checks on the host, HIP
+ *    launch or allocation failures); mhm_last_error() gives the text.
+ *  - element level: info[e] (device int32, written asynchronously):
+ *      0   success
+ *      k>0 non-positive pivot at column k (1-based) of Ahat: the element's
+ *          outputs are filled with NaN (LAPACK potrf convention)
+ *     -1   the FP32 factorisation or its FP64 refinement did not reach the
+ *          tolerance in max_iters steps; the element was recomputed with the
+ *          FP64 path and its outputs are valid
+ *     -2   the element's descriptor is inconsistent (s or l out of range,
+ *          offsets that disagree with s and l or exceed the *_total sizes,
+ *          sign/flip flags out of range, a non-positive area); nothing of
+ *          the element is written
+ *     -3   the element is larger than the launched kernel supports
+ */
+#ifndef MHM_H
+#define MHM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MHM_S_LIMIT 64   /* largest s per element          */
+#define MHM_L_LIMIT 4    /* largest l per element (r <= 16) */
+
+typedef struct mhm_ctx_s* mhm_ctx;
+
+typedef enum {
+  MHM_OK = 0,
+  MHM_E_ARG = 1,
+  MHM_E_NOMEM = 2,
+  MHM_E_DEVICE = 3,
+  MHM_E_UNSUPPORTED = 4
+} mhm_status;
+
+typedef enum {
+  MHM_FP64 = 0,     /* FP64 Cholesky and triangular solves (MFMA f64)          */
+  MHM_FP32_IR = 1   /* FP32 Cholesky and solves (MFMA f32) + FP64 refinement    */
+} mhm_prec;
+
+/* A ragged batch of local problems p_t = (K_t, {F_t}) (Algorithm 1). */
+typedef struct {
+  int32_t n_elem;          /* host: number of elements (0 is allowed)          */
+  int32_t s_max;           /* host: bound on s over the batch (launch choice)  */
+  int32_t l_max;           /* host: bound on l; contribution blocks are padded
+                              to NImax = 3(l_max+1)                             */
+  int32_t reserved;
+  const int32_t* s;        /* [n_elem] subdivisions, 1..MHM_S_LIMIT            */
+  const int32_t* l;        /* [n_elem] face degree, 0..MHM_L_LIMIT             */
+  const double* vert;      /* [n_elem*6] x0 y0 x1 y1 x2 y2, counter-clockwise  */
+  const int8_t* sigma;     /* [n_elem*3] +1 / -1                               */
+  const int8_t* flip;      /* [n_elem*3] 0 / 1                                 */
+  const double* kappa;     /* [tri_total] per sub-triangle, at tri_off[e]      */
+  const double* f;         /* [tri_total] per sub-triangle, at tri_off[e]      */
+  const int64_t* tri_off;  /* [n_elem+1] prefix sums of s^2                    */
+  const int64_t* mat_off;  /* [n_elem+1] prefix sums of n^2   (Ahat, factor)   */
+  const int64_t* rhs_off;  /* [n_elem+1] prefix sums of n*r   (Btilde, X)      */
+  const int64_t* node_off; /* [n_elem+1] prefix sums of n     (c)              */
+  int64_t tri_total;       /* host: element count of kappa and f               */
+  int64_t mat_total;       /* host: doubles in the Ahat buffer                 */
+  int64_t rhs_total;       /* host: doubles in the Btilde and X buffers        */
+  int64_t node_total;      /* host: doubles in the c buffer                    */
+} mhm_batch;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL means the default stream).  The context owns its
+ * workspace and frees it in mhm_destroy. */
+mhm_status mhm_create(mhm_ctx* ctx, int device, void* hip_stream);
+mhm_status mhm_destroy(mhm_ctx ctx);
+/* Change the stream subsequent calls enqueue on. */
+mhm_status mhm_set_stream(mhm_ctx ctx, void* hip_stream);
+/* Text of the last call-level error on this context ("" if none); with a
+ * NULL context, the last error of a context-less call (mhm_create) on the
+ * calling thread. */
+const char* mhm_last_error(mhm_ctx ctx);
+/* Block until all work enqueued by this context has finished. */
+mhm_status mhm_sync(mhm_ctx ctx);
+/* Device workspace (bytes) the context allocates for a batch and precision
+ * (elements too large for on-chip storage use a per-workgroup slot). */
+size_t mhm_workspace_bytes(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec);
+
+/* Steps a2-a3: assemble Ahat (n x n, column-major, both triangles),
+ * Btilde (n x r, column-major), c (n) and |K| per element.  info as above
+ * (only 0 or -2 here).  Defined by eqs. (2)-(3), (8)-(9) and Section 3's
+ * shared matrix A with N_I + 1 load vectors. */
+mhm_status mhm_local_assemble(mhm_ctx ctx, const mhm_batch* batch,
+                              double* Ahat, double* Btilde, double* c,
+                              double* area, int32_t* info);
+
+/* Steps a4-a5 (and a5' for MHM_FP32_IR): factor Ahat = L L^T once and solve
+ * the r right-hand sides (Section 3: one matrix, factored once, many load
+ * vectors), then project X to zero mean.
+ *   Ahat_io  in: Ahat from mhm_local_assemble.  out: the lower triangle of
+ *            L (MHM_FP64), or the FP32 L, column-major, in the first n*n
+ *            floats of the element's slot (MHM_FP32_IR; FP64 L for elements
+ *            that report info == -1).  The strict upper part is unspecified.
+ *   Btilde   in: compatible right-hand sides.
+ *   X        out: n x r solutions (FP64).
+ *   ir_iters out (may be NULL): refinement steps taken per element.
+ *   max_iters: refinement step limit (MHM_FP32_IR; ignored for MHM_FP64). */
+mhm_status mhm_local_factor_solve(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec,
+                                  double* Ahat_io, const double* Btilde, double* X,
+                                  int32_t* info, int32_t* ir_iters, int max_iters);
+
+/* Step a6: the element's contribution to eq. (6) from its solutions X.
+ * M [n_elem][NImax*NImax] (column-major NImax x NImax, zero padded),
+ * E [n_elem][NImax], B [n_elem][NImax], F [n_elem]; NImax = 3(l_max+1).
+ * Elements whose info[e] != 0 on entry are skipped (info may be NULL). */
+mhm_status mhm_skeleton_contrib(mhm_ctx ctx, const mhm_batch* batch, const double* X,
+                                double* M, double* E, double* B, double* F,
+                                const int32_t* info);
+
+/* Steps a2-a6 fused per element: assemble, factor, solve (and refine),
+ * contribute, without writing Ahat or Btilde to memory.  Same contract and
+ * layouts as the three calls above.  Under MHM_FP32_IR, elements whose
+ * refinement does not converge are recomputed in FP64 (info = -1). */
+mhm_status mhm_local_batch_run(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec,
+                               double* X, double* M, double* E, double* B, double* F,
+                               int32_t* info, int32_t* ir_iters, int max_iters);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MHM_H */

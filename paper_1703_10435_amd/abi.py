@@ -1,0 +1,141 @@
+"""ctypes binding of ``libmhm.so`` (declared in ``include/mhm.h``).
+
+Argument marshalling only: every step of the local-problem path runs in the
+library's HIP kernels.  Importing this module does not touch the GPU; the
+first call that needs the library loads it and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmhm.so")
+
+MHM_OK, MHM_E_ARG, MHM_E_NOMEM, MHM_E_DEVICE, MHM_E_UNSUPPORTED = 0, 1, 2, 3, 4
+MHM_FP64, MHM_FP32_IR = 0, 1
+MHM_S_LIMIT, MHM_L_LIMIT = 64, 4
+
+INFO_OK, INFO_IR_FALLBACK, INFO_BAD_DESC, INFO_TOO_LARGE = 0, -1, -2, -3
+
+EXPORTS = (
+    "mhm_create", "mhm_destroy", "mhm_set_stream", "mhm_last_error", "mhm_sync", "mhm_workspace_bytes",
+    "mhm_local_assemble", "mhm_local_factor_solve", "mhm_skeleton_contrib", "mhm_local_batch_run",
+)
+
+
+class mhm_batch(ctypes.Structure):
+    _fields_ = [
+        ("n_elem", ctypes.c_int32), ("s_max", ctypes.c_int32), ("l_max", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("s", ctypes.c_void_p), ("l", ctypes.c_void_p), ("vert", ctypes.c_void_p),
+        ("sigma", ctypes.c_void_p), ("flip", ctypes.c_void_p), ("kappa", ctypes.c_void_p),
+        ("f", ctypes.c_void_p), ("tri_off", ctypes.c_void_p), ("mat_off", ctypes.c_void_p),
+        ("rhs_off", ctypes.c_void_p), ("node_off", ctypes.c_void_p),
+        ("tri_total", ctypes.c_int64), ("mat_total", ctypes.c_int64), ("rhs_total", ctypes.c_int64),
+        ("node_total", ctypes.c_int64),
+    ]
+
+
+class MhmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mhm status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once).  Raises FileNotFoundError when it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is not built; run `python -m paper_1703_10435_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p
+    bp = ctypes.POINTER(mhm_batch)
+    sig = {
+        "mhm_create": (i32, [ctypes.POINTER(vp), i32, vp]),
+        "mhm_destroy": (i32, [vp]),
+        "mhm_set_stream": (i32, [vp, vp]),
+        "mhm_last_error": (ctypes.c_char_p, [vp]),
+        "mhm_sync": (i32, [vp]),
+        "mhm_workspace_bytes": (ctypes.c_size_t, [vp, bp, i32]),
+        "mhm_local_assemble": (i32, [vp, bp, vp, vp, vp, vp, i64p]),
+        "mhm_local_factor_solve": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, i32]),
+        "mhm_skeleton_contrib": (i32, [vp, bp, vp, vp, vp, vp, vp, vp]),
+        "mhm_local_batch_run": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """An ``mhm_ctx`` bound to a device and a torch HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        lib = load()
+        self.lib = lib
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = lib.mhm_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != MHM_OK:
+            raise MhmError(st, "mhm_create: " + lib.mhm_last_error(None).decode())
+        self.h = h
+
+    def set_stream(self, stream):
+        self.stream = stream
+        self._check(self.lib.mhm_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def _check(self, st):
+        if st != MHM_OK:
+            raise MhmError(st, self.lib.mhm_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mhm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------- the C ABI calls
+    def sync(self):
+        self._check(self.lib.mhm_sync(self.h))
+
+    def workspace_bytes(self, batch, prec: int) -> int:
+        return int(self.lib.mhm_workspace_bytes(self.h, ctypes.byref(batch.desc), prec))
+
+    def local_assemble(self, batch, Ahat, Btil, c, area, info):
+        self._check(self.lib.mhm_local_assemble(self.h, ctypes.byref(batch.desc), _ptr(Ahat), _ptr(Btil),
+                                                _ptr(c), _ptr(area), _ptr(info)))
+
+    def local_factor_solve(self, batch, prec, Ahat_io, Btil, X, info, ir_iters=None, max_iters: int = 10):
+        self._check(self.lib.mhm_local_factor_solve(self.h, ctypes.byref(batch.desc), prec, _ptr(Ahat_io),
+                                                    _ptr(Btil), _ptr(X), _ptr(info), _ptr(ir_iters), max_iters))
+
+    def skeleton_contrib(self, batch, X, M, E, B, F, info=None):
+        self._check(self.lib.mhm_skeleton_contrib(self.h, ctypes.byref(batch.desc), _ptr(X), _ptr(M), _ptr(E),
+                                                  _ptr(B), _ptr(F), _ptr(info)))
+
+    def local_batch_run(self, batch, prec, X, M, E, B, F, info, ir_iters=None, max_iters: int = 10):
+        self._check(self.lib.mhm_local_batch_run(self.h, ctypes.byref(batch.desc), prec, _ptr(X), _ptr(M),
+                                                 _ptr(E), _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters),
+                                                 max_iters))

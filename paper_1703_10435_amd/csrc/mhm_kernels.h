@@ -1,0 +1,42 @@
+// Internal interface between the C ABI (mhm_api.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mhm.h"
+
+namespace mhm {
+
+struct LocalArgs {
+  const double* Ahat;   // load mode: assembled Ahat (column-major per element)
+  const double* Btil;   // load mode: compatible right-hand sides
+  double* Lout;         // factor output (may be null)
+  double* X;            // solutions, n x r per element at rhs_off
+  double* M;            // fused mode: contribution blocks (may be null)
+  double* E;
+  double* B;
+  double* F;
+  int32_t* info;
+  int32_t* ir_iters;    // may be null
+  int max_iters;
+  int only_fallback;    // process only elements whose info is -1
+  double ir_tol;        // normwise backward-error target of the refinement
+  void* ws;             // workspace mode: per-workgroup tile slots
+  int64_t ws_slot;      // elements (of the tile type) per slot
+  int tile_cap;         // tiles that fit in LDS or in one slot
+  int n_cap;            // largest n (length of the LDS c array)
+  int k_cap;            // LDS doubles reserved for kappa (fused, LDS mode)
+};
+
+constexpr int TILE_WORDS = 16 * 17;   // stored tile: 16 rows, padded stride 17
+
+hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, double* c, double* area,
+                           int32_t* info, int grid, hipStream_t st);
+hipError_t launch_contrib(const mhm_batch* bt, const double* X, double* M, double* E, double* B, double* F,
+                          const int32_t* info, int grid, hipStream_t st);
+size_t local_lds_bytes(bool fp32, bool in_lds, bool fused, int n_cap, int k_cap, int tile_cap);
+hipError_t launch_local(bool fp32, bool in_lds, bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
+                        hipStream_t st);
+
+}  // namespace mhm

@@ -1,0 +1,43 @@
+"""Convenience drivers over the C ABI: run a batch through the three-call path
+(assemble -> factor/solve -> contribution) or the fused call, on one stream.
+
+Only marshalling and buffer management here; all arithmetic is in libmhm.so.
+"""
+from __future__ import annotations
+
+from . import abi
+from .batch import DeviceBatch
+
+
+def run_three_call(ctx: abi.Context, db: DeviceBatch, prec: int = abi.MHM_FP64, out: dict | None = None,
+                   max_iters: int = 10) -> dict:
+    """solveLocalProblem + the element share of reduceLocalProblems as three
+    library calls: mhm_local_assemble, mhm_local_factor_solve,
+    mhm_skeleton_contrib."""
+    if out is None:
+        out = db.alloc_outputs(three_call=True)
+    ctx.local_assemble(db, out["Ahat"], out["Btil"], out["c"], out["area"], out["info"])
+    ctx.local_factor_solve(db, prec, out["Ahat"], out["Btil"], out["X"], out["info"], out["ir_iters"], max_iters)
+    ctx.skeleton_contrib(db, out["X"], out["M"], out["E"], out["B"], out["F"], out["info"])
+    return out
+
+
+def run_fused(ctx: abi.Context, db: DeviceBatch, prec: int = abi.MHM_FP64, out: dict | None = None,
+              max_iters: int = 10) -> dict:
+    """The same work as one mhm_local_batch_run call."""
+    if out is None:
+        out = db.alloc_outputs(three_call=False)
+    ctx.local_batch_run(db, prec, out["X"], out["M"], out["E"], out["B"], out["F"], out["info"],
+                        out["ir_iters"], max_iters)
+    return out
+
+
+def solve_batch(batch: dict, prec: int = abi.MHM_FP64, mode: str = "fused", ctx: abi.Context | None = None,
+                max_iters: int = 10):
+    """Upload a host batch, run it, return per-element results (numpy)."""
+    ctx = ctx or abi.Context()
+    db = DeviceBatch(batch)
+    run = run_fused if mode == "fused" else run_three_call
+    out = run(ctx, db, prec, max_iters=max_iters)
+    ctx.sync()
+    return db.unpack(out), out, db
