@@ -61,7 +61,7 @@ int grid_for(const mhm_batch* b) { return std::min(b->n_elem, kGridCap); }
 // Launch plan of k_local for a batch.
 struct Plan {
   bool fp32, in_lds;
-  int nt, tile_cap, n_cap, k_cap, grid;
+  int nt, tile_cap, n_cap, f_cap, k_cap, grid;
   size_t lds, ws_need;
   int64_t ws_slot;
 };
@@ -70,21 +70,22 @@ Plan plan_local(mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, bool force
   Plan p;
   p.fp32 = fp32;
   p.n_cap = n_of(b->s_max);
+  p.f_cap = mhm::local_face_cap(b);
   p.nt = (p.n_cap + 15) / 16;
   p.tile_cap = p.nt * (p.nt + 1) / 2 + p.nt;
   const size_t tsz = fp32 ? sizeof(float) : sizeof(double);
-  const int k_lds = b->s_max * b->s_max;
-  const size_t lds_in = mhm::local_lds_bytes(fp32, true, fused, p.n_cap, fused ? k_lds : 0, p.tile_cap);
+  const int k_lds = fused ? b->s_max * b->s_max : 0;
+  const size_t lds_in = mhm::local_lds_bytes(fp32, true, p.n_cap, p.f_cap, k_lds, p.tile_cap);
   p.in_lds = !force_ws && lds_in + kStaticLds <= c->lds_limit;
   if (p.in_lds) {
-    p.k_cap = fused ? k_lds : 0;
+    p.k_cap = k_lds;
     p.lds = lds_in;
     p.grid = grid_for(b);
     p.ws_slot = 0;
     p.ws_need = 0;
   } else {
     p.k_cap = 0;
-    p.lds = mhm::local_lds_bytes(fp32, false, fused, p.n_cap, 0, p.tile_cap);
+    p.lds = mhm::local_lds_bytes(fp32, false, p.n_cap, p.f_cap, 0, p.tile_cap);
     p.grid = std::min(b->n_elem, 2 * c->n_cu);
     p.ws_slot = (int64_t)p.tile_cap * mhm::TILE_WORDS;
     p.ws_need = (size_t)p.grid * (size_t)p.ws_slot * tsz;
@@ -141,6 +142,7 @@ mhm_status run_local(mhm_ctx c, const mhm_batch* b, mhm_prec prec, bool fused, c
   a.ws_slot = p.ws_slot;
   a.tile_cap = p.tile_cap;
   a.n_cap = p.n_cap;
+  a.f_cap = p.f_cap;
   a.k_cap = p.k_cap;
   hipError_t e = mhm::launch_local(fp32, p.in_lds, fused, b, a, p.lds, p.grid, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "k_local launch");
@@ -153,6 +155,7 @@ mhm_status run_local(mhm_ctx c, const mhm_batch* b, mhm_prec prec, bool fused, c
     f.ws_slot = fb.ws_slot;
     f.tile_cap = fb.tile_cap;
     f.n_cap = fb.n_cap;
+    f.f_cap = fb.f_cap;
     f.k_cap = 0;
     if (!fused) {
       f.M = f.E = f.B = f.F = nullptr;

@@ -42,6 +42,7 @@ struct Elem {
   double G[3][3];           // D_a . D_b / (4 |K|): P1 stiffness of any sub-triangle / kappa
   double flen[3];           // |F_e|
   double cunit;             // |K| / (3 s^2): mass of one sub-triangle corner
+  double inv_area, inv_s;
   int sigma[3], flip[3];
   int64_t tri0, mat0, rhs0, node0;
 };
@@ -64,7 +65,7 @@ __device__ __forceinline__ void node_ij(int p, int s, int& i, int& j) {
 }
 
 // Decode and validate element e.  Returns false for an inconsistent descriptor.
-__device__ inline bool load_elem(const BatchDev& b, int e, Elem& E) {
+__device__ __forceinline__ bool load_elem(const BatchDev& b, int e, Elem& E) {
   const int s = b.s[e];
   const int l = b.l[e];
   if (s < 1 || s > MHM_S_LIMIT || s > b.s_max || l < 0 || l > MHM_L_LIMIT || l > b.l_max) return false;
@@ -119,6 +120,8 @@ __device__ inline bool load_elem(const BatchDev& b, int e, Elem& E) {
   // face e is the edge opposite vertex e, i.e. D_e
   for (int k = 0; k < 3; ++k) E.flen[k] = sqrt(D[k][0] * D[k][0] + D[k][1] * D[k][1]);
   E.cunit = E.area / (3.0 * s * s);
+  E.inv_area = 1.0 / E.area;
+  E.inv_s = 1.0 / s;
   return true;
 }
 
@@ -189,7 +192,7 @@ __device__ __forceinline__ double legendre(int q, double t) {
 
 // R[node at position k of face e][column e(l+1)+q] = -sigma_e (P_q, phi)_{F_e}:
 // exact for q <= 4 with the 3-point Gauss rule on each of the s face segments.
-__device__ inline double face_load(const Elem& E, int e, int q, int k) {
+__device__ __forceinline__ double face_load(const Elem& E, int e, int q, int k) {
   const double r15 = 0.38729833462074168852;  // sqrt(15)/10
   const double xg[3] = {0.5 - r15, 0.5, 0.5 + r15};
   const double wg[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
@@ -199,13 +202,13 @@ __device__ inline double face_load(const Elem& E, int e, int q, int k) {
     const int seg = side == 0 ? k - 1 : k;   // node k is the right end of seg k-1, left end of seg k
     if (seg < 0 || seg >= s) continue;
     for (int g = 0; g < 3; ++g) {
-      const double tau = (seg + xg[g]) / s;
+      const double tau = (seg + xg[g]) * E.inv_s;
       const double t = E.flip[e] ? 1.0 - 2.0 * tau : 2.0 * tau - 1.0;
       const double hat = side == 0 ? xg[g] : 1.0 - xg[g];
       acc += wg[g] * legendre(q, t) * hat;
     }
   }
-  return -(double)E.sigma[e] * E.flen[e] / s * acc;
+  return -(double)E.sigma[e] * E.flen[e] * E.inv_s * acc;
 }
 
 // Lattice node at position k (0..s) along face e, from v[e+1] to v[e+2].

@@ -25,7 +25,8 @@ struct LocalArgs {
   void* ws;             // workspace mode: per-workgroup tile slots
   int64_t ws_slot;      // elements (of the tile type) per slot
   int tile_cap;         // tiles that fit in LDS or in one slot
-  int n_cap;            // largest n (length of the LDS c array)
+  int n_cap;            // largest n (length of the LDS c and source-load arrays)
+  int f_cap;            // LDS doubles of the face-load table, 3 (l_max+1)(s_max+1)
   int k_cap;            // LDS doubles reserved for kappa (fused, LDS mode)
 };
 
@@ -35,7 +36,8 @@ hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, doub
                            int32_t* info, int grid, hipStream_t st);
 hipError_t launch_contrib(const mhm_batch* bt, const double* X, double* M, double* E, double* B, double* F,
                           const int32_t* info, int grid, hipStream_t st);
-size_t local_lds_bytes(bool fp32, bool in_lds, bool fused, int n_cap, int k_cap, int tile_cap);
+size_t local_lds_bytes(bool fp32, bool in_lds, int n_cap, int f_cap, int k_cap, int tile_cap);
+int local_face_cap(const mhm_batch* bt);
 hipError_t launch_local(bool fp32, bool in_lds, bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
                         hipStream_t st);
 

@@ -3,11 +3,11 @@
 // k_assemble   steps a2-a3: Ahat = A + gamma c c^T (dense, column-major),
 //              Btilde = B - c (1^T B)/|K|, c, |K|               (HBM-write bound)
 // k_local      steps a2-a6 on 16x16 tiles: (assemble or load) -> Cholesky
-//              (MFMA f64 or f32) -> forward/backward solves of the r
-//              right-hand sides (MFMA) -> FP64 matrix-free refinement (FP32
-//              path) -> zero-mean projection -> optional contribution.
-//              Tiles live in LDS when the element fits, else in a
-//              per-workgroup slot of a device workspace.
+//              (MFMA f64 or f32) with the forward solve of the r right-hand
+//              sides carried along as an extra tile row -> backward solve
+//              (MFMA) -> FP64 matrix-free refinement (FP32 path) -> zero-mean
+//              projection -> optional contribution.  Tiles live in LDS when
+//              the element fits, else in a per-workgroup workspace slot.
 // k_contrib    step a6: the element's blocks of the skeleton system.
 //
 // One workgroup of 256 threads (4 waves of 64) handles one element at a time.
@@ -30,17 +30,33 @@ __device__ __forceinline__ double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
-// Block-wide sum; every thread gets the result.  `red` holds NWAVES doubles.
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
+// sum over the 16 lanes of a lane group (lanes 16g .. 16g+15)
+__device__ __forceinline__ double group16_sum(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// Block-wide sums of three values; every thread gets the results.
+// `red` holds 3*NWAVES doubles.
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
   const int w = threadIdx.x >> 6;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = a;
+    red[NWAVES + w] = b;
+    red[2 * NWAVES + w] = c;
+  }
   __syncthreads();
-  double t = 0.0;
+  a = b = c = 0.0;
 #pragma unroll
-  for (int k = 0; k < NWAVES; ++k) t += red[k];
-  return t;
+  for (int k = 0; k < NWAVES; ++k) {
+    a += red[k];
+    b += red[NWAVES + k];
+    c += red[2 * NWAVES + k];
+  }
 }
 __device__ __forceinline__ double block_max(double v, double* red) {
   v = wave_max(v);
@@ -63,8 +79,18 @@ __device__ __forceinline__ double readlane(double x, int lane) {
 __device__ __forceinline__ float readlane(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
-__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
-__device__ __forceinline__ float rsqrt_t(float x) { return 1.0f / sqrtf(x); }
+// 1/sqrt(x): hardware estimate refined by Newton steps y <- y (3 - x y^2) / 2
+__device__ __forceinline__ double rsqrt_t(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+__device__ __forceinline__ float rsqrt_t(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  y = y * (1.5f - 0.5f * x * y * y);
+  return y;
+}
 
 // Sum of fn(t) over the sub-triangles t around node (i,j).
 template <class FN>
@@ -80,46 +106,38 @@ __device__ __forceinline__ double node_tri_sum(int i, int j, int s, FN fn) {
   return a;
 }
 
-// R[p][a] for node (i,j) and face column a (0 if the node is not on that face).
-__device__ __forceinline__ double face_load_node(const Elem& E, int a, int i, int j) {
-  const int e = a / (E.l + 1), q = a - e * (E.l + 1);
-  const int k = face_pos(e, i, j, E.s);
-  return k < 0 ? 0.0 : face_load(E, e, q, k);
-}
-
-// Column sums 1^T B: face columns from the face nodes, the source column from
-// the sub-triangles (1^T b_f = integral of f).  Result in colsum[0..r-1].
-__device__ void rhs_column_sums(const Elem& E, const BatchDev& b, double* colsum, double* red) {
-  const int tid = threadIdx.x;
-  const int lp1 = E.l + 1;
-  // face columns: one wave per column, lanes over the s+1 face nodes
-  const int w = tid >> 6, lane = tid & 63;
-  for (int a = w; a < E.NI; a += NWAVES) {
+// -------------------------------------------------------- per-element tables
+// ft[a*(s+1) + k] = R[face node k of face e(a)][a]   (face load table)
+// colsum[a] = 1^T B[:, a]  (face columns from ft, source column from bf)
+__device__ __forceinline__ void face_table(const Elem& E, double* ft) {
+  const int sp1 = E.s + 1, lp1 = E.l + 1;
+  for (int idx = threadIdx.x; idx < E.NI * sp1; idx += NTHREADS) {
+    const int a = idx / sp1, k = idx - a * sp1;
     const int e = a / lp1, q = a - e * lp1;
-    double v = 0.0;
-    for (int k = lane; k <= E.s; k += 64) v += face_load(E, e, q, k);
-    v = wave_sum(v);
-    if (lane == 0) colsum[a] = v;
+    ft[idx] = face_load(E, e, q, k);
   }
-  double fs = 0.0;
-  const int T = E.s * E.s;
-  for (int t = tid; t < T; t += NTHREADS) fs += b.f[E.tri0 + t];
-  fs = block_sum(fs, red);   // contains barriers
-  if (tid == 0) colsum[E.NI] = fs * (E.area / ((double)E.s * E.s));
-  __syncthreads();
+}
+__device__ __forceinline__ void face_colsums(const Elem& E, const double* ft, double* colsum) {
+  const int sp1 = E.s + 1;
+  if ((int)threadIdx.x < E.NI) {
+    double v = 0.0;
+    for (int k = 0; k < sp1; ++k) v += ft[threadIdx.x * sp1 + k];
+    colsum[threadIdx.x] = v;
+  }
 }
 
-// Btilde[p][a] for node p = (i,j).
-__device__ __forceinline__ double btilde_entry(const Elem& E, const BatchDev& b, const double* colsum,
-                                               int a, int i, int j, double cp) {
-  double v;
+// Btilde[p][a] from the tables.
+__device__ __forceinline__ double btilde_tab(const Elem& E, const double* ft, const double* bf, const double* c,
+                                             const double* colsum, int a, int p, int i, int j) {
+  double v = 0.0;
   if (a < E.NI) {
-    v = face_load_node(E, a, i, j);
+    const int e = a / (E.l + 1);
+    const int k = face_pos(e, i, j, E.s);
+    if (k >= 0) v = ft[a * (E.s + 1) + k];
   } else {
-    const double* fp = b.f + E.tri0;
-    v = E.cunit * node_tri_sum(i, j, E.s, [&](int t) { return fp[t]; });
+    v = bf[p];
   }
-  return v - cp * colsum[a] / E.area;
+  return v - c[p] * colsum[a] * E.inv_area;
 }
 
 // =============================================================== k_assemble
@@ -127,11 +145,12 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
                                                         double* area, int32_t* info) {
   __shared__ Elem E;
   __shared__ int ok;
-  __shared__ double red[NWAVES];
+  __shared__ double red[3 * NWAVES];
   __shared__ double colsum[16];
   __shared__ double gam;
-  extern __shared__ double dyn[];   // kappa[s*s], c[n]
+  extern __shared__ double dyn[];   // kappa[s^2] | c[n] | bf[n] | ft[NI(s+1)]
   const int tid = threadIdx.x;
+  const int smax = b.s_max, nmax = (smax + 1) * (smax + 2) / 2;
   for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
     __syncthreads();
     if (tid == 0) {
@@ -139,26 +158,36 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
       if (info) info[e] = ok ? INFO_OK : INFO_BAD_DESC;
     }
     __syncthreads();
-    if (!ok) { __syncthreads(); continue; }
+    if (!ok) continue;
     const int s = E.s, n = E.n, r = E.r, T = s * s;
     double* kap = dyn;
-    double* c = dyn + T;
+    double* c = kap + smax * smax;
+    double* bf = c + nmax;
+    double* ft = bf + nmax;
     for (int t = tid; t < T; t += NTHREADS) kap[t] = b.kappa[E.tri0 + t];
+    face_table(E, ft);
     __syncthreads();
-    double tr = 0.0, cc2 = 0.0;
+    double tr = 0.0, cc2 = 0.0, fs = 0.0;
+    const double* fp = b.f + E.tri0;
     for (int p = tid; p < n; p += NTHREADS) {
       int i, j;
       node_ij(p, s, i, j);
       const Stencil st = stencil(i, j, s, E.G, [&](int t) { return kap[t]; });
       const double cp = st.cnt * E.cunit;
+      const double bp = E.cunit * node_tri_sum(i, j, s, [&](int t) { return fp[t]; });
       c[p] = cp;
+      bf[p] = bp;
       tr += st.d;
       cc2 += cp * cp;
+      fs += bp;
     }
-    tr = block_sum(tr, red);
-    cc2 = block_sum(cc2, red);
-    if (tid == 0) gam = tr / (n * cc2);
-    rhs_column_sums(E, b, colsum, red);   // ends with a barrier; c[] visible
+    block_sum3(tr, cc2, fs, red);
+    if (tid == 0) {
+      gam = tr / (n * cc2);
+      colsum[E.NI] = fs;
+    }
+    face_colsums(E, ft, colsum);
+    __syncthreads();
     const double g = gam;
     // Ahat: wave w writes columns q = w, w+4, ...; lanes sweep rows.
     const int w = tid >> 6, lane = tid & 63;
@@ -182,27 +211,26 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
         A[(int64_t)q * n + p] = v;
       }
     }
-    // Btilde, column-major n x r
     double* Bt = Btil + E.rhs0;
     for (int idx = tid; idx < n * r; idx += NTHREADS) {
       const int a = idx / n, p = idx - a * n;
       int i, j;
       node_ij(p, s, i, j);
-      Bt[idx] = btilde_entry(E, b, colsum, a, i, j, c[p]);
+      Bt[idx] = btilde_tab(E, ft, bf, c, colsum, a, p, i, j);
     }
     for (int p = tid; p < n; p += NTHREADS) cout[E.node0 + p] = c[p];
     if (tid == 0 && area) area[e] = E.area;
-    __syncthreads();
   }
 }
 
 // ============================================================ contribution
 // M[a][b] = -sum_k R(a,k) X[node(a,k)][b], E[a] = sum_k R(a,k) X[node(a,k)][NI],
-// B[a] = -sum_k R(a,k), F = integral of f.  X column-major n x r.
-__device__ void contrib_element(const Elem& E, const BatchDev& b, const double* X, int NImax, double* M,
-                                double* Ev, double* Bv, double* F, int e, double* red) {
+// B[a] = -sum_k R(a,k), F = integral of f (= colsum of the source column).
+// X column-major n x r (already projected); ft the face table.
+__device__ __forceinline__ void contrib_element(const Elem& E, const double* X, const double* ft, double Fval, int NImax,
+                                double* M, double* Ev, double* Bv, double* F, int e) {
   const int tid = threadIdx.x;
-  const int NI = E.NI, n = E.n, lp1 = E.l + 1, s = E.s;
+  const int NI = E.NI, n = E.n, lp1 = E.l + 1, s = E.s, sp1 = s + 1;
   double* Me = M + (int64_t)e * NImax * NImax;
   for (int idx = tid; idx < NImax * NImax; idx += NTHREADS) {
     const int a = idx % NImax, bb = idx / NImax;
@@ -210,94 +238,109 @@ __device__ void contrib_element(const Elem& E, const BatchDev& b, const double* 
   }
   if (tid < NI * E.r) {
     const int a = tid % NI, bb = tid / NI;
-    const int ef = a / lp1, q = a - ef * lp1;
+    const int ef = a / lp1;
+    const double* fa = ft + a * sp1;
+    const double* xb = X + (int64_t)bb * n;
     double v = 0.0;
-    for (int k = 0; k <= s; ++k) v += face_load(E, ef, q, k) * X[(int64_t)bb * n + face_node(ef, k, s)];
+    for (int k = 0; k < sp1; ++k) v += fa[k] * xb[face_node(ef, k, s)];
     if (bb < NI) Me[(int64_t)bb * NImax + a] = -v;
     else Ev[(int64_t)e * NImax + a] = v;
   } else if (tid >= 240 && tid < 240 + NImax) {
     const int a = tid - 240;
     double v = 0.0;
     if (a < NI) {
-      const int ef = a / lp1, q = a - ef * lp1;
-      for (int k = 0; k <= s; ++k) v -= face_load(E, ef, q, k);
+      for (int k = 0; k < sp1; ++k) v -= ft[a * sp1 + k];
     } else {
       Ev[(int64_t)e * NImax + a] = 0.0;
     }
     Bv[(int64_t)e * NImax + a] = v;
   }
-  double fs = 0.0;
-  for (int t = tid; t < s * s; t += NTHREADS) fs += b.f[E.tri0 + t];
-  fs = block_sum(fs, red);
-  if (tid == 0) F[e] = fs * (E.area / ((double)s * s));
+  if (tid == 255) F[e] = Fval;
 }
 
 __global__ void __launch_bounds__(NTHREADS) k_contrib(BatchDev b, const double* X, double* M, double* Ev,
                                                        double* Bv, double* F, const int32_t* info) {
   __shared__ Elem E;
   __shared__ int ok;
-  __shared__ double red[NWAVES];
+  __shared__ double red[3 * NWAVES];
+  __shared__ double fsum;
+  extern __shared__ double ft[];   // NI(s+1)
   const int NImax = 3 * (b.l_max + 1);
   for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
+    __syncthreads();
     if (threadIdx.x == 0) ok = (info == nullptr || info[e] == 0 || info[e] == INFO_IR_FALLBACK) &&
                                load_elem(b, e, E) && E.rhs0 >= 0;
     __syncthreads();
-    if (ok) contrib_element(E, b, X + E.rhs0, NImax, M, Ev, Bv, F, e, red);
+    if (!ok) continue;
+    face_table(E, ft);
+    double fs = 0.0, z1 = 0.0, z2 = 0.0;
+    for (int t = threadIdx.x; t < E.s * E.s; t += NTHREADS) fs += b.f[E.tri0 + t];
+    block_sum3(fs, z1, z2, red);   // barriers: ft visible afterwards
+    if (threadIdx.x == 0) fsum = fs * (E.area / ((double)E.s * E.s));
     __syncthreads();
+    contrib_element(E, X + E.rhs0, ft, fsum, NImax, M, Ev, Bv, F, e);
   }
 }
 
 // ================================================================== k_local
-// Diagonal tile: Cholesky factor L and its inverse W = L^{-1}, by one wave, in
-// registers (MFMA result layout of T), right-looking over the 16 columns.
-// Reads the lower triangle of `t`; returns the first failing column or -1.
+// Diagonal tile: Cholesky factor L and its inverse W = L^{-1}, by one wave.
+// Lane c (and its copies c+16, c+32, c+48) keeps column c of the symmetric
+// tile in registers.  Step j broadcasts column j from lane j with readlane
+// (scalar registers feed the FMAs directly), so a step needs no LDS traffic:
+//   a[r][c] -= a[r][j] a[j][c] / a[j][j]             (r, c > j)
+//   W[j][c] = V[j][c] / sqrt(a[j][j]),  V[r][c] -= L[r][j] W[j][c]   (r > j)
+// Column c is final after step c and is scaled by 1/sqrt(a[c][c]) at the end.
+// The tile's slot receives W; L goes to `Lo` (column-major n x n, may be
+// null).  Returns the first failing column or -1.
 template <typename T>
-__device__ int potrf_inv_tile(const T* t, typename Mfma<T>::v4& lv, typename Mfma<T>::v4& wv, int lane) {
-  typedef Mfma<T> MF;
-  const int cc = lane & 15, g = lane >> 4;
-  T a[4], w[4], l[4];
+__device__ __forceinline__ int potrf_tile(T* t, T* Lo, int n, int k, int lane) {
+  const int c = lane & 15;
+  T col[16], w[16];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int r = MF::row(g, v);
-    a[v] = r >= cc ? t[r * TST + cc] : t[cc * TST + r];
-    w[v] = r == cc ? T(1) : T(0);
-    l[v] = T(0);
+  for (int r = 0; r < 16; ++r) {
+    col[r] = r >= c ? t[r * TST + c] : t[c * TST + r];
+    w[r] = r == c ? T(1) : T(0);
   }
   int bad = -1;
+  T myrs = T(1);
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const int gj = MF::grp(j), vj = MF::item(j);    // lane group and item holding row j
-    T ajj = readlane(a[vj], j + 16 * gj);
+    T ajj = readlane(col[j], j);
     if (!(ajj > T(0))) {
       if (bad < 0) bad = j;
       ajj = T(1);
     }
     const T rs = rsqrt_t(ajj);
-    T colv[4];
+    if (c == j) myrs = rs;
+    const T tj = col[j] * (rs * rs);      // a[j][c] / a[j][j]
+    const T wj = w[j] * rs;               // W[j][c]
+    const T wjr = wj * rs;
+    w[j] = wj;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) colv[v] = shfl(a[v], j + 16 * g);          // a[row(g,v)][j]
-    const T rowv = shfl(a[vj], cc + 16 * gj);                               // a[j][cc]
-    const T wrow = shfl(w[vj], cc + 16 * gj) * rs;                          // W[j][cc]
-    const T inv = rs * rs;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = MF::row(g, v);
-      const T lc = r >= j ? colv[v] * rs : T(0);                             // L[r][j]
-      if (cc == j) l[v] = lc;
-      a[v] -= colv[v] * rowv * inv;
-      if (r > j) w[v] -= lc * wrow;
-      else if (r == j) w[v] = wrow;
+    for (int r = j + 1; r < 16; ++r) {
+      const T arj = readlane(col[r], j);  // a[r][j]
+      w[r] -= arj * wjr;
+      if (c > j) col[r] -= arj * tj;
     }
   }
+  if (lane < 16) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    lv[v] = l[v];
-    wv[v] = w[v];
+    for (int r = 0; r < 16; ++r) t[r * TST + c] = w[r];
+    if (Lo) {
+      const int q = 16 * k + c;
+      if (q < n) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int p = 16 * k + r;
+          if (r >= c && p < n) Lo[(int64_t)q * n + p] = col[r] * myrs;
+        }
+      }
+    }
   }
   return bad;
 }
 
-// Store the accumulator tile (rows 16I.., cols 16J..) of L into a column-major
+// Store the result tile (rows 16I.., cols 16J..) of L into a column-major
 // n x n matrix (lower triangle only).
 template <typename T>
 __device__ __forceinline__ void store_L(T* Lo, int n, int I, int J, const typename Mfma<T>::v4& acc, int lane) {
@@ -310,13 +353,27 @@ __device__ __forceinline__ void store_L(T* Lo, int n, int I, int J, const typena
   }
 }
 
+// Trailing tile t of step k -> (i, j): columns j = k+1 .. nt-1, rows i = j .. nt
+// (row nt is the right-hand-side row).
+__device__ __forceinline__ void trail_ij(int t, int k, int nt, int& i, int& j) {
+  const int m = nt - 1 - k;
+  int jj = 0, rem = t;
+  while (rem >= m - jj + 1) {
+    rem -= m - jj + 1;
+    ++jj;
+  }
+  j = k + 1 + jj;
+  i = j + rem;
+}
+
 template <typename T, bool IN_LDS, bool FUSED>
 __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) {
+  typedef typename Mfma<T>::v4 V4;
   __shared__ Elem E;
   __shared__ int ok, bad, conv;
-  __shared__ double red[NWAVES];
+  __shared__ double red[3 * NWAVES];
   __shared__ double colsum[16];
-  __shared__ double cx[16];          // c^T X per column
+  __shared__ double cx[16];          // (c^T X) per column
   __shared__ double gam;
   __shared__ double wred[NWAVES][3][16];
   extern __shared__ double dyn[];
@@ -333,7 +390,9 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
       } else {
         const bool good = load_elem(b, e, E) && E.rhs0 >= 0 && (FUSED || E.mat0 >= 0);
         if (!good) st = INFO_BAD_DESC;
-        else if ((E.nt * (E.nt + 1)) / 2 + E.nt > args.tile_cap || E.n > args.n_cap) st = INFO_TOO_LARGE;
+        else if ((E.nt * (E.nt + 1)) / 2 + E.nt > args.tile_cap || E.n > args.n_cap ||
+                 (FUSED && E.NI * (E.s + 1) > args.f_cap) || (FUSED && IN_LDS && E.s * E.s > args.k_cap))
+          st = INFO_TOO_LARGE;
         ok = st == INFO_OK;
         if (!ok || !args.only_fallback) args.info[e] = st;
         if (args.ir_iters && !args.only_fallback) args.ir_iters[e] = 0;
@@ -342,49 +401,60 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
       conv = 0;
     }
     __syncthreads();
-    if (!ok) { __syncthreads(); continue; }
+    if (!ok) continue;
 
     const int s = E.s, n = E.n, r = E.r, nt = E.nt, T2 = s * s;
-    // dynamic LDS: c[n_cap] | kap[k_cap] (fused, in LDS) | tiles (IN_LDS)
+    // dynamic LDS: c[n_cap] | bf[n_cap] | ft[f_cap] | kap[k_cap] | tiles (IN_LDS)
     double* c = dyn;
-    double* kapl = dyn + args.n_cap;
+    double* bf = c + args.n_cap;
+    double* ft = bf + args.n_cap;
+    double* kapl = ft + args.f_cap;
     const bool kap_lds = FUSED && IN_LDS;
-    T* tiles = IN_LDS ? reinterpret_cast<T*>(dyn + args.n_cap + args.k_cap)
+    T* tiles = IN_LDS ? reinterpret_cast<T*>(kapl + args.k_cap)
                       : reinterpret_cast<T*>(args.ws) + (int64_t)blockIdx.x * args.ws_slot;
+    // tile (I,J), J <= I <= nt; row nt holds the right-hand sides (transposed)
     auto tl = [&](int I, int J) -> T* { return tiles + (int64_t)((I * (I + 1)) / 2 + J) * TILE; };
-    auto tr_ = [&](int J) -> T* { return tiles + (int64_t)((nt * (nt + 1)) / 2 + J) * TILE; };
     const double* kapg = b.kappa + E.tri0;
     auto kap = [&](int t) -> double { return kap_lds ? kapl[t] : kapg[t]; };
 
+    // ------------------------------------------------------------- set-up
     if (kap_lds)
       for (int t = tid; t < T2; t += NTHREADS) kapl[t] = kapg[t];
+    if (FUSED) face_table(E, ft);
     __syncthreads();
-    // c (closed form), gamma
-    double tr = 0.0, cc2 = 0.0;
-    for (int p = tid; p < n; p += NTHREADS) {
-      int i, j;
-      node_ij(p, s, i, j);
-      const double cp = node_tri_count(i, j, s) * E.cunit;
-      c[p] = cp;
-      cc2 += cp * cp;
-      if (FUSED) tr += stencil(i, j, s, E.G, kap).d;
-    }
-    cc2 = block_sum(cc2, red);
-    if (FUSED) {
-      tr = block_sum(tr, red);
-      if (tid == 0) gam = tr / (n * cc2);
-      rhs_column_sums(E, b, colsum, red);
+    {
+      double tr = 0.0, cc2 = 0.0, fs = 0.0;
+      const double* fp = b.f + E.tri0;
+      for (int p = tid; p < n; p += NTHREADS) {
+        int i, j;
+        node_ij(p, s, i, j);
+        const double cp = node_tri_count(i, j, s) * E.cunit;
+        c[p] = cp;
+        cc2 += cp * cp;
+        if (FUSED || fp32) tr += stencil(i, j, s, E.G, kap).d;
+        if (FUSED) {
+          const double bp = E.cunit * node_tri_sum(i, j, s, [&](int t) { return fp[t]; });
+          bf[p] = bp;
+          fs += bp;
+        }
+      }
+      block_sum3(tr, cc2, fs, red);
+      if (tid == 0) {
+        gam = tr / (n * cc2);
+        colsum[E.NI] = fs;
+      }
+      if (FUSED) face_colsums(E, ft, colsum);
     }
     __syncthreads();
 
     // ---------------------------------------------------------- fill tiles
     if (FUSED) {
       const double g = gam;
+      const int rr = tid >> 4, cl = tid & 15;
       for (int I = 0; I < nt; ++I)
         for (int J = 0; J <= I; ++J) {
-          const int rr = tid >> 4, cl = tid & 15;   // tid < 256 covers the tile
           const int p = 16 * I + rr, q = 16 * J + cl;
-          double v = (p < n && q < n) ? g * c[p] * c[q] : (p == q ? 1.0 : 0.0);
+          const double v = (p < n && q < n) ? g * c[p] * c[q] : (p == q ? 1.0 : 0.0);
           tl(I, J)[rr * TST + cl] = (T)v;
         }
       __syncthreads();
@@ -404,146 +474,179 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
         if (i >= 1) add(q + (s - j), st.nw);
       }
       for (int J = 0; J < nt; ++J) {
-        const int a = tid >> 4, cl = tid & 15, p = 16 * J + cl;
+        const int a = rr, p = 16 * J + cl;
         double v = 0.0;
         if (a < r && p < n) {
           int i, j;
           node_ij(p, s, i, j);
-          v = btilde_entry(E, b, colsum, a, i, j, c[p]);
+          v = btilde_tab(E, ft, bf, c, colsum, a, p, i, j);
         }
-        tr_(J)[a * TST + cl] = (T)v;
+        tl(nt, J)[a * TST + cl] = (T)v;
       }
     } else {
       const double* A = args.Ahat + E.mat0;
+      const int rr = tid & 15, cl = tid >> 4;
       for (int I = 0; I < nt; ++I)
         for (int J = 0; J <= I; ++J) {
-          const int rr = tid & 15, cl = tid >> 4;
           const int p = 16 * I + rr, q = 16 * J + cl;
           const double v = (p < n && q < n) ? A[(int64_t)q * n + p] : (p == q ? 1.0 : 0.0);
           tl(I, J)[rr * TST + cl] = (T)v;
         }
       const double* Bt = args.Btil + E.rhs0;
       for (int J = 0; J < nt; ++J) {
-        const int a = tid >> 4, cl = tid & 15, p = 16 * J + cl;
+        const int a = tid >> 4, p = 16 * J + (tid & 15);
         const double v = (a < r && p < n) ? Bt[(int64_t)a * n + p] : 0.0;
-        tr_(J)[a * TST + cl] = (T)v;
+        tl(nt, J)[a * TST + (tid & 15)] = (T)v;
       }
     }
     __syncthreads();
 
     // ------------------------------------------------------- factorisation
+    // Right-looking over tile columns k; the right-hand-side row nt is
+    // eliminated with the matrix, so it ends holding Y^T = (L^{-1} Btilde)^T.
+    // Look-ahead: wave 0 updates tile (k+1,k+1) first and factors it while
+    // the other waves finish the trailing update of step k.
     T* Lo = nullptr;
     if (args.Lout && E.mat0 >= 0) Lo = reinterpret_cast<T*>(args.Lout + E.mat0);
-    for (int k = 0; k < nt; ++k) {
-      if (wave == 0) {
-        typename Mfma<T>::v4 lv, wv;
-        const int bj = potrf_inv_tile<T>(tl(k, k), lv, wv, lane);
-        if (Lo) store_L<T>(Lo, n, k, k, lv, lane);
-        st_acc<T>(tl(k, k), wv, lane);
-        if (lane == 0 && bj >= 0 && bad < 0) bad = 16 * k + bj;
+    // Step k = -1 only factors the first diagonal tile.
+    for (int k = -1; k < nt; ++k) {
+      if (k >= 0) {
+        // panel: L_ik = A_ik W_kk^T, i = k+1 .. nt
+        for (int i = k + 1 + wave; i <= nt; i += 2 * NWAVES) {
+          const int i2 = i + NWAVES;
+          const bool two = i2 <= nt;
+          V4 a1 = {0, 0, 0, 0}, a2 = {0, 0, 0, 0};
+          const T* W = tl(k, k);
+          const T* A1 = tl(i, k);
+          const T* A2 = tl(two ? i2 : i, k);
+#pragma unroll
+          for (int cch = 0; cch < 4; ++cch) {
+            const T wv = ld_rowcol(W, cch, lane);
+            a1 = Mfma<T>::op(ld_rowcol(A1, cch, lane), wv, a1);
+            a2 = Mfma<T>::op(ld_rowcol(A2, cch, lane), wv, a2);
+          }
+          st_acc<T>(tl(i, k), a1, lane);
+          if (Lo && i < nt) store_L<T>(Lo, n, i, k, a1, lane);
+          if (two) {
+            st_acc<T>(tl(i2, k), a2, lane);
+            if (Lo && i2 < nt) store_L<T>(Lo, n, i2, k, a2, lane);
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      // panel: L_ik = A_ik W_kk^T
-      for (int i = k + 1 + wave; i < nt; i += NWAVES) {
-        typename Mfma<T>::v4 acc = {0, 0, 0, 0};
-        mma_add_nt<T>(acc, tl(i, k), tl(k, k), lane);
-        st_acc<T>(tl(i, k), acc, lane);
-        if (Lo) store_L<T>(Lo, n, i, k, acc, lane);
-      }
-      __syncthreads();
-      // trailing update: C_ij -= L_ik L_jk^T, k < j <= i
+      // trailing update C_ij -= L_ik L_jk^T (k < j <= i <= nt); wave 0 takes
+      // tile (k+1, k+1) (trailing tile 0) and factors it
       const int m = nt - 1 - k;
-      const int ntr = m * (m + 1) / 2;
-      for (int t = wave; t < ntr; t += NWAVES) {
-        // t -> (i, j) over the trailing lower triangle, column by column
-        int jj = 0, rem = t;
-        while (rem >= m - jj) { rem -= m - jj; ++jj; }
-        const int j = k + 1 + jj, i = j + rem;
-        typename Mfma<T>::v4 acc = ld_acc<T>(tl(i, j), lane);
-        mma_sub_nt<T>(acc, tl(i, k), tl(j, k), lane);
-        st_acc<T>(tl(i, j), acc, lane);
+      if (wave == 0) {
+        if (m > 0) {
+          if (k >= 0) {
+            V4 acc = ld_acc<T>(tl(k + 1, k + 1), lane);
+            mma_sub_nt<T>(acc, tl(k + 1, k), tl(k + 1, k), lane);
+            st_acc<T>(tl(k + 1, k + 1), acc, lane);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // the stores above before the reads below
+          }
+          const int bj = potrf_tile<T>(tl(k + 1, k + 1), Lo, n, k + 1, lane);
+          if (lane == 0 && bj >= 0 && bad < 0) bad = 16 * (k + 1) + bj;
+        }
+      } else if (k >= 0 && m > 0) {
+        const int ntr = m * (m + 3) / 2;
+        const int nw = NWAVES - 1;
+        for (int t = wave; t < ntr; t += 2 * nw) {
+          const int t2 = t + nw;
+          const bool two = t2 < ntr;
+          int i1, j1, i2, j2;
+          trail_ij(t, k, nt, i1, j1);
+          if (two) {
+            trail_ij(t2, k, nt, i2, j2);
+          } else {
+            i2 = i1;
+            j2 = j1;
+          }
+          V4 c1 = ld_acc<T>(tl(i1, j1), lane);
+          V4 c2 = ld_acc<T>(tl(i2, j2), lane);
+          const T* Li1 = tl(i1, k);
+          const T* Lj1 = tl(j1, k);
+          const T* Li2 = tl(i2, k);
+          const T* Lj2 = tl(j2, k);
+#pragma unroll
+          for (int cch = 0; cch < 4; ++cch) {
+            c1 = Mfma<T>::op(-ld_rowcol(Li1, cch, lane), ld_rowcol(Lj1, cch, lane), c1);
+            c2 = Mfma<T>::op(-ld_rowcol(Li2, cch, lane), ld_rowcol(Lj2, cch, lane), c2);
+          }
+          st_acc<T>(tl(i1, j1), c1, lane);
+          if (two) st_acc<T>(tl(i2, j2), c2, lane);
+        }
       }
       __syncthreads();
     }
 
     // ---------------------------------------------- solves on the RHS row
     // Stored RHS tile J holds Z_J^T (rows: right-hand sides, cols: nodes).
-    auto solve_rhs = [&]() {
-      for (int j = 0; j < nt; ++j) {       // forward: Y = L^{-1} Z
+    auto backward = [&]() {
+      for (int j = nt - 1; j >= 0; --j) {  // X = L^{-T} Y
         if (wave == (j & (NWAVES - 1))) {
-          typename Mfma<T>::v4 acc = {0, 0, 0, 0};
-          mma_add_nt<T>(acc, tr_(j), tl(j, j), lane);   // Y_j^T = Z_j^T W_j^T
-          st_acc<T>(tr_(j), acc, lane);
-        }
-        __syncthreads();
-        for (int i = j + 1 + wave; i < nt; i += NWAVES) {
-          typename Mfma<T>::v4 acc = ld_acc<T>(tr_(i), lane);
-          mma_sub_nt<T>(acc, tr_(j), tl(i, j), lane);  // Z_i^T -= Y_j^T L_ij^T
-          st_acc<T>(tr_(i), acc, lane);
-        }
-        __syncthreads();
-      }
-      for (int j = nt - 1; j >= 0; --j) {  // backward: X = L^{-T} Y
-        if (wave == (j & (NWAVES - 1))) {
-          typename Mfma<T>::v4 acc = {0, 0, 0, 0};
-          mma_add_nn<T>(acc, tr_(j), tl(j, j), lane);   // X_j^T = Z_j^T W_j
-          st_acc<T>(tr_(j), acc, lane);
+          V4 acc = {0, 0, 0, 0};
+          mma_add_nn<T>(acc, tl(nt, j), tl(j, j), lane);   // X_j^T = Z_j^T W_j
+          st_acc<T>(tl(nt, j), acc, lane);
         }
         __syncthreads();
         for (int i = wave; i < j; i += NWAVES) {
-          typename Mfma<T>::v4 acc = ld_acc<T>(tr_(i), lane);
-          mma_sub_nn<T>(acc, tr_(j), tl(j, i), lane);  // Z_i^T -= X_j^T L_ji
-          st_acc<T>(tr_(i), acc, lane);
+          V4 acc = ld_acc<T>(tl(nt, i), lane);
+          mma_sub_nn<T>(acc, tl(nt, j), tl(j, i), lane);  // Z_i^T -= X_j^T L_ji
+          st_acc<T>(tl(nt, i), acc, lane);
         }
         __syncthreads();
       }
     };
-    solve_rhs();
-
-    double* X = args.X + E.rhs0;
-    const bool failed = bad >= 0;
-    if (!failed) {
-      // X (FP64) from the solved tiles
-      for (int idx = tid; idx < n * r; idx += NTHREADS) {
-        const int a = idx / n, p = idx - a * n;
-        X[idx] = (double)tr_(p >> 4)[a * TST + (p & 15)];
-      }
-      __syncthreads();
-    }
-
-    // --------------------------------------- FP64 refinement (FP32 path)
-    if (fp32 && !failed) {
-      const double* Btg = FUSED ? nullptr : args.Btil + E.rhs0;
-      double g = gam;
-      if (!FUSED) {
-        // gamma = trace(A) / (n c^T c), the same reduction order as k_assemble
-        double t = 0.0;
-        for (int p = tid; p < n; p += NTHREADS) {
-          int i, j;
-          node_ij(p, s, i, j);
-          t += stencil(i, j, s, E.G, kap).d;
-        }
-        t = block_sum(t, red);
-        g = t / (n * cc2);
-      }
-      int it = 0;
-      for (;; ++it) {
-        // c^T X per column
-        for (int a = 0; a < r; ++a) {
-          double v = 0.0;
-          for (int p = tid; p < n; p += NTHREADS) v += c[p] * X[(int64_t)a * n + p];
-          v = block_sum(v, red);
-          if (tid == 0) cx[a] = v;
+    auto forward = [&]() {
+      for (int j = 0; j < nt; ++j) {       // Y = L^{-1} Z
+        if (wave == (j & (NWAVES - 1))) {
+          V4 acc = {0, 0, 0, 0};
+          mma_add_nt<T>(acc, tl(nt, j), tl(j, j), lane);   // Y_j^T = Z_j^T W_j^T
+          st_acc<T>(tl(nt, j), acc, lane);
         }
         __syncthreads();
-        // residual R = Btilde - (A X + gamma c (c^T X)), into the RHS tiles (FP32)
+        for (int i = j + 1 + wave; i < nt; i += NWAVES) {
+          V4 acc = ld_acc<T>(tl(nt, i), lane);
+          mma_sub_nt<T>(acc, tl(nt, j), tl(i, j), lane);  // Z_i^T -= Y_j^T L_ij^T
+          st_acc<T>(tl(nt, i), acc, lane);
+        }
+        __syncthreads();
+      }
+    };
+    backward();
+    const bool failed = bad >= 0;
+
+    double* X = args.X + E.rhs0;
+    const int ca = tid >> 4, cl16 = tid & 15;   // 16 columns x 16 lanes for column sums
+
+    if (fp32 && !failed) {
+      // --------------------------------------- FP64 refinement (FP32 path)
+      for (int idx = tid; idx < n * r; idx += NTHREADS) {
+        const int a = idx / n, p = idx - a * n;
+        X[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)];
+      }
+      __syncthreads();
+      const double* Btg = FUSED ? nullptr : args.Btil + E.rhs0;
+      const double g = gam;
+      int it = 0;
+      for (;; ++it) {
+        {  // c^T X per column
+          double v = 0.0;
+          if (ca < r)
+            for (int p = cl16; p < n; p += 16) v += c[p] * X[(int64_t)ca * n + p];
+          v = group16_sum(v);
+          if (cl16 == 0) cx[ca] = v;
+        }
+        __syncthreads();
+        // residual R = Btilde - (A X + gamma c (c^T X)) into the RHS tiles (FP32)
         double rmax[16], xmax[16], bmax[16];
         double anorm = 0.0;
 #pragma unroll
         for (int a = 0; a < 16; ++a) rmax[a] = xmax[a] = bmax[a] = 0.0;
         for (int p = tid; p < 16 * nt; p += NTHREADS) {
           if (p >= n) {
-            for (int a = 0; a < 16; ++a) tr_(p >> 4)[a * TST + (p & 15)] = T(0);
+            for (int a = 0; a < 16; ++a) tl(nt, p >> 4)[a * TST + (p & 15)] = T(0);
             continue;
           }
           int i, j;
@@ -567,16 +670,15 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
               if (hS) ax += st.so * xa[pS];
               if (hNW) ax += st.nw * xa[pNW];
               if (hSE) ax += st.se * xa[pSE];
-              const double bv = FUSED ? btilde_entry(E, b, colsum, a, i, j, cp) : Btg[(int64_t)a * n + p];
+              const double bv = FUSED ? btilde_tab(E, ft, bf, c, colsum, a, p, i, j) : Btg[(int64_t)a * n + p];
               rv = bv - ax;
               rmax[a] = fmax(rmax[a], fabs(rv));
               xmax[a] = fmax(xmax[a], fabs(xa[p]));
               bmax[a] = fmax(bmax[a], fabs(bv));
             }
-            tr_(p >> 4)[a * TST + (p & 15)] = (T)rv;
+            tl(nt, p >> 4)[a * TST + (p & 15)] = (T)rv;
           }
         }
-        // per-column maxima across the block
         anorm = block_max(anorm, red);
 #pragma unroll
         for (int a = 0; a < 16; ++a) {
@@ -606,26 +708,35 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
         }
         __syncthreads();
         if (conv || it >= args.max_iters) break;
-        solve_rhs();
+        forward();
+        backward();
         for (int idx = tid; idx < n * r; idx += NTHREADS) {
           const int a = idx / n, p = idx - a * n;
-          X[idx] += (double)tr_(p >> 4)[a * TST + (p & 15)];
+          X[idx] += (double)tl(nt, p >> 4)[a * TST + (p & 15)];
         }
         __syncthreads();
       }
+      const bool cvd = conv;
       if (tid == 0) {
         if (args.ir_iters) args.ir_iters[e] = it;
-        if (!conv) args.info[e] = INFO_IR_FALLBACK;
+        if (!cvd) args.info[e] = INFO_IR_FALLBACK;
+      }
+      if (!cvd) continue;   // recomputed by the FP64 fallback pass
+      {  // zero-mean projection of the FP64 iterate
+        double v = 0.0;
+        if (ca < r)
+          for (int p = cl16; p < n; p += 16) v += c[p] * X[(int64_t)ca * n + p];
+        v = group16_sum(v);
+        if (cl16 == 0) cx[ca] = v * E.inv_area;
       }
       __syncthreads();
-      if (!conv) continue;   // recomputed by the FP64 fallback pass
-    }
-    if (fp32 && failed) {
-      if (tid == 0) args.info[e] = INFO_IR_FALLBACK;
+      for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] -= cx[idx / n];
       __syncthreads();
+    } else if (fp32) {
+      // FP32 pivot failure: recomputed by the FP64 fallback pass
+      if (tid == 0) args.info[e] = INFO_IR_FALLBACK;
       continue;
-    }
-    if (failed) {
+    } else if (failed) {
       for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] = __builtin_nan("");
       if (tid == 0) args.info[e] = bad + 1;
       if (FUSED && args.M) {
@@ -637,26 +748,24 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
         }
         if (tid == 0) args.F[e] = __builtin_nan("");
       }
-      __syncthreads();
       continue;
+    } else {
+      {  // zero-mean projection in FP64, straight from the solved tiles
+        double v = 0.0;
+        if (ca < r)
+          for (int p = cl16; p < n; p += 16) v += c[p] * (double)tl(nt, p >> 4)[ca * TST + (p & 15)];
+        v = group16_sum(v);
+        if (cl16 == 0) cx[ca] = v * E.inv_area;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < n * r; idx += NTHREADS) {
+        const int a = idx / n, p = idx - a * n;
+        X[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)] - cx[a];
+      }
+      __syncthreads();
     }
 
-    // ------------------------------------------- zero-mean projection (FP64)
-    for (int a = 0; a < r; ++a) {
-      double v = 0.0;
-      for (int p = tid; p < n; p += NTHREADS) v += c[p] * X[(int64_t)a * n + p];
-      v = block_sum(v, red);
-      if (tid == 0) cx[a] = v / E.area;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < n * r; idx += NTHREADS) {
-      const int a = idx / n;
-      X[idx] -= cx[a];
-    }
-    __syncthreads();
-
-    if (FUSED && args.M) contrib_element(E, b, X, NImax, args.M, args.E, args.B, args.F, e, red);
-    __syncthreads();
+    if (FUSED && args.M) contrib_element(E, X, ft, colsum[E.NI], NImax, args.M, args.E, args.B, args.F, e);
   }
 }
 
@@ -684,11 +793,13 @@ static BatchDev to_dev(const mhm_batch* p) {
   return d;
 }
 
+int local_face_cap(const mhm_batch* bt) { return 3 * (bt->l_max + 1) * (bt->s_max + 1); }
+
 hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, double* c, double* area, int32_t* info,
                            int grid, hipStream_t st) {
   const int smax = bt->s_max;
   const int nmax = (smax + 1) * (smax + 2) / 2;
-  const size_t lds = sizeof(double) * ((size_t)smax * smax + nmax);
+  const size_t lds = sizeof(double) * ((size_t)smax * smax + 2 * (size_t)nmax + local_face_cap(bt));
   hipError_t err = hipFuncSetAttribute((const void*)k_assemble, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_assemble, dim3(grid), dim3(NTHREADS), lds, st, to_dev(bt), Ahat, Btil, c, area, info);
@@ -697,7 +808,10 @@ hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, doub
 
 hipError_t launch_contrib(const mhm_batch* bt, const double* X, double* M, double* E, double* B, double* F,
                           const int32_t* info, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_contrib, dim3(grid), dim3(NTHREADS), 0, st, to_dev(bt), X, M, E, B, F, info);
+  const size_t lds = sizeof(double) * local_face_cap(bt);
+  hipError_t err = hipFuncSetAttribute((const void*)k_contrib, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_contrib, dim3(grid), dim3(NTHREADS), lds, st, to_dev(bt), X, M, E, B, F, info);
   return hipGetLastError();
 }
 
@@ -710,10 +824,9 @@ static hipError_t launch_local_t(const mhm_batch* bt, LocalArgs a, size_t lds, i
   return hipGetLastError();
 }
 
-size_t local_lds_bytes(bool fp32, bool in_lds, bool fused, int n_cap, int k_cap, int tile_cap) {
-  size_t bytes = sizeof(double) * ((size_t)n_cap + (size_t)k_cap);
+size_t local_lds_bytes(bool fp32, bool in_lds, int n_cap, int f_cap, int k_cap, int tile_cap) {
+  size_t bytes = sizeof(double) * (2 * (size_t)n_cap + (size_t)f_cap + (size_t)k_cap);
   if (in_lds) bytes += (size_t)tile_cap * TILE * (fp32 ? sizeof(float) : sizeof(double));
-  (void)fused;
   return bytes;
 }
 

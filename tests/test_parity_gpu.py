@@ -215,3 +215,58 @@ def test_batch_invariance_alone_vs_mixed(ctx):
         alone = _run(ctx, sub_batch(b, [e]), 0, "fused")[0]
         np.testing.assert_array_equal(alone["X"], full[e]["X"])
         np.testing.assert_array_equal(alone["M"], full[e]["M"])
+
+
+# ------------------------------------------------------- per-call outputs
+def _assemble_and_factor(ctx, b, prec=0):
+    import torch
+    from paper_1703_10435_amd import batch as hb
+    db = hb.DeviceBatch(b)
+    out = db.alloc_outputs(three_call=True)
+    say(f"[gpu] assemble+factor {b.get('name', '?')} n_elem={b['n_elem']} prec={prec}")
+    ctx.local_assemble(db, out["Ahat"], out["Btil"], out["c"], out["area"], out["info"])
+    ctx.sync()
+    A0 = out["Ahat"].cpu().numpy().copy()
+    B0 = out["Btil"].cpu().numpy().copy()
+    c0 = out["c"].cpu().numpy().copy()
+    ar = out["area"].cpu().numpy().copy()
+    info_a = out["info"].cpu().numpy().copy()
+    ctx.local_factor_solve(db, prec, out["Ahat"], out["Btil"], out["X"], out["info"], out["ir_iters"], 10)
+    ctx.sync()
+    L = out["Ahat"].cpu().numpy().copy()
+    return db, A0, B0, c0, ar, info_a, L
+
+
+@pytest.mark.parametrize("which", ["C1", "ragged"])
+def test_assemble_outputs_match_definition(ctx, which):
+    """Ahat = A + gamma c c^T with gamma = trace(A)/(n c^T c), Btilde = B -
+    c (1^T B)/|K|, c and |K| against the oracle's A, c, R, b."""
+    b = configs.make("C1") if which == "C1" else _random_batch(21, [1, 3, 5, 16, 7], [0, 1, 4, 2, 3], "asm")
+    db, A0, B0, c0, ar, info_a, _ = _assemble_and_factor(ctx, b)
+    assert np.all(info_a[:b["n_elem"]] == 0)
+    for e in range(b["n_elem"]):
+        ora = local.solve_element(b, e)
+        n = ora["A"].shape[0]
+        r = ora["X"].shape[1]
+        gam = np.trace(ora["A"]) / (n * (ora["c"] @ ora["c"]))
+        Ahat = ora["A"] + gam * np.outer(ora["c"], ora["c"])
+        Bf = np.column_stack([ora["R"], ora["b"]])
+        Bt = Bf - np.outer(ora["c"], Bf.sum(axis=0)) / ora["area"]
+        Ag = A0[db.mat_off[e]:db.mat_off[e + 1]].reshape(n, n).T
+        Bg = B0[db.rhs_off[e]:db.rhs_off[e + 1]].reshape(r, n).T
+        cg = c0[db.node_off[e]:db.node_off[e + 1]]
+        assert np.abs(Ag - Ahat).max() <= 1e-13 * np.abs(Ahat).max(), (e, np.abs(Ag - Ahat).max())
+        assert np.abs(Bg - Bt).max() <= 1e-13 * max(np.abs(Bt).max(), 1e-300), e
+        assert np.abs(cg - ora["c"]).max() <= 1e-14 * ora["c"].max(), e
+        assert ar[e] == pytest.approx(ora["area"], rel=1e-15)
+
+
+def test_factor_output_reproduces_ahat(ctx):
+    b = _random_batch(22, [16, 4, 24], [2, 1, 3], "factor")
+    db, A0, B0, c0, ar, info_a, L0 = _assemble_and_factor(ctx, b)
+    for e in range(b["n_elem"]):
+        n = int(db.n[e])
+        Ah = A0[db.mat_off[e]:db.mat_off[e + 1]].reshape(n, n).T
+        L = np.tril(L0[db.mat_off[e]:db.mat_off[e + 1]].reshape(n, n).T)
+        err = np.abs(L @ L.T - Ah).max() / np.abs(Ah).max()
+        assert err < 1e-14, (e, err)
