@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmhm.so")
-SOURCES = ["mhm_kernels.hip", "mhm_api.hip"]
+SOURCES = ["mhm_kernels.hip", "mhm_local_rr.hip", "mhm_api.hip"]
 ARCH = "gfx950"
 
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -15,6 +16,7 @@ struct mhm_ctx_s {
   hipStream_t stream = nullptr;
   int n_cu = 256;
   size_t lds_limit = 160 * 1024;
+  bool no_rr = false;          // MHM_NO_RR=1: use the LDS-tile kernel for FP64 too
   void* ws = nullptr;
   size_t ws_bytes = 0;
   std::string err;
@@ -60,7 +62,7 @@ int grid_for(const mhm_batch* b) { return std::min(b->n_elem, kGridCap); }
 
 // Launch plan of k_local for a batch.
 struct Plan {
-  bool fp32, in_lds;
+  bool fp32, in_lds, rr;
   int nt, tile_cap, n_cap, f_cap, k_cap, grid;
   size_t lds, ws_need;
   int64_t ws_slot;
@@ -77,6 +79,17 @@ Plan plan_local(mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, bool force
   const int k_lds = fused ? b->s_max * b->s_max : 0;
   const size_t lds_in = mhm::local_lds_bytes(fp32, true, p.n_cap, p.f_cap, k_lds, p.tile_cap);
   p.in_lds = !force_ws && lds_in + kStaticLds <= c->lds_limit;
+  // FP64 elements of up to 16 * local_rr_max_nt() nodes: register-resident kernel
+  p.rr = !fp32 && !force_ws && !c->no_rr && p.nt <= mhm::local_rr_max_nt();
+  if (p.rr) {
+    p.in_lds = true;
+    p.k_cap = k_lds;
+    p.lds = mhm::local_rr_lds_bytes(p.n_cap, p.f_cap, k_lds);
+    p.grid = grid_for(b);
+    p.ws_slot = 0;
+    p.ws_need = 0;
+    return p;
+  }
   if (p.in_lds) {
     p.k_cap = k_lds;
     p.lds = lds_in;
@@ -144,7 +157,8 @@ mhm_status run_local(mhm_ctx c, const mhm_batch* b, mhm_prec prec, bool fused, c
   a.n_cap = p.n_cap;
   a.f_cap = p.f_cap;
   a.k_cap = p.k_cap;
-  hipError_t e = mhm::launch_local(fp32, p.in_lds, fused, b, a, p.lds, p.grid, c->stream);
+  hipError_t e = p.rr ? mhm::launch_local_rr(fused, b, a, p.lds, p.grid, c->stream)
+                      : mhm::launch_local(fp32, p.in_lds, fused, b, a, p.lds, p.grid, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "k_local launch");
   if (fp32) {
     // FP64 recomputation of the elements whose refinement did not converge
@@ -182,6 +196,8 @@ mhm_status mhm_create(mhm_ctx* out, int device, void* hip_stream) {
   if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
   mhm_ctx c = new mhm_ctx_s();
   c->device = device;
+  const char* nrr = std::getenv("MHM_NO_RR");
+  c->no_rr = nrr && nrr[0] == '1';
   c->stream = static_cast<hipStream_t>(hip_stream);
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0) c->n_cu = v;

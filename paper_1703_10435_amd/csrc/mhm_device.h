@@ -35,6 +35,29 @@ struct BatchDev {
   int64_t tri_total, mat_total, rhs_total, node_total;
 };
 
+inline BatchDev to_dev(const mhm_batch* p) {
+  BatchDev d;
+  d.n_elem = p->n_elem;
+  d.s_max = p->s_max;
+  d.l_max = p->l_max;
+  d.s = p->s;
+  d.l = p->l;
+  d.vert = p->vert;
+  d.sigma = p->sigma;
+  d.flip = p->flip;
+  d.kappa = p->kappa;
+  d.f = p->f;
+  d.tri_off = p->tri_off;
+  d.mat_off = p->mat_off;
+  d.rhs_off = p->rhs_off;
+  d.node_off = p->node_off;
+  d.tri_total = p->tri_total;
+  d.mat_total = p->mat_total;
+  d.rhs_total = p->rhs_total;
+  d.node_total = p->node_total;
+  return d;
+}
+
 // One element's geometry and offsets, decoded once per workgroup.
 struct Elem {
   int s, l, n, NI, r, nt;   // nt = ceil(n / 16) tiles per matrix edge

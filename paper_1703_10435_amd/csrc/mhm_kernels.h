@@ -38,6 +38,10 @@ hipError_t launch_contrib(const mhm_batch* bt, const double* X, double* M, doubl
                           const int32_t* info, int grid, hipStream_t st);
 size_t local_lds_bytes(bool fp32, bool in_lds, int n_cap, int f_cap, int k_cap, int tile_cap);
 int local_face_cap(const mhm_batch* bt);
+// Register-resident FP64 kernel for elements with n <= 16 * local_rr_max_nt().
+size_t local_rr_lds_bytes(int n_cap, int f_cap, int k_cap);
+int local_rr_max_nt();
+hipError_t launch_local_rr(bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid, hipStream_t st);
 hipError_t launch_local(bool fp32, bool in_lds, bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
                         hipStream_t st);
 

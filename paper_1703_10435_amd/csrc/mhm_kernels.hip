@@ -770,29 +770,6 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
 }
 
 // ------------------------------------------------------------- host launchers
-static BatchDev to_dev(const mhm_batch* p) {
-  BatchDev d;
-  d.n_elem = p->n_elem;
-  d.s_max = p->s_max;
-  d.l_max = p->l_max;
-  d.s = p->s;
-  d.l = p->l;
-  d.vert = p->vert;
-  d.sigma = p->sigma;
-  d.flip = p->flip;
-  d.kappa = p->kappa;
-  d.f = p->f;
-  d.tri_off = p->tri_off;
-  d.mat_off = p->mat_off;
-  d.rhs_off = p->rhs_off;
-  d.node_off = p->node_off;
-  d.tri_total = p->tri_total;
-  d.mat_total = p->mat_total;
-  d.rhs_total = p->rhs_total;
-  d.node_total = p->node_total;
-  return d;
-}
-
 int local_face_cap(const mhm_batch* bt) { return 3 * (bt->l_max + 1) * (bt->s_max + 1); }
 
 hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, double* c, double* area, int32_t* info,

@@ -1,0 +1,536 @@
+// Register-resident FP64 local-problem kernel (gfx950), for elements with
+// n <= 16*RR_NT nodes.
+//
+// Same steps and results as k_local<double, ...> (a2-a6), organised so that
+// two elements fit on one CU at a time:
+//  * the 16x16 tiles of the lower triangle of Ahat and the right-hand-side
+//    row live in the MFMA accumulators of the four waves (tile number t of
+//    the column-major trapezoid is owned by wave t%4, slot t/4);
+//  * a trailing update C_ij -= L_ik L_jk^T reads its two operands from the
+//    published panel column in LDS and accumulates in registers;
+//  * for f64 the MFMA result layout (lane l holds rows (l/16)+4v of column
+//    l%16) coincides with the B-operand layout (chunk v: rows 4v+(l/16)), so
+//    an L tile held in registers feeds the backward solve directly;
+//  * LDS holds only the current panel column, the inverses W_j of the
+//    diagonal tiles, the right-hand-side row during the backward solve and
+//    the per-element tables (about 53 KB at n = 153).
+#include "mhm_device.h"
+#include "mhm_kernels.h"
+
+namespace mhm {
+
+namespace rr {
+
+constexpr int NTHREADS = 256;
+constexpr int NWAVES = 4;
+constexpr int NT = 10;                              // tiles per matrix edge (n <= 160)
+constexpr int NTILES = NT * (NT + 1) / 2 + NT;      // lower triangle + RHS row
+constexpr int S = (NTILES + NWAVES - 1) / NWAVES;   // register slots per wave
+typedef Mfma<double>::v4 V4;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double group16_sum(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = a;
+    red[NWAVES + w] = b;
+    red[2 * NWAVES + w] = c;
+  }
+  __syncthreads();
+  a = b = c = 0.0;
+#pragma unroll
+  for (int k = 0; k < NWAVES; ++k) {
+    a += red[k];
+    b += red[NWAVES + k];
+    c += red[2 * NWAVES + k];
+  }
+}
+// Value of lane `src` of this lane's 16-lane row (DPP row_newbcast; `src`
+// must fold to a constant).
+__device__ __forceinline__ int row_bcast_i(int x, int src) {
+  switch (src) {
+    case 0: return __builtin_amdgcn_update_dpp(0, x, 0x150, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x151, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, x, 0x152, 0xF, 0xF, false);
+    case 3: return __builtin_amdgcn_update_dpp(0, x, 0x153, 0xF, 0xF, false);
+    case 4: return __builtin_amdgcn_update_dpp(0, x, 0x154, 0xF, 0xF, false);
+    case 5: return __builtin_amdgcn_update_dpp(0, x, 0x155, 0xF, 0xF, false);
+    case 6: return __builtin_amdgcn_update_dpp(0, x, 0x156, 0xF, 0xF, false);
+    case 7: return __builtin_amdgcn_update_dpp(0, x, 0x157, 0xF, 0xF, false);
+    case 8: return __builtin_amdgcn_update_dpp(0, x, 0x158, 0xF, 0xF, false);
+    case 9: return __builtin_amdgcn_update_dpp(0, x, 0x159, 0xF, 0xF, false);
+    case 10: return __builtin_amdgcn_update_dpp(0, x, 0x15A, 0xF, 0xF, false);
+    case 11: return __builtin_amdgcn_update_dpp(0, x, 0x15B, 0xF, 0xF, false);
+    case 12: return __builtin_amdgcn_update_dpp(0, x, 0x15C, 0xF, 0xF, false);
+    case 13: return __builtin_amdgcn_update_dpp(0, x, 0x15D, 0xF, 0xF, false);
+    case 14: return __builtin_amdgcn_update_dpp(0, x, 0x15E, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_update_dpp(0, x, 0x15F, 0xF, 0xF, false);
+  }
+}
+__device__ __forceinline__ double bcast16(double x, int src) {
+  const long long b = __double_as_longlong(x);
+  const int lo = row_bcast_i((int)b, src);
+  const int hi = row_bcast_i((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
+template <class FN>
+__device__ __forceinline__ double node_tri_sum(int i, int j, int s, FN fn) {
+  const int ij = i + j;
+  double a = 0.0;
+  if (ij <= s - 1) a += fn(tri_up(i, j, s));
+  if (i >= 1 && ij <= s) a += fn(tri_up(i - 1, j, s));
+  if (j >= 1 && ij <= s) a += fn(tri_up(i, j - 1, s));
+  if (i >= 1 && j >= 1 && ij <= s) a += fn(tri_dn(i - 1, j - 1, s));
+  if (i >= 1 && ij <= s - 1) a += fn(tri_dn(i - 1, j, s));
+  if (j >= 1 && ij <= s - 1) a += fn(tri_dn(i, j - 1, s));
+  return a;
+}
+
+// Cholesky factor and inverse of one 16x16 tile stored (lower triangle) at
+// `t`, by one wave.  Lanes are split 4 x 16: lane (c, g) = c + 16 g holds
+// rows g + 4v (v = 0..3) of column c, the MFMA result layout; the pivot
+// column is broadcast inside each 16-lane row and the pivot row across rows.
+// Writes W = L^{-1} back to `t` (full tile, zero above the diagonal) and the
+// lower triangle of L to Lo (column-major n x n, may be null).
+__device__ __forceinline__ int potrf_inv(double* t, double* Lo, int n, int k, int lane) {
+  const int c = lane & 15, g = lane >> 4;
+  double a[4], w[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = g + 4 * v;
+    a[v] = r >= c ? t[r * TST + c] : t[c * TST + r];
+    w[v] = r == c ? 1.0 : 0.0;
+  }
+  int bad = -1;
+  double myrs = 1.0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int gj = j & 3, vj = j >> 2;          // lane group / item holding row j
+    // row j of the current matrix, seen from column c: a[j][c] (lane (c, gj), item vj)
+    const double ajc = __shfl(a[vj], c + 16 * gj, 64);
+    double ajj = readlane_d(ajc, j);            // pivot (lane j holds a[j][j])
+    if (!(ajj > 0.0)) {
+      if (bad < 0) bad = j;
+      ajj = 1.0;
+    }
+    const double rs = rsqrt_nr(ajj);
+    if (c == j) myrs = rs;
+    const double inv = rs * rs;
+    // W row j: W[j][c] = V[j][c] / sqrt(ajj) (lane (c, gj), item vj)
+    const double wjc = __shfl(w[vj], c + 16 * gj, 64) * rs;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = g + 4 * v;
+      const double arj = bcast16(a[v], j);      // a[r][j]
+      if (r > j) {
+        w[v] -= arj * rs * wjc;
+        if (c > j) a[v] -= arj * ajc * inv;
+      } else if (r == j) {
+        w[v] = wjc;
+      }
+    }
+  }
+  // column c of L is a[.][c] * myrs for rows >= c (entries above stay as read)
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = g + 4 * v;
+    t[r * TST + c] = w[v];
+  }
+  if (Lo) {
+    const int q = 16 * k + c;
+    if (q < n) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = g + 4 * v, p = 16 * k + r;
+        if (r >= c && p < n) Lo[(int64_t)q * n + p] = a[v] * myrs;
+      }
+    }
+  }
+  return bad;
+}
+
+__device__ __forceinline__ void store_L(double* Lo, int n, int I, int J, const V4& acc, int lane) {
+  const int q = 16 * J + (lane & 15);
+  if (q >= n) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int p = 16 * I + Mfma<double>::row(lane >> 4, v);
+    if (p < n && p >= q) Lo[(int64_t)q * n + p] = acc[v];
+  }
+}
+
+}  // namespace rr
+
+template <bool FUSED>
+__global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalArgs args) {
+  using namespace rr;
+  __shared__ Elem E;
+  __shared__ int ok, bad;
+  __shared__ double red[3 * NWAVES];
+  __shared__ double colsum[16];
+  __shared__ double cx[16];
+  __shared__ double gam;
+  __shared__ short tij[NTILES][2];     // tile number -> (I, J), column-major over the trapezoid
+  extern __shared__ double dyn[];      // c | bf | ft | kap | P[NT+1] | W[NT]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int NImax = 3 * (b.l_max + 1);
+
+  double* c = dyn;
+  double* bf = c + args.n_cap;
+  double* ft = bf + args.n_cap;
+  double* kapl = ft + args.f_cap;
+  double* P = kapl + args.k_cap;       // panel column / right-hand-side row
+  double* Wb = P + (NT + 1) * TILE;    // inverses of the diagonal tiles
+  auto Pt = [&](int I) -> double* { return P + I * TILE; };
+  auto Wt = [&](int J) -> double* { return Wb + J * TILE; };
+
+  V4 acc[S];
+
+  for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
+    __syncthreads();
+    if (tid == 0) {
+      int st = INFO_OK;
+      const bool good = load_elem(b, e, E) && E.rhs0 >= 0 && (FUSED || E.mat0 >= 0);
+      if (!good) st = INFO_BAD_DESC;
+      else if (E.nt > NT || E.n > args.n_cap || (FUSED && (E.NI * (E.s + 1) > args.f_cap || E.s * E.s > args.k_cap)))
+        st = INFO_TOO_LARGE;
+      ok = st == INFO_OK;
+      args.info[e] = st;
+      if (args.ir_iters) args.ir_iters[e] = 0;
+      bad = -1;
+    }
+    __syncthreads();
+    if (!ok) continue;
+    const int s = E.s, n = E.n, r = E.r, nt = E.nt, T2 = s * s;
+    const int ntiles = nt * (nt + 1) / 2 + nt;
+    const double* kapg = b.kappa + E.tri0;
+    auto kap = [&](int t) -> double { return FUSED ? kapl[t] : kapg[t]; };
+
+    // ------------------------------------------------------------- set-up
+    if (FUSED) {
+      for (int t = tid; t < T2; t += NTHREADS) kapl[t] = kapg[t];
+      const int sp1 = s + 1, lp1 = E.l + 1;
+      for (int idx = tid; idx < E.NI * sp1; idx += NTHREADS) {
+        const int a = idx / sp1, k = idx - a * sp1;
+        const int ef = a / lp1, q = a - ef * lp1;
+        ft[idx] = face_load(E, ef, q, k);
+      }
+    }
+    if (tid == 0) {
+      int t = 0;
+      for (int J = 0; J < nt; ++J)
+        for (int I = J; I <= nt; ++I) {
+          tij[t][0] = (short)I;
+          tij[t][1] = (short)J;
+          ++t;
+        }
+    }
+    __syncthreads();
+    {
+      double tr = 0.0, cc2 = 0.0, fs = 0.0;
+      const double* fp = b.f + E.tri0;
+      for (int p = tid; p < n; p += NTHREADS) {
+        int i, j;
+        node_ij(p, s, i, j);
+        const double cp = node_tri_count(i, j, s) * E.cunit;
+        c[p] = cp;
+        cc2 += cp * cp;
+        if (FUSED) {
+          tr += stencil(i, j, s, E.G, kap).d;
+          const double bp = E.cunit * node_tri_sum(i, j, s, [&](int t) { return fp[t]; });
+          bf[p] = bp;
+          fs += bp;
+        }
+      }
+      block_sum3(tr, cc2, fs, red);
+      if (tid == 0) {
+        gam = tr / (n * cc2);
+        colsum[E.NI] = fs;
+      }
+      if (FUSED && tid < E.NI) {
+        double v = 0.0;
+        for (int k = 0; k <= s; ++k) v += ft[tid * (s + 1) + k];
+        colsum[tid] = v;
+      }
+    }
+    __syncthreads();
+
+    // ------------------------------------------- fill the register tiles
+    // Lane l of the owner holds rows 16I + (l/16) + 4v of column 16J + l%16.
+    {
+      const double g = gam;
+      const int cl = lane & 15, grp = lane >> 4;
+      const double* A = FUSED ? nullptr : args.Ahat + E.mat0;
+      const double* Bt = FUSED ? nullptr : args.Btil + E.rhs0;
+#pragma unroll
+      for (int sl = 0; sl < S; ++sl) {
+        const int t = NWAVES * sl + wave;
+        V4 v4 = {0, 0, 0, 0};
+        if (t < ntiles) {
+          const int I = tij[t][0], J = tij[t][1];
+          const int q = 16 * J + cl;
+          if (I < nt) {
+            if (FUSED) {
+              int qi = 0, qj = 0;
+              Stencil st = {0, 0, 0, 0, 0, 0, 0, 0};
+              if (q < n) {
+                node_ij(q, s, qi, qj);
+                st = stencil(qi, qj, s, E.G, kap);
+              }
+              const int pE = q + 1, pW = q - 1, pN = q + (s + 1 - qj), pS = q - (s + 2 - qj), pNW = q + (s - qj),
+                        pSE = q - (s + 1 - qj);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int p = 16 * I + grp + 4 * v;
+                double x;
+                if (p < n && q < n) {
+                  x = g * c[p] * c[q];
+                  x += (p == q) ? st.d : 0.0;
+                  x += (p == pE) ? st.e : 0.0;
+                  x += (p == pW) ? st.w : 0.0;
+                  x += (p == pN) ? st.n : 0.0;
+                  x += (p == pS) ? st.so : 0.0;
+                  x += (p == pNW) ? st.nw : 0.0;
+                  x += (p == pSE) ? st.se : 0.0;
+                } else {
+                  x = (p == q) ? 1.0 : 0.0;
+                }
+                v4[v] = x;
+              }
+            } else {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int p = 16 * I + grp + 4 * v;
+                v4[v] = (p < n && q < n) ? A[(int64_t)q * n + p] : (p == q ? 1.0 : 0.0);
+              }
+            }
+          } else {
+            // right-hand-side row: item v holds rhs column a = grp + 4v at node q
+            int qi = 0, qj = 0;
+            if (FUSED && q < n) node_ij(q, s, qi, qj);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int a = grp + 4 * v;
+              double x = 0.0;
+              if (a < r && q < n) {
+                if (FUSED) {
+                  double base = 0.0;
+                  if (a < E.NI) {
+                    const int ef = a / (E.l + 1);
+                    const int kk = face_pos(ef, qi, qj, s);
+                    if (kk >= 0) base = ft[a * (s + 1) + kk];
+                  } else {
+                    base = bf[q];
+                  }
+                  x = base - c[q] * colsum[a] * E.inv_area;
+                } else {
+                  x = Bt[(int64_t)a * n + q];
+                }
+              }
+              v4[v] = x;
+            }
+          }
+        }
+        acc[sl] = v4;
+      }
+    }
+    // diagonal tile 0 (tile number 0, wave 0 slot 0) -> W buffer, factor it
+    if (wave == 0) st_acc<double>(Wt(0), acc[0], lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    double* Lo = (args.Lout && E.mat0 >= 0) ? args.Lout + E.mat0 : nullptr;
+    if (wave == 0) {
+      const int bj = rr::potrf_inv(Wt(0), Lo, n, 0, lane);
+      if (lane == 0 && bj >= 0) bad = bj;
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------- factorisation
+    for (int k = 0; k < nt; ++k) {
+      // panel: L_ik = A_ik W_k^T for the owners of tiles (i, k), i > k;
+      // published to P[i]
+#pragma unroll
+      for (int sl = 0; sl < S; ++sl) {
+        const int t = NWAVES * sl + wave;
+        if (t < ntiles && tij[t][1] == k && tij[t][0] > k) {
+          const int I = tij[t][0];
+          st_acc<double>(Pt(I), acc[sl], lane);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          V4 x = {0, 0, 0, 0};
+#pragma unroll
+          for (int cch = 0; cch < 4; ++cch)
+            x = Mfma<double>::op(ld_rowcol(Pt(I), cch, lane), ld_rowcol(Wt(k), cch, lane), x);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          acc[sl] = x;
+          st_acc<double>(Pt(I), x, lane);
+          if (Lo && I < nt) rr::store_L(Lo, n, I, k, x, lane);
+        }
+      }
+      __syncthreads();
+      // trailing update: C_ij -= L_ik L_jk^T for k < j <= i <= nt; the owner
+      // of tile (k+1, k+1) passes it on to the W buffer and factors it
+      int dslot = -1;
+#pragma unroll
+      for (int sl = 0; sl < S; ++sl) {
+        const int t = NWAVES * sl + wave;
+        if (t < ntiles) {
+          const int I = tij[t][0], J = tij[t][1];
+          if (J > k) {
+            V4 x = acc[sl];
+#pragma unroll
+            for (int cch = 0; cch < 4; ++cch)
+              x = Mfma<double>::op(-ld_rowcol(Pt(I), cch, lane), ld_rowcol(Pt(J), cch, lane), x);
+            acc[sl] = x;
+            if (I == k + 1 && J == k + 1) {
+              st_acc<double>(Wt(k + 1), x, lane);
+              dslot = sl;
+            }
+          }
+        }
+      }
+      if (dslot >= 0) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int bj = rr::potrf_inv(Wt(k + 1), Lo, n, k + 1, lane);
+        if (lane == 0 && bj >= 0 && bad < 0) bad = 16 * (k + 1) + bj;
+      }
+      __syncthreads();
+    }
+
+    // --------------------------------------------- backward solve X = L^{-T} Y
+    // the right-hand-side row (Y^T) moves to P; tile J of P holds Z_J^T
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+      const int t = NWAVES * sl + wave;
+      if (t < ntiles && tij[t][0] == nt) st_acc<double>(Pt(tij[t][1]), acc[sl], lane);
+    }
+    __syncthreads();
+    for (int j = nt - 1; j >= 0; --j) {
+      if (wave == (j & 3)) {
+        V4 x = {0, 0, 0, 0};
+#pragma unroll
+        for (int cch = 0; cch < 4; ++cch)
+          x = Mfma<double>::op(ld_rowcol(Pt(j), cch, lane), ld_colrow(Wt(j), cch, lane), x);   // Z_j^T W_j
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        st_acc<double>(Pt(j), x, lane);
+      }
+      __syncthreads();
+      // Z_i^T -= X_j^T L_ji (i < j) by the owner of tile (j, i): its registers
+      // are the B operand
+#pragma unroll
+      for (int sl = 0; sl < S; ++sl) {
+        const int t = NWAVES * sl + wave;
+        if (t < ntiles && tij[t][0] == j && tij[t][1] < j) {
+          const int I = tij[t][1];
+          V4 z = ld_acc<double>(Pt(I), lane);
+#pragma unroll
+          for (int cch = 0; cch < 4; ++cch) z = Mfma<double>::op(-ld_rowcol(Pt(j), cch, lane), acc[sl][cch], z);
+          st_acc<double>(Pt(I), z, lane);
+        }
+      }
+      __syncthreads();
+    }
+
+    double* X = args.X + E.rhs0;
+    if (bad >= 0) {
+      for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] = __builtin_nan("");
+      if (tid == 0) args.info[e] = bad + 1;
+      if (FUSED && args.M) {
+        for (int idx = tid; idx < NImax * NImax; idx += NTHREADS)
+          args.M[(int64_t)e * NImax * NImax + idx] = __builtin_nan("");
+        if (tid < NImax) {
+          args.E[(int64_t)e * NImax + tid] = __builtin_nan("");
+          args.B[(int64_t)e * NImax + tid] = __builtin_nan("");
+        }
+        if (tid == 0) args.F[e] = __builtin_nan("");
+      }
+      continue;
+    }
+    // zero-mean projection (FP64) and output
+    {
+      const int ca = tid >> 4, cl16 = tid & 15;
+      double v = 0.0;
+      if (ca < r)
+        for (int p = cl16; p < n; p += 16) v += c[p] * Pt(p >> 4)[ca * TST + (p & 15)];
+      v = group16_sum(v);
+      if (cl16 == 0) cx[ca] = v * E.inv_area;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < n * r; idx += NTHREADS) {
+      const int a = idx / n, p = idx - a * n;
+      X[idx] = Pt(p >> 4)[a * TST + (p & 15)] - cx[a];
+    }
+    __syncthreads();
+    if (FUSED && args.M) {
+      // contribution blocks of eq. (6): M = -R^T X_I, E = R^T x_f, B, F
+      const int NI = E.NI, lp1 = E.l + 1, sp1 = s + 1;
+      double* Me = args.M + (int64_t)e * NImax * NImax;
+      for (int idx = tid; idx < NImax * NImax; idx += NTHREADS) {
+        const int a = idx % NImax, bb = idx / NImax;
+        if (a >= NI || bb >= NI) Me[idx] = 0.0;
+      }
+      if (tid < NI * r) {
+        const int a = tid % NI, bb = tid / NI;
+        const int ef = a / lp1;
+        const double* fa = ft + a * sp1;
+        const double* xb = X + (int64_t)bb * n;
+        double v = 0.0;
+        for (int k = 0; k < sp1; ++k) v += fa[k] * xb[face_node(ef, k, s)];
+        if (bb < NI) Me[(int64_t)bb * NImax + a] = -v;
+        else args.E[(int64_t)e * NImax + a] = v;
+      } else if (tid >= 240 && tid < 240 + NImax) {
+        const int a = tid - 240;
+        double v = 0.0;
+        if (a < NI) {
+          for (int k = 0; k < sp1; ++k) v -= ft[a * sp1 + k];
+        } else {
+          args.E[(int64_t)e * NImax + a] = 0.0;
+        }
+        args.B[(int64_t)e * NImax + a] = v;
+      }
+      if (tid == 255) args.F[e] = colsum[E.NI];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launch
+size_t local_rr_lds_bytes(int n_cap, int f_cap, int k_cap) {
+  return sizeof(double) * (2 * (size_t)n_cap + (size_t)f_cap + (size_t)k_cap + (size_t)(2 * rr::NT + 1) * TILE);
+}
+int local_rr_max_nt() { return rr::NT; }
+
+hipError_t launch_local_rr(bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid, hipStream_t st) {
+  const BatchDev d = to_dev(bt);
+  const void* kern = fused ? (const void*)k_local_rr<true> : (const void*)k_local_rr<false>;
+  hipError_t err = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  if (fused) hipLaunchKernelGGL(k_local_rr<true>, dim3(grid), dim3(rr::NTHREADS), lds, st, d, a);
+  else hipLaunchKernelGGL(k_local_rr<false>, dim3(grid), dim3(rr::NTHREADS), lds, st, d, a);
+  return hipGetLastError();
+}
+
+}  // namespace mhm
