@@ -41,6 +41,39 @@ def _flops_per_element(n, r):
     return n ** 3 / 3.0 + 2.0 * n * n * r
 
 
+def _source_hash():
+    """sha256 over the library sources (the same recipe as profiles/*_counters.md)."""
+    import glob
+    import hashlib
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1703_10435_amd", "csrc", "*.hip"))
+                   + glob.glob(os.path.join(ROOT, "paper_1703_10435_amd", "csrc", "*.h"))
+                   + [os.path.join(ROOT, "include", "mhm.h")])
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(profile="k_local_rr_C2_fp64_counters.md"):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE x 2
+    + WRITE_SIZE, calibrated on a plain copy), or None when the kernel sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != _source_hash() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 # ----------------------------------------------------------- CPU baseline leg
 def _oracle_one(args):
     batch_path, e = args
@@ -103,6 +136,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: auto)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", action="store_true", help="also time the three-call and FP32+IR forms")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 (the local problems shard "
@@ -117,6 +152,13 @@ def main():
     if not os.path.exists(abi.LIB_PATH):
         from paper_1703_10435_amd import build as _b
         _b.build()
+    if args.copy_calib:
+        src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     batch = configs.make("C2")
     db = DeviceBatch(batch)
     out = db.alloc_outputs(three_call=True)
@@ -146,8 +188,9 @@ def main():
         "info_nonzero": int(np.sum(info != 0)),
         "kernel_ms": {"mean": kern_ms, "p50": float(np.median(per)), "p99": float(np.percentile(per, 99))},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "k_local<double,LDS,fused>", "flops_per_launch": flops},
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
+                     "kernel": "k_local_rr<fused> (FP64, register-resident tiles)", "flops_per_launch": flops,
+                     "flops_per_element": "n^3/3 + 2 n^2 r (Cholesky + forward/backward solves)"},
     }
 
     if args.extra:

@@ -3,17 +3,19 @@
 //
 // Same steps and results as k_local<double, ...> (a2-a6), organised so that
 // two elements fit on one CU at a time:
-//  * the 16x16 tiles of the lower triangle of Ahat and the right-hand-side
-//    row live in the MFMA accumulators of the four waves (tile number t of
-//    the column-major trapezoid is owned by wave t%4, slot t/4);
+//  * the 16x16 tiles of the lower triangle of Ahat live in the MFMA
+//    accumulators of the four waves (tile number t of the column-major
+//    triangle is owned by wave t%4, slot t/4); the right-hand-side row
+//    (transposed, one tile per 16 nodes) stays in LDS and is eliminated
+//    with the matrix;
 //  * a trailing update C_ij -= L_ik L_jk^T reads its two operands from the
 //    published panel column in LDS and accumulates in registers;
 //  * for f64 the MFMA result layout (lane l holds rows (l/16)+4v of column
 //    l%16) coincides with the B-operand layout (chunk v: rows 4v+(l/16)), so
 //    an L tile held in registers feeds the backward solve directly;
-//  * LDS holds only the current panel column, the inverses W_j of the
-//    diagonal tiles, the right-hand-side row during the backward solve and
-//    the per-element tables (about 53 KB at n = 153).
+//  * LDS holds the current panel column, the inverses W_j of the diagonal
+//    tiles, the right-hand-side row and the per-element tables (about 72 KB
+//    at n = 153).
 #include "mhm_device.h"
 #include "mhm_kernels.h"
 
@@ -24,7 +26,7 @@ namespace rr {
 constexpr int NTHREADS = 256;
 constexpr int NWAVES = 4;
 constexpr int NT = 10;                              // tiles per matrix edge (n <= 160)
-constexpr int NTILES = NT * (NT + 1) / 2 + NT;      // lower triangle + RHS row
+constexpr int NTILES = NT * (NT + 1) / 2;           // lower triangle
 constexpr int S = (NTILES + NWAVES - 1) / NWAVES;   // register slots per wave
 typedef Mfma<double>::v4 V4;
 
@@ -134,7 +136,7 @@ __device__ __forceinline__ int potrf_inv(double* t, double* Lo, int n, int k, in
     const int gj = j & 3, vj = j >> 2;          // lane group / item holding row j
     // row j of the current matrix, seen from column c: a[j][c] (lane (c, gj), item vj)
     const double ajc = __shfl(a[vj], c + 16 * gj, 64);
-    double ajj = readlane_d(ajc, j);            // pivot (lane j holds a[j][j])
+    double ajj = readlane_d(a[vj], j + 16 * gj);   // pivot a[j][j]
     if (!(ajj > 0.0)) {
       if (bad < 0) bad = j;
       ajj = 1.0;
@@ -175,6 +177,17 @@ __device__ __forceinline__ int potrf_inv(double* t, double* Lo, int n, int k, in
   return bad;
 }
 
+// acc[sl] = x for a run-time slot index (each case uses a fixed register set)
+#define RR_SET_SLOT(ACC, SL, X)                                                            \
+  switch (SL) {                                                                           \
+    case 0: ACC[0] = X; break;   case 1: ACC[1] = X; break;   case 2: ACC[2] = X; break;   \
+    case 3: ACC[3] = X; break;   case 4: ACC[4] = X; break;   case 5: ACC[5] = X; break;   \
+    case 6: ACC[6] = X; break;   case 7: ACC[7] = X; break;   case 8: ACC[8] = X; break;   \
+    case 9: ACC[9] = X; break;   case 10: ACC[10] = X; break; case 11: ACC[11] = X; break; \
+    case 12: ACC[12] = X; break; default: ACC[13] = X; break;                               \
+  }
+static_assert(S == 14, "RR_SET_SLOT covers 14 slots");
+
 __device__ __forceinline__ void store_L(double* Lo, int n, int I, int J, const V4& acc, int lane) {
   const int q = 16 * J + (lane & 15);
   if (q >= n) return;
@@ -196,8 +209,8 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
   __shared__ double colsum[16];
   __shared__ double cx[16];
   __shared__ double gam;
-  __shared__ short tij[NTILES][2];     // tile number -> (I, J), column-major over the trapezoid
-  extern __shared__ double dyn[];      // c | bf | ft | kap | P[NT+1] | W[NT]
+  __shared__ short tij[NTILES][2];     // tile number -> (I, J), column-major over the lower triangle
+  extern __shared__ double dyn[];      // c | bf | ft | kap | stencil[8 n] | P[NT] | W[NT] | R[NT]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int NImax = 3 * (b.l_max + 1);
 
@@ -205,10 +218,13 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
   double* bf = c + args.n_cap;
   double* ft = bf + args.n_cap;
   double* kapl = ft + args.f_cap;
-  double* P = kapl + args.k_cap;       // panel column / right-hand-side row
-  double* Wb = P + (NT + 1) * TILE;    // inverses of the diagonal tiles
+  double* stt = kapl + args.k_cap;     // per node: d e w n s nw se, row j (fused)
+  double* P = stt + 8 * args.n_cap;    // panel column L_ik
+  double* Wb = P + NT * TILE;          // inverses of the diagonal tiles
+  double* Rb = Wb + NT * TILE;         // right-hand-side row: tile J holds Z_J^T
   auto Pt = [&](int I) -> double* { return P + I * TILE; };
   auto Wt = [&](int J) -> double* { return Wb + J * TILE; };
+  auto Rt = [&](int J) -> double* { return Rb + J * TILE; };
 
   V4 acc[S];
 
@@ -228,7 +244,7 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
     __syncthreads();
     if (!ok) continue;
     const int s = E.s, n = E.n, r = E.r, nt = E.nt, T2 = s * s;
-    const int ntiles = nt * (nt + 1) / 2 + nt;
+    const int ntiles = nt * (nt + 1) / 2;
     const double* kapg = b.kappa + E.tri0;
     auto kap = [&](int t) -> double { return FUSED ? kapl[t] : kapg[t]; };
 
@@ -245,7 +261,7 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
     if (tid == 0) {
       int t = 0;
       for (int J = 0; J < nt; ++J)
-        for (int I = J; I <= nt; ++I) {
+        for (int I = J; I < nt; ++I) {
           tij[t][0] = (short)I;
           tij[t][1] = (short)J;
           ++t;
@@ -262,7 +278,11 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
         c[p] = cp;
         cc2 += cp * cp;
         if (FUSED) {
-          tr += stencil(i, j, s, E.G, kap).d;
+          const Stencil st = stencil(i, j, s, E.G, kap);
+          double* sp = stt + 8 * p;
+          sp[0] = st.d; sp[1] = st.e; sp[2] = st.w; sp[3] = st.n;
+          sp[4] = st.so; sp[5] = st.nw; sp[6] = st.se; sp[7] = (double)j;
+          tr += st.d;
           const double bp = E.cunit * node_tri_sum(i, j, s, [&](int t) { return fp[t]; });
           bf[p] = bp;
           fs += bp;
@@ -281,162 +301,193 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
     }
     __syncthreads();
 
-    // ------------------------------------------- fill the register tiles
-    // Lane l of the owner holds rows 16I + (l/16) + 4v of column 16J + l%16.
+    // ------------------------------------------------------------ fill
+    // Register tiles: lane l of the owner holds rows 16I + (l/16) + 4v of
+    // column 16J + l%16.  RHS row in LDS: R_J[a][l] = Btilde[16J + l][a].
     {
       const double g = gam;
       const int cl = lane & 15, grp = lane >> 4;
       const double* A = FUSED ? nullptr : args.Ahat + E.mat0;
-      const double* Bt = FUSED ? nullptr : args.Btil + E.rhs0;
-#pragma unroll
+#pragma unroll 1
       for (int sl = 0; sl < S; ++sl) {
         const int t = NWAVES * sl + wave;
         V4 v4 = {0, 0, 0, 0};
         if (t < ntiles) {
           const int I = tij[t][0], J = tij[t][1];
           const int q = 16 * J + cl;
-          if (I < nt) {
-            if (FUSED) {
-              int qi = 0, qj = 0;
-              Stencil st = {0, 0, 0, 0, 0, 0, 0, 0};
-              if (q < n) {
-                node_ij(q, s, qi, qj);
-                st = stencil(qi, qj, s, E.G, kap);
-              }
-              const int pE = q + 1, pW = q - 1, pN = q + (s + 1 - qj), pS = q - (s + 2 - qj), pNW = q + (s - qj),
-                        pSE = q - (s + 1 - qj);
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                const int p = 16 * I + grp + 4 * v;
-                double x;
-                if (p < n && q < n) {
-                  x = g * c[p] * c[q];
-                  x += (p == q) ? st.d : 0.0;
-                  x += (p == pE) ? st.e : 0.0;
-                  x += (p == pW) ? st.w : 0.0;
-                  x += (p == pN) ? st.n : 0.0;
-                  x += (p == pS) ? st.so : 0.0;
-                  x += (p == pNW) ? st.nw : 0.0;
-                  x += (p == pSE) ? st.se : 0.0;
-                } else {
-                  x = (p == q) ? 1.0 : 0.0;
-                }
-                v4[v] = x;
-              }
-            } else {
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                const int p = 16 * I + grp + 4 * v;
-                v4[v] = (p < n && q < n) ? A[(int64_t)q * n + p] : (p == q ? 1.0 : 0.0);
-              }
+          if (FUSED) {
+            // stencil couplings reach |p - q| <= s + 2: only tiles near the diagonal
+            const bool band = 16 * (I - J) <= s + 17;
+            double sd = 0, se_ = 0, sw = 0, sn = 0, ss = 0, snw = 0, sse = 0;
+            int qj = 0;
+            if (band && q < n) {
+              const double* sp = stt + 8 * q;
+              sd = sp[0]; se_ = sp[1]; sw = sp[2]; sn = sp[3]; ss = sp[4]; snw = sp[5]; sse = sp[6];
+              qj = (int)sp[7];
             }
-          } else {
-            // right-hand-side row: item v holds rhs column a = grp + 4v at node q
-            int qi = 0, qj = 0;
-            if (FUSED && q < n) node_ij(q, s, qi, qj);
+            const int pE = q + 1, pW = q - 1, pN = q + (s + 1 - qj), pS = q - (s + 2 - qj), pNW = q + (s - qj),
+                      pSE = q - (s + 1 - qj);
+            const double gcq = q < n ? g * c[q] : 0.0;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int a = grp + 4 * v;
-              double x = 0.0;
-              if (a < r && q < n) {
-                if (FUSED) {
-                  double base = 0.0;
-                  if (a < E.NI) {
-                    const int ef = a / (E.l + 1);
-                    const int kk = face_pos(ef, qi, qj, s);
-                    if (kk >= 0) base = ft[a * (s + 1) + kk];
-                  } else {
-                    base = bf[q];
-                  }
-                  x = base - c[q] * colsum[a] * E.inv_area;
-                } else {
-                  x = Bt[(int64_t)a * n + q];
+              const int p = 16 * I + grp + 4 * v;
+              double x;
+              if (p < n && q < n) {
+                x = gcq * c[p];
+                if (band) {
+                  x += (p == q) ? sd : 0.0;
+                  x += (p == pE) ? se_ : 0.0;
+                  x += (p == pW) ? sw : 0.0;
+                  x += (p == pN) ? sn : 0.0;
+                  x += (p == pS) ? ss : 0.0;
+                  x += (p == pNW) ? snw : 0.0;
+                  x += (p == pSE) ? sse : 0.0;
                 }
+              } else {
+                x = (p == q) ? 1.0 : 0.0;
               }
               v4[v] = x;
             }
-          }
-        }
-        acc[sl] = v4;
-      }
-    }
-    // diagonal tile 0 (tile number 0, wave 0 slot 0) -> W buffer, factor it
-    if (wave == 0) st_acc<double>(Wt(0), acc[0], lane);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    double* Lo = (args.Lout && E.mat0 >= 0) ? args.Lout + E.mat0 : nullptr;
-    if (wave == 0) {
-      const int bj = rr::potrf_inv(Wt(0), Lo, n, 0, lane);
-      if (lane == 0 && bj >= 0) bad = bj;
-    }
-    __syncthreads();
-
-    // ------------------------------------------------------- factorisation
-    for (int k = 0; k < nt; ++k) {
-      // panel: L_ik = A_ik W_k^T for the owners of tiles (i, k), i > k;
-      // published to P[i]
+          } else {
 #pragma unroll
-      for (int sl = 0; sl < S; ++sl) {
-        const int t = NWAVES * sl + wave;
-        if (t < ntiles && tij[t][1] == k && tij[t][0] > k) {
-          const int I = tij[t][0];
-          st_acc<double>(Pt(I), acc[sl], lane);
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          V4 x = {0, 0, 0, 0};
-#pragma unroll
-          for (int cch = 0; cch < 4; ++cch)
-            x = Mfma<double>::op(ld_rowcol(Pt(I), cch, lane), ld_rowcol(Wt(k), cch, lane), x);
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          acc[sl] = x;
-          st_acc<double>(Pt(I), x, lane);
-          if (Lo && I < nt) rr::store_L(Lo, n, I, k, x, lane);
-        }
-      }
-      __syncthreads();
-      // trailing update: C_ij -= L_ik L_jk^T for k < j <= i <= nt; the owner
-      // of tile (k+1, k+1) passes it on to the W buffer and factors it
-      int dslot = -1;
-#pragma unroll
-      for (int sl = 0; sl < S; ++sl) {
-        const int t = NWAVES * sl + wave;
-        if (t < ntiles) {
-          const int I = tij[t][0], J = tij[t][1];
-          if (J > k) {
-            V4 x = acc[sl];
-#pragma unroll
-            for (int cch = 0; cch < 4; ++cch)
-              x = Mfma<double>::op(-ld_rowcol(Pt(I), cch, lane), ld_rowcol(Pt(J), cch, lane), x);
-            acc[sl] = x;
-            if (I == k + 1 && J == k + 1) {
-              st_acc<double>(Wt(k + 1), x, lane);
-              dslot = sl;
+            for (int v = 0; v < 4; ++v) {
+              const int p = 16 * I + grp + 4 * v;
+              v4[v] = (p < n && q < n) ? A[(int64_t)q * n + p] : (p == q ? 1.0 : 0.0);
             }
           }
         }
+        RR_SET_SLOT(acc, sl, v4)
       }
-      if (dslot >= 0) {
+      // right-hand-side row
+      const double* Bt = FUSED ? nullptr : args.Btil + E.rhs0;
+      for (int J = 0; J < nt; ++J) {
+        const int a = tid >> 4, cq = tid & 15, q = 16 * J + cq;
+        double x = 0.0;
+        if (a < r && q < n) {
+          if (FUSED) {
+            int qi, qj;
+            node_ij(q, s, qi, qj);
+            double base = 0.0;
+            if (a < E.NI) {
+              const int ef = a / (E.l + 1);
+              const int kk = face_pos(ef, qi, qj, s);
+              if (kk >= 0) base = ft[a * (s + 1) + kk];
+            } else {
+              base = bf[q];
+            }
+            x = base - c[q] * colsum[a] * E.inv_area;
+          } else {
+            x = Bt[(int64_t)a * n + q];
+          }
+        }
+        Rt(J)[a * TST + cq] = x;
+      }
+    }
+    double* Lo = (!FUSED && args.Lout && E.mat0 >= 0) ? args.Lout + E.mat0 : nullptr;
+    __syncthreads();
+
+    // ------------------------------------------------------- factorisation
+    // Step k = -1 only hands tile (0, 0) to the factor.  The RHS row is
+    // eliminated with the matrix and ends holding Y^T = (L^{-1} Btilde)^T.
+    for (int k = -1; k < nt; ++k) {
+      if (k >= 0) {
+        // panel: L_ik = A_ik W_k^T by the owners of tiles (i, k), i > k,
+        // published to P[i]; Y_k^T = Z_k^T W_k^T by wave k%4
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) {
+          const int t = NWAVES * sl + wave;
+          if (t < ntiles && tij[t][1] == k && tij[t][0] > k) {
+            const int I = tij[t][0];
+            st_acc<double>(Pt(I), acc[sl], lane);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            V4 x = {0, 0, 0, 0};
+#pragma unroll
+            for (int cch = 0; cch < 4; ++cch)
+              x = Mfma<double>::op(ld_rowcol(Pt(I), cch, lane), ld_rowcol(Wt(k), cch, lane), x);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            acc[sl] = x;
+            st_acc<double>(Pt(I), x, lane);
+            if (!FUSED && Lo) rr::store_L(Lo, n, I, k, x, lane);
+          }
+        }
+        if (wave == (k & 3)) {
+          V4 x = {0, 0, 0, 0};
+#pragma unroll
+          for (int cch = 0; cch < 4; ++cch)
+            x = Mfma<double>::op(ld_rowcol(Rt(k), cch, lane), ld_rowcol(Wt(k), cch, lane), x);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          st_acc<double>(Rt(k), x, lane);
+        }
+        __syncthreads();
+      }
+      // trailing update: C_ij -= L_ik L_jk^T for k < j <= i < nt.  The owner
+      // of tile (k+1, k+1) updates it first, hands it to the W buffer and
+      // factors it; then every wave updates its other tiles, two at a time
+      // (the tiles of a step are a suffix of each wave's slots).
+      bool mine = false;
+#pragma unroll
+      for (int sl = 0; sl < S; ++sl) {
+        const int t = NWAVES * sl + wave;
+        if (t < ntiles && tij[t][0] == k + 1 && tij[t][1] == k + 1) {
+          V4 x = acc[sl];
+          if (k >= 0) {
+#pragma unroll
+            for (int cch = 0; cch < 4; ++cch)
+              x = Mfma<double>::op(-ld_rowcol(Pt(k + 1), cch, lane), ld_rowcol(Pt(k + 1), cch, lane), x);
+            acc[sl] = x;
+          }
+          st_acc<double>(Wt(k + 1), x, lane);
+          mine = true;
+        }
+      }
+      if (mine) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const int bj = rr::potrf_inv(Wt(k + 1), Lo, n, k + 1, lane);
         if (lane == 0 && bj >= 0 && bad < 0) bad = 16 * (k + 1) + bj;
       }
+      if (k >= 0) {
+#pragma unroll
+        for (int sl = 0; sl < S; sl += 2) {
+          const int t0 = NWAVES * sl + wave, t1 = t0 + NWAVES;
+          const bool a0 = t0 < ntiles && tij[t0][1] > k && !(tij[t0][0] == k + 1 && tij[t0][1] == k + 1);
+          const bool a1 = sl + 1 < S && t1 < ntiles && tij[t1][1] > k &&
+                          !(tij[t1][0] == k + 1 && tij[t1][1] == k + 1);
+          if (a0 || a1) {
+            const int i0 = a0 ? tij[t0][0] : tij[t1][0], j0 = a0 ? tij[t0][1] : tij[t1][1];
+            const int i1 = a1 ? tij[t1][0] : i0, j1 = a1 ? tij[t1][1] : j0;
+            V4 x0 = acc[sl];
+            V4 x1 = sl + 1 < S ? acc[sl + 1] : acc[sl];
+#pragma unroll
+            for (int cch = 0; cch < 4; ++cch) {
+              x0 = Mfma<double>::op(-ld_rowcol(Pt(i0), cch, lane), ld_rowcol(Pt(j0), cch, lane), x0);
+              x1 = Mfma<double>::op(-ld_rowcol(Pt(i1), cch, lane), ld_rowcol(Pt(j1), cch, lane), x1);
+            }
+            if (a0) acc[sl] = x0;
+            if (sl + 1 < S && a1) acc[sl + 1] = x1;
+          }
+        }
+      }
+      // RHS row: Z_j^T -= Y_k^T L_jk^T, j > k
+      if (k >= 0)
+        for (int j = k + 1 + wave; j < nt; j += NWAVES) {
+          V4 z = ld_acc<double>(Rt(j), lane);
+#pragma unroll
+          for (int cch = 0; cch < 4; ++cch)
+            z = Mfma<double>::op(-ld_rowcol(Rt(k), cch, lane), ld_rowcol(Pt(j), cch, lane), z);
+          st_acc<double>(Rt(j), z, lane);
+        }
       __syncthreads();
     }
 
     // --------------------------------------------- backward solve X = L^{-T} Y
-    // the right-hand-side row (Y^T) moves to P; tile J of P holds Z_J^T
-#pragma unroll
-    for (int sl = 0; sl < S; ++sl) {
-      const int t = NWAVES * sl + wave;
-      if (t < ntiles && tij[t][0] == nt) st_acc<double>(Pt(tij[t][1]), acc[sl], lane);
-    }
-    __syncthreads();
     for (int j = nt - 1; j >= 0; --j) {
       if (wave == (j & 3)) {
         V4 x = {0, 0, 0, 0};
 #pragma unroll
         for (int cch = 0; cch < 4; ++cch)
-          x = Mfma<double>::op(ld_rowcol(Pt(j), cch, lane), ld_colrow(Wt(j), cch, lane), x);   // Z_j^T W_j
+          x = Mfma<double>::op(ld_rowcol(Rt(j), cch, lane), ld_colrow(Wt(j), cch, lane), x);   // Z_j^T W_j
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        st_acc<double>(Pt(j), x, lane);
+        st_acc<double>(Rt(j), x, lane);
       }
       __syncthreads();
       // Z_i^T -= X_j^T L_ji (i < j) by the owner of tile (j, i): its registers
@@ -446,10 +497,10 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
         const int t = NWAVES * sl + wave;
         if (t < ntiles && tij[t][0] == j && tij[t][1] < j) {
           const int I = tij[t][1];
-          V4 z = ld_acc<double>(Pt(I), lane);
+          V4 z = ld_acc<double>(Rt(I), lane);
 #pragma unroll
-          for (int cch = 0; cch < 4; ++cch) z = Mfma<double>::op(-ld_rowcol(Pt(j), cch, lane), acc[sl][cch], z);
-          st_acc<double>(Pt(I), z, lane);
+          for (int cch = 0; cch < 4; ++cch) z = Mfma<double>::op(-ld_rowcol(Rt(j), cch, lane), acc[sl][cch], z);
+          st_acc<double>(Rt(I), z, lane);
         }
       }
       __syncthreads();
@@ -475,14 +526,14 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
       const int ca = tid >> 4, cl16 = tid & 15;
       double v = 0.0;
       if (ca < r)
-        for (int p = cl16; p < n; p += 16) v += c[p] * Pt(p >> 4)[ca * TST + (p & 15)];
+        for (int p = cl16; p < n; p += 16) v += c[p] * Rt(p >> 4)[ca * TST + (p & 15)];
       v = group16_sum(v);
       if (cl16 == 0) cx[ca] = v * E.inv_area;
     }
     __syncthreads();
     for (int idx = tid; idx < n * r; idx += NTHREADS) {
       const int a = idx / n, p = idx - a * n;
-      X[idx] = Pt(p >> 4)[a * TST + (p & 15)] - cx[a];
+      X[idx] = Rt(p >> 4)[a * TST + (p & 15)] - cx[a];
     }
     __syncthreads();
     if (FUSED && args.M) {
@@ -519,7 +570,7 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
 
 // ------------------------------------------------------------------ launch
 size_t local_rr_lds_bytes(int n_cap, int f_cap, int k_cap) {
-  return sizeof(double) * (2 * (size_t)n_cap + (size_t)f_cap + (size_t)k_cap + (size_t)(2 * rr::NT + 1) * TILE);
+  return sizeof(double) * (10 * (size_t)n_cap + (size_t)f_cap + (size_t)k_cap + (size_t)(3 * rr::NT) * TILE);
 }
 int local_rr_max_nt() { return rr::NT; }
 
