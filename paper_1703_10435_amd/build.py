@@ -9,11 +9,12 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmhm.so")
-SOURCES = ["mhm_kernels.hip", "mhm_local_rr.hip", "mhm_api.hip"]
+SOURCES = ["mhm_kernels.hip", "mhm_local_rr.hip", "mhm_local_ll.hip", "mhm_api.hip"]
 ARCH = "gfx950"
 
 
@@ -35,14 +36,18 @@ def compile_flags() -> list:
 
 def build(verbose: bool = False) -> str:
     cc = hipcc()
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [cc, *compile_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+    objs = [os.path.join(CSRC, src.replace(".hip", ".o")) for src in SOURCES]
+
+    def compile_one(i):
+        cmd = [cc, *compile_flags(), "-c", os.path.join(CSRC, SOURCES[i]), "-o", objs[i]]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    # one translation unit per worker; .result() re-raises a failed compile
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as pool:
+        for f in [pool.submit(compile_one, i) for i in range(len(SOURCES))]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -17,6 +17,7 @@ struct mhm_ctx_s {
   int n_cu = 256;
   size_t lds_limit = 160 * 1024;
   bool no_rr = false;          // MHM_NO_RR=1: use the LDS-tile kernel for FP64 too
+  bool no_ll = false;          // MHM_NO_LL=1: right-looking workspace kernel for large elements
   void* ws = nullptr;
   size_t ws_bytes = 0;
   std::string err;
@@ -62,7 +63,7 @@ int grid_for(const mhm_batch* b) { return std::min(b->n_elem, kGridCap); }
 
 // Launch plan of k_local for a batch.
 struct Plan {
-  bool fp32, in_lds, rr;
+  bool fp32, in_lds, rr, ll;
   int nt, tile_cap, n_cap, f_cap, k_cap, grid;
   size_t lds, ws_need;
   int64_t ws_slot;
@@ -80,6 +81,7 @@ Plan plan_local(mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, bool force
   const size_t lds_in = mhm::local_lds_bytes(fp32, true, p.n_cap, p.f_cap, k_lds, p.tile_cap);
   p.in_lds = !force_ws && lds_in + kStaticLds <= c->lds_limit;
   // FP64 elements of up to 16 * local_rr_max_nt() nodes: register-resident kernel
+  p.ll = false;
   p.rr = !fp32 && !force_ws && !c->no_rr && p.nt <= mhm::local_rr_max_nt();
   if (p.rr) {
     p.in_lds = true;
@@ -98,7 +100,9 @@ Plan plan_local(mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, bool force
     p.ws_need = 0;
   } else {
     p.k_cap = 0;
-    p.lds = mhm::local_lds_bytes(fp32, false, p.n_cap, p.f_cap, 0, p.tile_cap);
+    p.ll = !c->no_ll && mhm::local_ll_rows_per_wave(p.nt) > 0;
+    p.lds = p.ll ? mhm::local_ll_lds_bytes(fp32, p.n_cap, p.f_cap)
+                 : mhm::local_lds_bytes(fp32, false, p.n_cap, p.f_cap, 0, p.tile_cap);
     p.grid = std::min(b->n_elem, 2 * c->n_cu);
     p.ws_slot = (int64_t)p.tile_cap * mhm::TILE_WORDS;
     p.ws_need = (size_t)p.grid * (size_t)p.ws_slot * tsz;
@@ -158,6 +162,7 @@ mhm_status run_local(mhm_ctx c, const mhm_batch* b, mhm_prec prec, bool fused, c
   a.f_cap = p.f_cap;
   a.k_cap = p.k_cap;
   hipError_t e = p.rr ? mhm::launch_local_rr(fused, b, a, p.lds, p.grid, c->stream)
+               : p.ll ? mhm::launch_local_ll(fp32, fused, p.nt, b, a, p.lds, p.grid, c->stream)
                       : mhm::launch_local(fp32, p.in_lds, fused, b, a, p.lds, p.grid, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "k_local launch");
   if (fp32) {
@@ -174,7 +179,8 @@ mhm_status run_local(mhm_ctx c, const mhm_batch* b, mhm_prec prec, bool fused, c
     if (!fused) {
       f.M = f.E = f.B = f.F = nullptr;
     }
-    e = mhm::launch_local(false, false, true, b, f, fb.lds, fb.grid, c->stream);
+    e = fb.ll ? mhm::launch_local_ll(false, true, fb.nt, b, f, fb.lds, fb.grid, c->stream)
+              : mhm::launch_local(false, false, true, b, f, fb.lds, fb.grid, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "k_local fallback launch");
   }
   return MHM_OK;
@@ -198,6 +204,8 @@ mhm_status mhm_create(mhm_ctx* out, int device, void* hip_stream) {
   c->device = device;
   const char* nrr = std::getenv("MHM_NO_RR");
   c->no_rr = nrr && nrr[0] == '1';
+  const char* nll = std::getenv("MHM_NO_LL");
+  c->no_ll = nll && nll[0] == '1';
   c->stream = static_cast<hipStream_t>(hip_stream);
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0) c->n_cu = v;

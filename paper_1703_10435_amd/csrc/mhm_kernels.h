@@ -42,6 +42,11 @@ int local_face_cap(const mhm_batch* bt);
 size_t local_rr_lds_bytes(int n_cap, int f_cap, int k_cap);
 int local_rr_max_nt();
 hipError_t launch_local_rr(bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid, hipStream_t st);
+// Left-looking kernel for large elements (tiles in a workspace slot).
+int local_ll_rows_per_wave(int nt);
+size_t local_ll_lds_bytes(bool fp32, int n_cap, int f_cap);
+hipError_t launch_local_ll(bool fp32, bool fused, int nt_max, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
+                           hipStream_t st);
 hipError_t launch_local(bool fp32, bool in_lds, bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
                         hipStream_t st);
 

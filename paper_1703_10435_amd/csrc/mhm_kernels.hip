@@ -11,7 +11,7 @@
 // k_contrib    step a6: the element's blocks of the skeleton system.
 //
 // One workgroup of 256 threads (4 waves of 64) handles one element at a time.
-#include "mhm_device.h"
+#include "mhm_common.h"
 #include "mhm_kernels.h"
 
 namespace mhm {
@@ -19,133 +19,12 @@ namespace mhm {
 constexpr int NTHREADS = 256;
 constexpr int NWAVES = NTHREADS / 64;
 
-// ---------------------------------------------------------------- reductions
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-// sum over the 16 lanes of a lane group (lanes 16g .. 16g+15)
-__device__ __forceinline__ double group16_sum(double v) {
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-// Block-wide sums of three values; every thread gets the results.
-// `red` holds 3*NWAVES doubles.
-__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* red) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  c = wave_sum(c);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    red[w] = a;
-    red[NWAVES + w] = b;
-    red[2 * NWAVES + w] = c;
-  }
-  __syncthreads();
-  a = b = c = 0.0;
-#pragma unroll
-  for (int k = 0; k < NWAVES; ++k) {
-    a += red[k];
-    b += red[NWAVES + k];
-    c += red[2 * NWAVES + k];
-  }
-}
-__device__ __forceinline__ double block_max(double v, double* red) {
-  v = wave_max(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  double t = red[0];
-#pragma unroll
-  for (int k = 1; k < NWAVES; ++k) t = fmax(t, red[k]);
-  return t;
-}
-
-__device__ __forceinline__ double readlane(double x, int lane) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)b, lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float readlane(float x, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
-}
-// 1/sqrt(x): hardware estimate refined by Newton steps y <- y (3 - x y^2) / 2
-__device__ __forceinline__ double rsqrt_t(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * (1.5 - 0.5 * x * y * y);
-  y = y * (1.5 - 0.5 * x * y * y);
-  return y;
-}
-__device__ __forceinline__ float rsqrt_t(float x) {
-  float y = __builtin_amdgcn_rsqf(x);
-  y = y * (1.5f - 0.5f * x * y * y);
-  return y;
-}
-
-// Sum of fn(t) over the sub-triangles t around node (i,j).
-template <class FN>
-__device__ __forceinline__ double node_tri_sum(int i, int j, int s, FN fn) {
-  const int ij = i + j;
-  double a = 0.0;
-  if (ij <= s - 1) a += fn(tri_up(i, j, s));
-  if (i >= 1 && ij <= s) a += fn(tri_up(i - 1, j, s));
-  if (j >= 1 && ij <= s) a += fn(tri_up(i, j - 1, s));
-  if (i >= 1 && j >= 1 && ij <= s) a += fn(tri_dn(i - 1, j - 1, s));
-  if (i >= 1 && ij <= s - 1) a += fn(tri_dn(i - 1, j, s));
-  if (j >= 1 && ij <= s - 1) a += fn(tri_dn(i, j - 1, s));
-  return a;
-}
-
-// -------------------------------------------------------- per-element tables
-// ft[a*(s+1) + k] = R[face node k of face e(a)][a]   (face load table)
-// colsum[a] = 1^T B[:, a]  (face columns from ft, source column from bf)
-__device__ __forceinline__ void face_table(const Elem& E, double* ft) {
-  const int sp1 = E.s + 1, lp1 = E.l + 1;
-  for (int idx = threadIdx.x; idx < E.NI * sp1; idx += NTHREADS) {
-    const int a = idx / sp1, k = idx - a * sp1;
-    const int e = a / lp1, q = a - e * lp1;
-    ft[idx] = face_load(E, e, q, k);
-  }
-}
-__device__ __forceinline__ void face_colsums(const Elem& E, const double* ft, double* colsum) {
-  const int sp1 = E.s + 1;
-  if ((int)threadIdx.x < E.NI) {
-    double v = 0.0;
-    for (int k = 0; k < sp1; ++k) v += ft[threadIdx.x * sp1 + k];
-    colsum[threadIdx.x] = v;
-  }
-}
-
-// Btilde[p][a] from the tables.
-__device__ __forceinline__ double btilde_tab(const Elem& E, const double* ft, const double* bf, const double* c,
-                                             const double* colsum, int a, int p, int i, int j) {
-  double v = 0.0;
-  if (a < E.NI) {
-    const int e = a / (E.l + 1);
-    const int k = face_pos(e, i, j, E.s);
-    if (k >= 0) v = ft[a * (E.s + 1) + k];
-  } else {
-    v = bf[p];
-  }
-  return v - c[p] * colsum[a] * E.inv_area;
-}
-
 // =============================================================== k_assemble
 __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat, double* Btil, double* cout,
                                                         double* area, int32_t* info) {
   __shared__ Elem E;
   __shared__ int ok;
-  __shared__ double red[3 * NWAVES];
+  __shared__ double red[48];
   __shared__ double colsum[16];
   __shared__ double gam;
   extern __shared__ double dyn[];   // kappa[s^2] | c[n] | bf[n] | ft[NI(s+1)]
@@ -223,46 +102,11 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
   }
 }
 
-// ============================================================ contribution
-// M[a][b] = -sum_k R(a,k) X[node(a,k)][b], E[a] = sum_k R(a,k) X[node(a,k)][NI],
-// B[a] = -sum_k R(a,k), F = integral of f (= colsum of the source column).
-// X column-major n x r (already projected); ft the face table.
-__device__ __forceinline__ void contrib_element(const Elem& E, const double* X, const double* ft, double Fval, int NImax,
-                                double* M, double* Ev, double* Bv, double* F, int e) {
-  const int tid = threadIdx.x;
-  const int NI = E.NI, n = E.n, lp1 = E.l + 1, s = E.s, sp1 = s + 1;
-  double* Me = M + (int64_t)e * NImax * NImax;
-  for (int idx = tid; idx < NImax * NImax; idx += NTHREADS) {
-    const int a = idx % NImax, bb = idx / NImax;
-    if (a >= NI || bb >= NI) Me[idx] = 0.0;
-  }
-  if (tid < NI * E.r) {
-    const int a = tid % NI, bb = tid / NI;
-    const int ef = a / lp1;
-    const double* fa = ft + a * sp1;
-    const double* xb = X + (int64_t)bb * n;
-    double v = 0.0;
-    for (int k = 0; k < sp1; ++k) v += fa[k] * xb[face_node(ef, k, s)];
-    if (bb < NI) Me[(int64_t)bb * NImax + a] = -v;
-    else Ev[(int64_t)e * NImax + a] = v;
-  } else if (tid >= 240 && tid < 240 + NImax) {
-    const int a = tid - 240;
-    double v = 0.0;
-    if (a < NI) {
-      for (int k = 0; k < sp1; ++k) v -= ft[a * sp1 + k];
-    } else {
-      Ev[(int64_t)e * NImax + a] = 0.0;
-    }
-    Bv[(int64_t)e * NImax + a] = v;
-  }
-  if (tid == 255) F[e] = Fval;
-}
-
 __global__ void __launch_bounds__(NTHREADS) k_contrib(BatchDev b, const double* X, double* M, double* Ev,
                                                        double* Bv, double* F, const int32_t* info) {
   __shared__ Elem E;
   __shared__ int ok;
-  __shared__ double red[3 * NWAVES];
+  __shared__ double red[48];
   __shared__ double fsum;
   extern __shared__ double ft[];   // NI(s+1)
   const int NImax = 3 * (b.l_max + 1);
@@ -282,96 +126,12 @@ __global__ void __launch_bounds__(NTHREADS) k_contrib(BatchDev b, const double* 
   }
 }
 
-// ================================================================== k_local
-// Diagonal tile: Cholesky factor L and its inverse W = L^{-1}, by one wave.
-// Lane c (and its copies c+16, c+32, c+48) keeps column c of the symmetric
-// tile in registers.  Step j broadcasts column j from lane j with readlane
-// (scalar registers feed the FMAs directly), so a step needs no LDS traffic:
-//   a[r][c] -= a[r][j] a[j][c] / a[j][j]             (r, c > j)
-//   W[j][c] = V[j][c] / sqrt(a[j][j]),  V[r][c] -= L[r][j] W[j][c]   (r > j)
-// Column c is final after step c and is scaled by 1/sqrt(a[c][c]) at the end.
-// The tile's slot receives W; L goes to `Lo` (column-major n x n, may be
-// null).  Returns the first failing column or -1.
-template <typename T>
-__device__ __forceinline__ int potrf_tile(T* t, T* Lo, int n, int k, int lane) {
-  const int c = lane & 15;
-  T col[16], w[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    col[r] = r >= c ? t[r * TST + c] : t[c * TST + r];
-    w[r] = r == c ? T(1) : T(0);
-  }
-  int bad = -1;
-  T myrs = T(1);
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    T ajj = readlane(col[j], j);
-    if (!(ajj > T(0))) {
-      if (bad < 0) bad = j;
-      ajj = T(1);
-    }
-    const T rs = rsqrt_t(ajj);
-    if (c == j) myrs = rs;
-    const T tj = col[j] * (rs * rs);      // a[j][c] / a[j][j]
-    const T wj = w[j] * rs;               // W[j][c]
-    const T wjr = wj * rs;
-    w[j] = wj;
-#pragma unroll
-    for (int r = j + 1; r < 16; ++r) {
-      const T arj = readlane(col[r], j);  // a[r][j]
-      w[r] -= arj * wjr;
-      if (c > j) col[r] -= arj * tj;
-    }
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) t[r * TST + c] = w[r];
-    if (Lo) {
-      const int q = 16 * k + c;
-      if (q < n) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int p = 16 * k + r;
-          if (r >= c && p < n) Lo[(int64_t)q * n + p] = col[r] * myrs;
-        }
-      }
-    }
-  }
-  return bad;
-}
-
-// Store the result tile (rows 16I.., cols 16J..) of L into a column-major
-// n x n matrix (lower triangle only).
-template <typename T>
-__device__ __forceinline__ void store_L(T* Lo, int n, int I, int J, const typename Mfma<T>::v4& acc, int lane) {
-  const int q = 16 * J + (lane & 15);
-  if (q >= n) return;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int p = 16 * I + Mfma<T>::row(lane >> 4, v);
-    if (p < n && p >= q) Lo[(int64_t)q * n + p] = acc[v];
-  }
-}
-
-// Trailing tile t of step k -> (i, j): columns j = k+1 .. nt-1, rows i = j .. nt
-// (row nt is the right-hand-side row).
-__device__ __forceinline__ void trail_ij(int t, int k, int nt, int& i, int& j) {
-  const int m = nt - 1 - k;
-  int jj = 0, rem = t;
-  while (rem >= m - jj + 1) {
-    rem -= m - jj + 1;
-    ++jj;
-  }
-  j = k + 1 + jj;
-  i = j + rem;
-}
-
 template <typename T, bool IN_LDS, bool FUSED>
 __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) {
   typedef typename Mfma<T>::v4 V4;
   __shared__ Elem E;
   __shared__ int ok, bad, conv;
-  __shared__ double red[3 * NWAVES];
+  __shared__ double red[48];
   __shared__ double colsum[16];
   __shared__ double cx[16];          // (c^T X) per column
   __shared__ double gam;
@@ -639,73 +399,9 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
           if (cl16 == 0) cx[ca] = v;
         }
         __syncthreads();
-        // residual R = Btilde - (A X + gamma c (c^T X)) into the RHS tiles (FP32)
-        double rmax[16], xmax[16], bmax[16];
-        double anorm = 0.0;
-#pragma unroll
-        for (int a = 0; a < 16; ++a) rmax[a] = xmax[a] = bmax[a] = 0.0;
-        for (int p = tid; p < 16 * nt; p += NTHREADS) {
-          if (p >= n) {
-            for (int a = 0; a < 16; ++a) tl(nt, p >> 4)[a * TST + (p & 15)] = T(0);
-            continue;
-          }
-          int i, j;
-          node_ij(p, s, i, j);
-          const Stencil st = stencil(i, j, s, E.G, kap);
-          const double cp = c[p];
-          anorm = fmax(anorm, fabs(st.d) + fabs(st.e) + fabs(st.w) + fabs(st.n) + fabs(st.so) + fabs(st.nw) +
-                                   fabs(st.se) + g * cp * E.area);
-          const int pE = p + 1, pW = p - 1, pN = p + (s + 1 - j), pS = p - (s + 2 - j), pNW = p + (s - j),
-                    pSE = p - (s + 1 - j);
-          const bool hE = i + j <= s - 1, hW = i >= 1, hN = i + j <= s - 1, hS = j >= 1, hNW = i >= 1, hSE = j >= 1;
-#pragma unroll
-          for (int a = 0; a < 16; ++a) {
-            double rv = 0.0;
-            if (a < r) {
-              const double* xa = X + (int64_t)a * n;
-              double ax = st.d * xa[p] + g * cp * cx[a];
-              if (hE) ax += st.e * xa[pE];
-              if (hW) ax += st.w * xa[pW];
-              if (hN) ax += st.n * xa[pN];
-              if (hS) ax += st.so * xa[pS];
-              if (hNW) ax += st.nw * xa[pNW];
-              if (hSE) ax += st.se * xa[pSE];
-              const double bv = FUSED ? btilde_tab(E, ft, bf, c, colsum, a, p, i, j) : Btg[(int64_t)a * n + p];
-              rv = bv - ax;
-              rmax[a] = fmax(rmax[a], fabs(rv));
-              xmax[a] = fmax(xmax[a], fabs(xa[p]));
-              bmax[a] = fmax(bmax[a], fabs(bv));
-            }
-            tl(nt, p >> 4)[a * TST + (p & 15)] = (T)rv;
-          }
-        }
-        anorm = block_max(anorm, red);
-#pragma unroll
-        for (int a = 0; a < 16; ++a) {
-          rmax[a] = wave_max(rmax[a]);
-          xmax[a] = wave_max(xmax[a]);
-          bmax[a] = wave_max(bmax[a]);
-        }
-        if (lane == 0)
-          for (int a = 0; a < 16; ++a) {
-            wred[wave][0][a] = rmax[a];
-            wred[wave][1][a] = xmax[a];
-            wred[wave][2][a] = bmax[a];
-          }
-        __syncthreads();
-        if (tid == 0) {
-          bool cv = true;
-          for (int a = 0; a < r; ++a) {
-            double rm = 0, xm = 0, bm = 0;
-            for (int w2 = 0; w2 < NWAVES; ++w2) {
-              rm = fmax(rm, wred[w2][0][a]);
-              xm = fmax(xm, wred[w2][1][a]);
-              bm = fmax(bm, wred[w2][2][a]);
-            }
-            if (!(rm <= args.ir_tol * (anorm * xm + bm))) cv = false;
-          }
-          conv = cv;
-        }
+        const double anorm = ir_residual<T, FUSED>(E, kap, X, c, cx, g, ft, bf, colsum, Btg,
+                                                   [&](int J) -> T* { return tl(nt, J); }, &wred[0][0][0], red);
+        if (tid == 0) conv = ir_converged(&wred[0][0][0], NWAVES, r, anorm, args.ir_tol);
         __syncthreads();
         if (conv || it >= args.max_iters) break;
         forward();
