@@ -220,6 +220,100 @@ __device__ __forceinline__ int potrf_tile(T* t, T* Lo, int n, int k, int lane) {
   return bad;
 }
 
+// Broadcast lane `src` of each 16-lane row to the whole row (DPP row_newbcast).
+__device__ __forceinline__ int row_bcast_i(int x, int src) {
+  switch (src) {
+    case 0: return __builtin_amdgcn_update_dpp(0, x, 0x150, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x151, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, x, 0x152, 0xF, 0xF, false);
+    case 3: return __builtin_amdgcn_update_dpp(0, x, 0x153, 0xF, 0xF, false);
+    case 4: return __builtin_amdgcn_update_dpp(0, x, 0x154, 0xF, 0xF, false);
+    case 5: return __builtin_amdgcn_update_dpp(0, x, 0x155, 0xF, 0xF, false);
+    case 6: return __builtin_amdgcn_update_dpp(0, x, 0x156, 0xF, 0xF, false);
+    case 7: return __builtin_amdgcn_update_dpp(0, x, 0x157, 0xF, 0xF, false);
+    case 8: return __builtin_amdgcn_update_dpp(0, x, 0x158, 0xF, 0xF, false);
+    case 9: return __builtin_amdgcn_update_dpp(0, x, 0x159, 0xF, 0xF, false);
+    case 10: return __builtin_amdgcn_update_dpp(0, x, 0x15A, 0xF, 0xF, false);
+    case 11: return __builtin_amdgcn_update_dpp(0, x, 0x15B, 0xF, 0xF, false);
+    case 12: return __builtin_amdgcn_update_dpp(0, x, 0x15C, 0xF, 0xF, false);
+    case 13: return __builtin_amdgcn_update_dpp(0, x, 0x15D, 0xF, 0xF, false);
+    case 14: return __builtin_amdgcn_update_dpp(0, x, 0x15E, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_update_dpp(0, x, 0x15F, 0xF, 0xF, false);
+  }
+}
+__device__ __forceinline__ double row_bcast(double x, int src) {
+  const long long b = __double_as_longlong(x);
+  const int lo = row_bcast_i((int)b, src);
+  const int hi = row_bcast_i((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float row_bcast(float x, int src) {
+  return __int_as_float(row_bcast_i(__float_as_int(x), src));
+}
+
+// Cholesky factor and inverse of one 16x16 tile stored (lower triangle) at
+// `t`, by one wave, holding only 4 + 4 values per lane.  Lanes are split
+// 4 x 16: lane (c, g) = c + 16 g holds rows g + 4v (v = 0..3) of column c.
+// Step j takes the pivot from its lane, the pivot row across the 16-lane rows
+// (lane shuffle) and the pivot column inside each row (DPP broadcast).
+// Writes W = L^{-1} back to `t` (full tile, zero above the diagonal) and the
+// lower triangle of L to Lo (column-major n x n, may be null); returns the
+// first non-positive pivot (or -1).
+template <typename T>
+__device__ __forceinline__ int potrf_c(T* t, T* Lo, int n, int k, int lane) {
+  const int c = lane & 15, g = lane >> 4;
+  T a[4], w[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = g + 4 * v;
+    a[v] = r >= c ? t[r * TST + c] : t[c * TST + r];
+    w[v] = r == c ? T(1) : T(0);
+  }
+  int bad = -1;
+  T myrs = T(1);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int gj = j & 3, vj = j >> 2;          // lane group / item holding row j
+    const T ajc = __shfl(a[vj], c + 16 * gj, 64);    // a[j][c]
+    T ajj = readlane(a[vj], j + 16 * gj);           // a[j][j]
+    if (!(ajj > T(0))) {
+      if (bad < 0) bad = j;
+      ajj = T(1);
+    }
+    const T rs = rsqrt_t(ajj);
+    if (c == j) myrs = rs;
+    const T inv = rs * rs;
+    const T wjc = __shfl(w[vj], c + 16 * gj, 64) * rs;   // W[j][c]
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = g + 4 * v;
+      const T arj = row_bcast(a[v], j);      // a[r][j]
+      if (r > j) {
+        w[v] -= arj * rs * wjc;
+        if (c > j) a[v] -= arj * ajc * inv;
+      } else if (r == j) {
+        w[v] = wjc;
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = g + 4 * v;
+    t[r * TST + c] = w[v];
+  }
+  if (Lo) {
+    const int q = 16 * k + c;
+    if (q < n) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = g + 4 * v, p = 16 * k + r;
+        if (r >= c && p < n) Lo[(int64_t)q * n + p] = a[v] * myrs;
+      }
+    }
+  }
+  return bad;
+}
+
 // Store the result tile (rows 16I.., cols 16J..) of L into a column-major
 // n x n matrix (lower triangle only).
 template <typename T>

@@ -27,14 +27,120 @@ namespace ll {
 constexpr int NW = 8;
 constexpr int NTHREADS = 64 * NW;
 
-// acc[idx / PW][idx % PW] = v for a run-time idx (a chain of compares over
-// fixed register slots)
-template <int K, int N, int PW, class A, class V>
-__device__ __forceinline__ void set_slot(A& acc, int idx, const V& v) {
-  if constexpr (K < N) {
-    if (idx == K) acc[K / PW][K % PW] = v;
-    else set_slot<K + 1, N, PW>(acc, idx, v);
+// One block triangular sweep over the right-hand-side tile row of the factor
+// (tiles tl(nt, i) hold Z_i^T, 16 right-hand sides by 16 nodes; the diagonal
+// tiles tl(j, j) hold W_j = L_jj^{-1}):
+//   backward (BACK):  X_j^T = Z_j^T W_j,    Z_i^T -= X_j^T L_ji     (i < j)
+//   forward:          Y_j^T = Z_j^T W_j^T,  Z_i^T -= Y_j^T L_ij^T   (i > j)
+// Wave w keeps tiles i = w + NW ri in registers.  In the step for block
+// column j, after one barrier, every wave applies the published solution
+// tile of column j to its own tiles; the owner of the next column solves that
+// tile right after its last update and publishes it (LDS double buffer xb).
+// The L operands of a step are loaded one or two steps ahead, so their
+// global-memory latency overlaps the chain of column solves.  Every register
+// slot is addressed statically.
+template <typename T, int RPW, bool BACK, class TL>
+__device__ __forceinline__ void sweep(TL tl, int nt, T* xb, T* scr, int wave, int lane) {
+  typedef typename Mfma<T>::v4 V4;
+  constexpr int NB = RPW * (int)sizeof(T) <= 40 ? 2 : 1;   // operand buffers
+  V4 z[RPW];
+#pragma unroll
+  for (int ri = 0; ri < RPW; ++ri) {
+    const int i = wave + NW * ri;
+    if (i < nt) z[ri] = ld_acc<T>(tl(nt, i), lane);
+    else z[ri] = V4{0, 0, 0, 0};
   }
+  auto colj = [&](int st) { return BACK ? nt - 1 - st : st; };
+  auto upd = [&](int i, int j) { return BACK ? i < j : (i > j && i < nt); };
+  auto ld_w = [&](int j, T (&w)[4]) {
+    const T* W = tl(j, j);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w[c] = BACK ? ld_colrow(W, c, lane) : ld_rowcol(W, c, lane);
+  };
+  // operands of step st: L tiles applied to the own tiles, and W of the
+  // column solved during that step (owner only)
+  auto fetch = [&](int st, T (&b)[RPW][4], T (&w)[4]) {
+    if (st >= nt) return;
+    const int j = colj(st);
+#pragma unroll
+    for (int ri = 0; ri < RPW; ++ri) {
+      const int i = wave + NW * ri;
+      if (upd(i, j)) {
+        const T* L = BACK ? tl(j, i) : tl(i, j);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[ri][c] = BACK ? ld_colrow(L, c, lane) : ld_rowcol(L, c, lane);
+      }
+    }
+    if (st + 1 < nt && wave == colj(st + 1) % NW) ld_w(colj(st + 1), w);
+  };
+  auto solve_tile = [&](V4& zr, const T (&w)[4], T* dst) {
+    st_acc<T>(scr, zr, lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    V4 x = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x = Mfma<T>::op(ld_rowcol(scr, c, lane), w[c], x);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    zr = x;
+    st_acc<T>(dst, x, lane);
+  };
+  T bo[NB][RPW][4];
+  T wo[NB][4];
+  {
+    const int j = colj(0);
+    T w0[4];
+    if (wave == j % NW) ld_w(j, w0);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) fetch(q, bo[q], wo[q]);
+#pragma unroll
+    for (int ri = 0; ri < RPW; ++ri)
+      if (wave + NW * ri == j) solve_tile(z[ri], w0, xb);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+  }
+  auto step_once = [&](int st, const T (&b)[RPW][4], const T (&w)[4]) {
+    const int j = colj(st);
+    const int jn = st + 1 < nt ? colj(st + 1) : -1;
+    const T* xj = xb + (st & 1) * TILE;
+    T* xn = xb + ((st + 1) & 1) * TILE;
+    T a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = -ld_rowcol(xj, c, lane);
+#pragma unroll
+    for (int ri = 0; ri < RPW; ++ri) {
+      const int i = wave + NW * ri;
+      if (upd(i, j)) {
+        V4 x = z[ri];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x = Mfma<T>::op(a[c], b[ri][c], x);
+        z[ri] = x;
+        if (i == jn) solve_tile(z[ri], w, xn);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+  };
+  if constexpr (NB == 2) {
+    for (int st = 0; st < nt; st += 2) {
+      step_once(st, bo[0], wo[0]);
+      fetch(st + 2, bo[0], wo[0]);
+      if (st + 1 < nt) {
+        step_once(st + 1, bo[1], wo[1]);
+        fetch(st + 3, bo[1], wo[1]);
+      }
+    }
+  } else {
+    for (int st = 0; st < nt; ++st) {
+      step_once(st, bo[0], wo[0]);
+      fetch(st + 1, bo[0], wo[0]);
+    }
+  }
+#pragma unroll
+  for (int ri = 0; ri < RPW; ++ri) {
+    const int i = wave + NW * ri;
+    if (i < nt) st_acc<T>(tl(nt, i), z[ri], lane);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __syncthreads();
 }
 }  // namespace ll
 
@@ -186,95 +292,160 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
     for (int j0 = 0; j0 < nt; j0 += PW) {
       const int pw = nt - j0 < PW ? nt - j0 : PW;
       V4 acc[RPW][PW];
-      // (a) initial panel (one copy of the tile code; each result goes to its
-      // fixed register slot through a compile-time dispatch chain)
-#pragma unroll 1
-      for (int t = 0; t < RPW * PW; ++t) {
-        const int ri = t / PW, jj = t - ri * PW;
+      // (a) initial panel: rows are unrolled, the PW columns of a row run in
+      // a loop whose result is moved into its register slot by selects
+      // (a branch chain here would leave the panel array in scratch memory)
+#pragma unroll
+      for (int ri = 0; ri < RPW; ++ri) {
         const int i = j0 + wave + NW * ri;
-        V4 v = {0, 0, 0, 0};
-        if (i <= nt && jj < pw && (i == nt || i >= j0 + jj)) v = init_tile(i, j0 + jj);
-        ll::set_slot<0, RPW * PW, PW>(acc, t, v);
-      }
-      // (b) earlier tile columns
-      for (int m = 0; m < j0; ++m) {
-        T* st = stage + (m & 1) * PW * TILE;
-        for (int idx = tid; idx < pw * TILE; idx += NTHREADS) st[idx] = tl(j0 + idx / TILE, m)[idx % TILE];
-        __syncthreads();
 #pragma unroll
-        for (int ri = 0; ri < RPW; ++ri) {
-          const int i = j0 + wave + NW * ri;
-          if (i <= nt) {
-            const T* L = tl(i, m);
-            T a[4];
+        for (int k = 0; k < PW; ++k) acc[ri][k] = V4{0, 0, 0, 0};
+        if (i <= nt) {
+#pragma unroll 1
+          for (int jj = 0; jj < pw; ++jj) {
+            if (i == nt || i >= j0 + jj) {
+              const V4 v = init_tile(i, j0 + jj);
 #pragma unroll
-            for (int cch = 0; cch < 4; ++cch) a[cch] = -ld_rowcol(L, cch, lane);
-#pragma unroll
-            for (int jj = 0; jj < PW; ++jj) {
-              if (jj < pw && (i == nt || i >= j0 + jj)) {
-                V4 x = acc[ri][jj];
-#pragma unroll
-                for (int cch = 0; cch < 4; ++cch) x = Mfma<T>::op(a[cch], ld_rowcol(st + jj * TILE, cch, lane), x);
-                acc[ri][jj] = x;
-              }
+              for (int k = 0; k < PW; ++k) acc[ri][k] = jj == k ? v : acc[ri][k];
             }
           }
         }
       }
-      // (c) factor the panel
-#pragma unroll
-      for (int jj = 0; jj < PW; ++jj) {
-        if (jj < pw) {
-          const int col = j0 + jj;
-          // diagonal tile (row col is local row jj: wave jj, slot 0)
-          if (wave == jj) {
-            st_acc<T>(Wt, acc[0][jj], lane);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            const int bj = potrf_tile<T>(Wt, Lo, n, col, lane);
-            if (lane == 0 && bj >= 0 && bad < 0) bad = 16 * col + bj;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            T* dst = tl(col, col);
-            for (int idx = lane; idx < TILE; idx += 64) dst[idx] = Wt[idx];
-          }
-          __syncthreads();
-          // panel solve L_i,col = C_i,col W^T for the rows below
+      // (b) earlier tile columns.  The operands of column m + 1 (A operands
+      // in registers, B tiles for the LDS stage) are loaded while the MFMAs
+      // of column m run; one barrier per column (stage buffers alternate).
+      if (j0 > 0) {
+        constexpr int SPT = (PW * TILE + NTHREADS - 1) / NTHREADS;
+        constexpr int NB = RPW <= 5 ? 2 : 1;   // operand buffers (register budget)
+        T ab[NB][RPW][4];
+        T sb[NB][SPT];
+        auto fetch = [&](int m, T (&a)[RPW][4], T (&sv)[SPT]) {
+          if (m >= j0) return;
 #pragma unroll
           for (int ri = 0; ri < RPW; ++ri) {
             const int i = j0 + wave + NW * ri;
-            if (i > col && i <= nt) {
-              st_acc<T>(scr, acc[ri][jj], lane);
-              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-              V4 x = {0, 0, 0, 0};
+            if (i <= nt) {
+              const T* L = tl(i, m);
 #pragma unroll
-              for (int cch = 0; cch < 4; ++cch) x = Mfma<T>::op(ld_rowcol(scr, cch, lane), ld_rowcol(Wt, cch, lane), x);
-              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-              acc[ri][jj] = x;
-              st_acc<T>(tl(i, col), x, lane);
-              if (Lo && i < nt) store_L<T>(Lo, n, i, col, x, lane);
-              if (i < j0 + pw) st_acc<T>(pub + (i - j0) * TILE, x, lane);
+              for (int cch = 0; cch < 4; ++cch) a[ri][cch] = ld_rowcol(L, cch, lane);
             }
           }
+#pragma unroll
+          for (int q = 0; q < SPT; ++q) {
+            const int idx = tid + q * NTHREADS;
+            if (idx < pw * TILE) sv[q] = tl(j0 + idx / TILE, m)[idx % TILE];
+          }
+        };
+        auto apply = [&](int m, const T (&a)[RPW][4], const T (&sv)[SPT]) {
+          T* st = stage + (m & 1) * PW * TILE;
+#pragma unroll
+          for (int q = 0; q < SPT; ++q) {
+            const int idx = tid + q * NTHREADS;
+            if (idx < pw * TILE) st[idx] = sv[q];
+          }
           __syncthreads();
-          // in-panel update C_i,j -= L_i,col L_j,col^T for the later panel columns
 #pragma unroll
           for (int ri = 0; ri < RPW; ++ri) {
             const int i = j0 + wave + NW * ri;
-            if (i > col && i <= nt && jj + 1 < pw) {
-              st_acc<T>(scr, acc[ri][jj], lane);
-              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-              T a[4];
+            if (i <= nt) {
 #pragma unroll
-              for (int cch = 0; cch < 4; ++cch) a[cch] = -ld_rowcol(scr, cch, lane);
+              for (int jj = 0; jj < PW; ++jj) {
+                if (jj < pw && (i == nt || i >= j0 + jj)) {
+                  V4 x = acc[ri][jj];
 #pragma unroll
-              for (int j2 = jj + 1; j2 < PW; ++j2) {
-                if (j2 < pw && (i == nt || i >= j0 + j2)) {
-                  V4 x = acc[ri][j2];
-#pragma unroll
-                  for (int cch = 0; cch < 4; ++cch) x = Mfma<T>::op(a[cch], ld_rowcol(pub + j2 * TILE, cch, lane), x);
-                  acc[ri][j2] = x;
+                  for (int cch = 0; cch < 4; ++cch)
+                    x = Mfma<T>::op(-a[ri][cch], ld_rowcol(st + jj * TILE, cch, lane), x);
+                  acc[ri][jj] = x;
                 }
               }
-              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+          }
+        };
+        if constexpr (NB == 2) {
+          fetch(0, ab[0], sb[0]);
+          fetch(1, ab[1], sb[1]);
+          for (int m = 0; m < j0; m += 2) {
+            apply(m, ab[0], sb[0]);
+            fetch(m + 2, ab[0], sb[0]);
+            if (m + 1 < j0) {
+              apply(m + 1, ab[1], sb[1]);
+              fetch(m + 3, ab[1], sb[1]);
+            }
+          }
+        } else {
+          for (int m = 0; m < j0; ++m) {
+            fetch(m, ab[0], sb[0]);
+            apply(m, ab[0], sb[0]);
+          }
+        }
+      }
+      // (c) factor the panel, one column at a time (run-time loop; the tile
+      // code that touches the register panel matches the column statically)
+#pragma unroll 1
+      for (int jj = 0; jj < pw; ++jj) {
+        const int col = j0 + jj;
+        // diagonal tile (row col is local row jj: wave jj, slot 0)
+        if (wave == jj) {
+#pragma unroll
+          for (int k = 0; k < PW; ++k)
+            if (k == jj) st_acc<T>(Wt, acc[0][k], lane);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          const int bj = potrf_c<T>(Wt, Lo, n, col, lane);
+          if (lane == 0 && bj >= 0 && bad < 0) bad = 16 * col + bj;
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          T* dst = tl(col, col);
+          for (int idx = lane; idx < TILE; idx += 64) dst[idx] = Wt[idx];
+        }
+        __syncthreads();
+        // panel solve L_i,col = C_i,col W^T for the rows below, then the
+        // in-panel update C_i,j -= L_i,col L_j,col^T of the later columns
+#pragma unroll
+        for (int k = 0; k < PW; ++k) {
+          if (k == jj) {
+#pragma unroll
+            for (int ri = 0; ri < RPW; ++ri) {
+              const int i = j0 + wave + NW * ri;
+              if (i > col && i <= nt) {
+                st_acc<T>(scr, acc[ri][k], lane);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                V4 x = {0, 0, 0, 0};
+#pragma unroll
+                for (int cch = 0; cch < 4; ++cch)
+                  x = Mfma<T>::op(ld_rowcol(scr, cch, lane), ld_rowcol(Wt, cch, lane), x);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                acc[ri][k] = x;
+                st_acc<T>(tl(i, col), x, lane);
+                if (Lo && i < nt) store_L<T>(Lo, n, i, col, x, lane);
+                if (i < j0 + pw) st_acc<T>(pub + (i - j0) * TILE, x, lane);
+              }
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PW - 1; ++k) {
+          if (k == jj && jj + 1 < pw) {
+#pragma unroll
+            for (int ri = 0; ri < RPW; ++ri) {
+              const int i = j0 + wave + NW * ri;
+              if (i > col && i <= nt) {
+                st_acc<T>(scr, acc[ri][k], lane);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                T a[4];
+#pragma unroll
+                for (int cch = 0; cch < 4; ++cch) a[cch] = -ld_rowcol(scr, cch, lane);
+#pragma unroll
+                for (int j2 = k + 1; j2 < PW; ++j2) {
+                  if (j2 < pw && (i == nt || i >= j0 + j2)) {
+                    V4 x = acc[ri][j2];
+#pragma unroll
+                    for (int cch = 0; cch < 4; ++cch) x = Mfma<T>::op(a[cch], ld_rowcol(pub + j2 * TILE, cch, lane), x);
+                    acc[ri][j2] = x;
+                  }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+              }
             }
           }
         }
@@ -284,44 +455,9 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
     }
 
     // ------------------------------------------------ solves on the RHS row
-    auto backward = [&]() {
-      for (int j = nt - 1; j >= 0; --j) {   // X = L^{-T} Y
-        if (wave == j % NW) {
-          V4 x = {0, 0, 0, 0};
-          mma_add_nn<T>(x, tl(nt, j), tl(j, j), lane);   // X_j^T = Z_j^T W_j
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          st_acc<T>(tl(nt, j), x, lane);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __syncthreads();
-        for (int i = wave; i < j; i += NW) {
-          V4 z = ld_acc<T>(tl(nt, i), lane);
-          mma_sub_nn<T>(z, tl(nt, j), tl(j, i), lane);   // Z_i^T -= X_j^T L_ji
-          st_acc<T>(tl(nt, i), z, lane);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __syncthreads();
-      }
-    };
-    auto forward = [&]() {
-      for (int j = 0; j < nt; ++j) {        // Y = L^{-1} Z
-        if (wave == j % NW) {
-          V4 x = {0, 0, 0, 0};
-          mma_add_nt<T>(x, tl(nt, j), tl(j, j), lane);   // Y_j^T = Z_j^T W_j^T
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          st_acc<T>(tl(nt, j), x, lane);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __syncthreads();
-        for (int i = j + 1 + wave; i < nt; i += NW) {
-          V4 z = ld_acc<T>(tl(nt, i), lane);
-          mma_sub_nt<T>(z, tl(nt, j), tl(i, j), lane);   // Z_i^T -= Y_j^T L_ij^T
-          st_acc<T>(tl(nt, i), z, lane);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __syncthreads();
-      }
-    };
+    T* xb = stage;   // two published solution tiles (the staging area is free here)
+    auto backward = [&]() { ll::sweep<T, RPW, true>(tl, nt, xb, scr, wave, lane); };
+    auto forward = [&]() { ll::sweep<T, RPW, false>(tl, nt, xb, scr, wave, lane); };
     backward();
     const bool failed = bad >= 0;
     double* X = args.X + E.rhs0;
