@@ -49,9 +49,10 @@
  *      0   success
  *      k>0 non-positive pivot at column k (1-based) of Ahat: the element's
  *          outputs are filled with NaN (LAPACK potrf convention)
- *     -1   the FP32 factorisation or its FP64 refinement did not reach the
- *          tolerance in max_iters steps; the element was recomputed with the
- *          FP64 path and its outputs are valid
+ *     -1   the FP32 factorisation with FP64 refinement did not reach the
+ *          tolerance (within max_iters steps, or its observed contraction
+ *          said it would not); the element was recomputed with the FP64
+ *          path and its outputs are valid
  *     -2   the element's descriptor is inconsistent (s or l out of range,
  *          offsets that disagree with s and l or exceed the *_total sizes,
  *          sign/flip flags out of range, a non-positive area); nothing of
@@ -72,6 +73,7 @@ extern "C" {
 #define MHM_L_LIMIT 4    /* largest l per element (r <= 16) */
 
 typedef struct mhm_ctx_s* mhm_ctx;
+typedef struct mhm_graph_s* mhm_graph;
 
 typedef enum {
   MHM_OK = 0,
@@ -89,10 +91,13 @@ typedef enum {
 /* A ragged batch of local problems p_t = (K_t, {F_t}) (Algorithm 1). */
 typedef struct {
   int32_t n_elem;          /* host: number of elements (0 is allowed)          */
-  int32_t s_max;           /* host: bound on s over the batch (launch choice)  */
+  int32_t s_max;           /* host: upper bound on s over the batch            */
   int32_t l_max;           /* host: bound on l; contribution blocks are padded
                               to NImax = 3(l_max+1)                             */
-  int32_t reserved;
+  int32_t s_min;           /* host: lower bound on s over the batch (0: unknown,
+                              taken as 1).  When [s_min, s_max] spans several
+                              size classes the batch is binned on the device
+                              and every class gets its own launch           */
   const int32_t* s;        /* [n_elem] subdivisions, 1..MHM_S_LIMIT            */
   const int32_t* l;        /* [n_elem] face degree, 0..MHM_L_LIMIT             */
   const double* vert;      /* [n_elem*6] x0 y0 x1 y1 x2 y2, counter-clockwise  */
@@ -140,8 +145,10 @@ mhm_status mhm_local_assemble(mhm_ctx ctx, const mhm_batch* batch,
  * vectors), then project X to zero mean.
  *   Ahat_io  in: Ahat from mhm_local_assemble.  out: the lower triangle of
  *            L (MHM_FP64), or the FP32 L, column-major, in the first n*n
- *            floats of the element's slot (MHM_FP32_IR; FP64 L for elements
- *            that report info == -1).  The strict upper part is unspecified.
+ *            floats of the element's slot (MHM_FP32_IR; for elements that
+ *            report info == -1 this FP32 L is the one whose refinement did
+ *            not converge, and X comes from the FP64 recomputation).  The
+ *            strict upper part is unspecified.
  *   Btilde   in: compatible right-hand sides.
  *   X        out: n x r solutions (FP64).
  *   ir_iters out (may be NULL): refinement steps taken per element.
@@ -165,6 +172,39 @@ mhm_status mhm_skeleton_contrib(mhm_ctx ctx, const mhm_batch* batch, const doubl
 mhm_status mhm_local_batch_run(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec,
                                double* X, double* M, double* E, double* B, double* F,
                                int32_t* info, int32_t* ir_iters, int max_iters);
+
+/* Batching: choose, per size class present in the batch, the kernel family
+ * and panel width ("tile shape": register-resident tiles, LDS tiles,
+ * left-looking panels of 2 or 4 tile columns, or the right-looking
+ * workspace kernel) by timing every feasible one on up to 4 x (compute
+ * units) elements of that class, keep the fastest in the context for later
+ * mhm_local_batch_run and mhm_graph_create calls, then run the batch once
+ * (the outputs are those of mhm_local_batch_run).  Synchronises the stream;
+ * not for use under stream capture.  Method unchanged (Section 3, Algorithm
+ * 1): only the launch configuration is chosen. */
+mhm_status mhm_autotune(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec,
+                        double* X, double* M, double* E, double* B, double* F,
+                        int32_t* info, int32_t* ir_iters, int max_iters);
+/* The last autotuning's measurements as a JSON array (one object per class
+ * and candidate: s_max, prec, kernel, pw, ms, elements).  Copies at most
+ * len-1 characters plus a terminating zero into buf; returns the full size
+ * including the zero. */
+size_t mhm_tune_report(mhm_ctx ctx, char* buf, size_t len);
+
+/* Batching: capture the whole mhm_local_batch_run of this batch (binning,
+ * one persistent launch per size class on forked streams, FP64 fallback
+ * passes) into a HIP graph that owns its own workspace.  The batch arrays
+ * and outputs are bound at capture; their contents may change between
+ * launches, their addresses and the host fields of the batch may not.
+ * mhm_graph_launch enqueues one replay on the context's stream.  Contract
+ * and results as mhm_local_batch_run. */
+mhm_status mhm_graph_create(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec,
+                            double* X, double* M, double* E, double* B, double* F,
+                            int32_t* info, int32_t* ir_iters, int max_iters,
+                            mhm_graph* graph);
+mhm_status mhm_graph_launch(mhm_graph graph);
+/* Waits for the context's stream, then frees the graph and its workspace. */
+mhm_status mhm_graph_destroy(mhm_graph graph);
 
 #ifdef __cplusplus
 }

@@ -21,13 +21,14 @@ INFO_OK, INFO_IR_FALLBACK, INFO_BAD_DESC, INFO_TOO_LARGE = 0, -1, -2, -3
 EXPORTS = (
     "mhm_create", "mhm_destroy", "mhm_set_stream", "mhm_last_error", "mhm_sync", "mhm_workspace_bytes",
     "mhm_local_assemble", "mhm_local_factor_solve", "mhm_skeleton_contrib", "mhm_local_batch_run",
+    "mhm_autotune", "mhm_tune_report", "mhm_graph_create", "mhm_graph_launch", "mhm_graph_destroy",
 )
 
 
 class mhm_batch(ctypes.Structure):
     _fields_ = [
         ("n_elem", ctypes.c_int32), ("s_max", ctypes.c_int32), ("l_max", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("s_min", ctypes.c_int32),
         ("s", ctypes.c_void_p), ("l", ctypes.c_void_p), ("vert", ctypes.c_void_p),
         ("sigma", ctypes.c_void_p), ("flip", ctypes.c_void_p), ("kappa", ctypes.c_void_p),
         ("f", ctypes.c_void_p), ("tri_off", ctypes.c_void_p), ("mat_off", ctypes.c_void_p),
@@ -67,6 +68,11 @@ def load(path: str = LIB_PATH):
         "mhm_local_factor_solve": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, i32]),
         "mhm_skeleton_contrib": (i32, [vp, bp, vp, vp, vp, vp, vp, vp]),
         "mhm_local_batch_run": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, i32]),
+        "mhm_autotune": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, i32]),
+        "mhm_tune_report": (ctypes.c_size_t, [vp, ctypes.c_char_p, ctypes.c_size_t]),
+        "mhm_graph_create": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(vp)]),
+        "mhm_graph_launch": (i32, [vp]),
+        "mhm_graph_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -139,3 +145,42 @@ class Context:
         self._check(self.lib.mhm_local_batch_run(self.h, ctypes.byref(batch.desc), prec, _ptr(X), _ptr(M),
                                                  _ptr(E), _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters),
                                                  max_iters))
+
+    def autotune(self, batch, prec, X, M, E, B, F, info, ir_iters=None, max_iters: int = 10):
+        self._check(self.lib.mhm_autotune(self.h, ctypes.byref(batch.desc), prec, _ptr(X), _ptr(M), _ptr(E),
+                                          _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters), max_iters))
+
+    def tune_report(self) -> str:
+        n = int(self.lib.mhm_tune_report(self.h, None, 0))
+        buf = ctypes.create_string_buffer(max(n, 1))
+        self.lib.mhm_tune_report(self.h, buf, n)
+        return buf.value.decode()
+
+    def graph_create(self, batch, prec, X, M, E, B, F, info, ir_iters=None, max_iters: int = 10) -> "Graph":
+        g = ctypes.c_void_p()
+        self._check(self.lib.mhm_graph_create(self.h, ctypes.byref(batch.desc), prec, _ptr(X), _ptr(M), _ptr(E),
+                                              _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters), max_iters,
+                                              ctypes.byref(g)))
+        return Graph(self, g)
+
+
+class Graph:
+    """An ``mhm_graph``: one captured mhm_local_batch_run, replayed by launch()."""
+
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self.h = h
+
+    def launch(self):
+        self.ctx._check(self.ctx.lib.mhm_graph_launch(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.mhm_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -90,6 +90,7 @@ class DeviceBatch:
         self.n = lay["n"]
         self.r = lay["r"]
         self.s_max = int(s.max()) if E else 1
+        self.s_min = int(s.min()) if E else 1
         self.l_max = int(l.max()) if E else 0
         self.NImax = 3 * (self.l_max + 1)
         self.mat_off = lay["mat_off"]
@@ -109,6 +110,7 @@ class DeviceBatch:
         d = abi.mhm_batch()
         d.n_elem = E
         d.s_max = self.s_max
+        d.s_min = self.s_min
         d.l_max = self.l_max
         for k, v in self.t.items():
             setattr(d, k, v.data_ptr() if v.numel() else None)

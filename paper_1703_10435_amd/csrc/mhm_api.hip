@@ -1,5 +1,6 @@
-// C ABI of the MHM local-problem engine: argument checks, launch planning,
-// workspace management.  All compute happens in the kernels of mhm_kernels.hip.
+// C ABI of the MHM local-problem engine: argument checks, launch planning
+// (size classes, kernel families, autotuning), workspace management, graph
+// capture.  All compute happens in the kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -7,27 +8,74 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/mhm.h"
 #include "mhm_kernels.h"
-
-struct mhm_ctx_s {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  int n_cu = 256;
-  size_t lds_limit = 160 * 1024;
-  bool no_rr = false;          // MHM_NO_RR=1: use the LDS-tile kernel for FP64 too
-  bool no_ll = false;          // MHM_NO_LL=1: right-looking workspace kernel for large elements
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  std::string err;
-};
 
 namespace {
 
 constexpr int kGridCap = 1 << 20;
 constexpr size_t kStaticLds = 4096;      // static __shared__ of k_local, rounded up
 constexpr double kIrTol = 4.0e-15;
+constexpr size_t kAlign = 256;
+
+// Size classes of ragged batches (upper s of each class).  A batch whose s
+// range falls in one class runs as one launch; otherwise a binning kernel
+// sorts the elements into per-class lists and every class gets its own
+// persistent launch, on its own stream, sized for that class.
+constexpr int kNumClasses = 5;
+constexpr int kClassHi[kNumClasses] = {16, 25, 33, 48, 64};
+static_assert(kNumClasses <= mhm::BIN_MAX_CLASSES, "class table");
+
+int class_of(int s) {
+  for (int c = 0; c < kNumClasses; ++c)
+    if (s <= kClassHi[c]) return c;
+  return kNumClasses - 1;
+}
+
+// Kernel family ("tile shape") of a launch.
+enum Fam { FAM_RR = 0, FAM_LDS = 1, FAM_LL = 2, FAM_WS = 3 };
+const char* fam_name(int f) {
+  switch (f) {
+    case FAM_RR: return "register-tiles";
+    case FAM_LDS: return "lds-tiles";
+    case FAM_LL: return "left-looking";
+    default: return "workspace";
+  }
+}
+struct Choice {
+  int fam = -1;
+  int pw = 0;   // panel width (left-looking)
+};
+
+}  // namespace
+
+struct mhm_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 256;
+  size_t lds_limit = 160 * 1024;
+  bool no_rr = false;          // MHM_NO_RR=1: never use the register-tile kernel
+  bool no_ll = false;          // MHM_NO_LL=1: never use the left-looking kernel
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t aux[kNumClasses] = {};   // class streams of ragged runs
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kNumClasses] = {};
+  Choice tuned[kNumClasses][2][2];     // [class][fp32][fused], from mhm_autotune
+  std::string tune_log;
+  std::string err;
+};
+
+struct mhm_graph_s {
+  mhm_ctx ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* ws = nullptr;
+};
+
+namespace {
 
 thread_local std::string g_err;   // errors of calls without a context
 
@@ -42,6 +90,7 @@ mhm_status hip_fail(mhm_ctx c, hipError_t e, const char* where) {
 }
 
 int n_of(int s) { return (s + 1) * (s + 2) / 2; }
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 mhm_status check_batch(mhm_ctx c, const mhm_batch* b, bool need_mat, bool need_node) {
   if (!c) return MHM_E_ARG;
@@ -49,6 +98,7 @@ mhm_status check_batch(mhm_ctx c, const mhm_batch* b, bool need_mat, bool need_n
   if (b->n_elem < 0) return fail(c, MHM_E_ARG, "n_elem < 0");
   if (b->n_elem == 0) return MHM_OK;
   if (b->s_max < 1 || b->s_max > MHM_S_LIMIT) return fail(c, MHM_E_UNSUPPORTED, "s_max outside [1, MHM_S_LIMIT]");
+  if (b->s_min < 0 || b->s_min > b->s_max) return fail(c, MHM_E_ARG, "s_min outside [0, s_max]");
   if (b->l_max < 0 || b->l_max > MHM_L_LIMIT) return fail(c, MHM_E_UNSUPPORTED, "l_max outside [0, MHM_L_LIMIT]");
   if (!b->s || !b->l || !b->vert || !b->sigma || !b->flip || !b->kappa || !b->f || !b->tri_off || !b->rhs_off)
     return fail(c, MHM_E_ARG, "a required batch array is NULL");
@@ -61,53 +111,118 @@ mhm_status check_batch(mhm_ctx c, const mhm_batch* b, bool need_mat, bool need_n
 
 int grid_for(const mhm_batch* b) { return std::min(b->n_elem, kGridCap); }
 
-// Launch plan of k_local for a batch.
+// Launch plan of one local-problem kernel for elements with s <= s_cap.
 struct Plan {
-  bool fp32, in_lds, rr, ll;
-  int nt, tile_cap, n_cap, f_cap, k_cap, grid;
-  size_t lds, ws_need;
-  int64_t ws_slot;
+  bool ok = false, fp32 = false, fused = false;
+  Choice ch;
+  int nt = 0, tile_cap = 0, n_cap = 0, f_cap = 0, k_cap = 0, grid = 0;
+  size_t lds = 0, ws_need = 0;
+  int64_t ws_slot = 0;
 };
 
-Plan plan_local(mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, bool force_ws) {
+Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_cap, Choice ch, bool listed) {
   Plan p;
   p.fp32 = fp32;
-  p.n_cap = n_of(b->s_max);
-  p.f_cap = mhm::local_face_cap(b);
+  p.fused = fused;
+  p.ch = ch;
+  p.n_cap = n_of(s_cap);
+  p.f_cap = 3 * (b->l_max + 1) * (s_cap + 1);
   p.nt = (p.n_cap + 15) / 16;
   p.tile_cap = p.nt * (p.nt + 1) / 2 + p.nt;
   const size_t tsz = fp32 ? sizeof(float) : sizeof(double);
-  const int k_lds = fused ? b->s_max * b->s_max : 0;
-  const size_t lds_in = mhm::local_lds_bytes(fp32, true, p.n_cap, p.f_cap, k_lds, p.tile_cap);
-  p.in_lds = !force_ws && lds_in + kStaticLds <= c->lds_limit;
-  // FP64 elements of up to 16 * local_rr_max_nt() nodes: register-resident kernel
-  p.ll = false;
-  p.rr = !fp32 && !force_ws && !c->no_rr && p.nt <= mhm::local_rr_max_nt();
-  if (p.rr) {
-    p.in_lds = true;
-    p.k_cap = k_lds;
-    p.lds = mhm::local_rr_lds_bytes(p.n_cap, p.f_cap, k_lds);
-    p.grid = grid_for(b);
-    p.ws_slot = 0;
-    p.ws_need = 0;
-    return p;
+  const int k_lds = fused ? s_cap * s_cap : 0;
+  // one workgroup per element, or a persistent grid over a class list
+  const int one_each = listed ? std::min(b->n_elem, 8 * c->n_cu) : grid_for(b);
+  const int slots = std::min(b->n_elem, 2 * c->n_cu);
+  switch (ch.fam) {
+    case FAM_RR:
+      p.ok = !fp32 && p.nt <= mhm::local_rr_max_nt();
+      p.k_cap = k_lds;
+      p.lds = mhm::local_rr_lds_bytes(p.n_cap, p.f_cap, k_lds);
+      p.grid = one_each;
+      break;
+    case FAM_LDS:
+      p.k_cap = k_lds;
+      p.lds = mhm::local_lds_bytes(fp32, true, p.n_cap, p.f_cap, k_lds, p.tile_cap);
+      p.ok = p.lds + kStaticLds <= c->lds_limit;
+      p.grid = one_each;
+      break;
+    case FAM_LL:
+      p.ok = mhm::local_ll_has(fp32, ch.pw, p.nt);
+      p.lds = mhm::local_ll_lds_bytes(fp32, ch.pw, p.n_cap, p.f_cap);
+      p.grid = slots;
+      p.tile_cap += p.nt;   // the diagonal factor tiles kept for the factor output
+      p.ws_slot = (int64_t)p.tile_cap * mhm::TILE_WORDS;
+      break;
+    default:
+      p.lds = mhm::local_lds_bytes(fp32, false, p.n_cap, p.f_cap, 0, p.tile_cap);
+      p.ok = p.lds + kStaticLds <= c->lds_limit;
+      p.grid = slots;
+      p.ws_slot = (int64_t)p.tile_cap * mhm::TILE_WORDS;
+      break;
   }
-  if (p.in_lds) {
-    p.k_cap = k_lds;
-    p.lds = lds_in;
-    p.grid = grid_for(b);
-    p.ws_slot = 0;
-    p.ws_need = 0;
-  } else {
-    p.k_cap = 0;
-    p.ll = !c->no_ll && mhm::local_ll_rows_per_wave(p.nt) > 0;
-    p.lds = p.ll ? mhm::local_ll_lds_bytes(fp32, p.n_cap, p.f_cap)
-                 : mhm::local_lds_bytes(fp32, false, p.n_cap, p.f_cap, 0, p.tile_cap);
-    p.grid = std::min(b->n_elem, 2 * c->n_cu);
-    p.ws_slot = (int64_t)p.tile_cap * mhm::TILE_WORDS;
-    p.ws_need = (size_t)p.grid * (size_t)p.ws_slot * tsz;
-  }
+  p.ok = p.ok && p.lds + kStaticLds <= c->lds_limit;
+  p.ws_need = align_up((size_t)p.grid * (size_t)p.ws_slot * tsz);
   return p;
+}
+
+// Default family when nothing was tuned.
+Choice default_choice(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_cap, bool listed) {
+  const Choice cands[] = {{FAM_RR, 0}, {FAM_LDS, 0}, {FAM_LL, mhm::local_ll_default_panel(fp32)}, {FAM_WS, 0}};
+  for (const Choice& ch : cands) {
+    if (ch.fam == FAM_RR && c->no_rr) continue;
+    if (ch.fam == FAM_LL && c->no_ll) continue;
+    if (plan_for(c, b, fp32, fused, s_cap, ch, listed).ok) return ch;
+  }
+  return Choice{FAM_WS, 0};
+}
+
+// The FP64 recomputation pass of an FP32 launch (refinement that did not
+// converge): left-looking where it applies, else the workspace kernel.
+Plan fallback_plan(const mhm_ctx c, const mhm_batch* b, int s_cap, bool listed) {
+  Plan p = plan_for(c, b, false, true, s_cap, Choice{FAM_LL, 2}, listed);
+  if (c->no_ll || !p.ok) p = plan_for(c, b, false, true, s_cap, Choice{FAM_WS, 0}, listed);
+  return p;
+}
+
+// Everything one run of the local problems enqueues.
+struct ClassRun {
+  int cls = 0, s_cap = 0;
+  Plan main, fb;
+  size_t ws_off = 0;   // this class's workspace (main and fallback pass share it)
+};
+struct RunPlan {
+  bool listed = false;   // binned into class lists
+  int n_runs = 0;
+  ClassRun run[kNumClasses];
+  size_t list_bytes = 0;  // class lists + counts at the start of the workspace
+  size_t ws_total = 0;
+};
+
+// `over`: force this choice for every class (tuning); otherwise the tuned
+// or default choice per class.
+RunPlan make_run_plan(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, const Choice* over) {
+  RunPlan rp;
+  const int s_lo = b->s_min > 0 ? b->s_min : 1;
+  const int c_lo = class_of(s_lo), c_hi = class_of(b->s_max);
+  rp.listed = c_lo != c_hi;
+  if (rp.listed) rp.list_bytes = align_up(sizeof(int32_t) * ((size_t)kNumClasses * b->n_elem + kNumClasses));
+  size_t off = rp.list_bytes;
+  // largest class first: it goes on the caller's stream and starts first
+  for (int k = c_hi; k >= c_lo; --k) {
+    ClassRun& r = rp.run[rp.n_runs++];
+    r.cls = k;
+    r.s_cap = rp.listed ? std::min(kClassHi[k], b->s_max) : b->s_max;
+    Choice ch = over ? *over : c->tuned[k][fp32][fused];
+    if (ch.fam < 0 || !plan_for(c, b, fp32, fused, r.s_cap, ch, rp.listed).ok)
+      ch = default_choice(c, b, fp32, fused, r.s_cap, rp.listed);
+    r.main = plan_for(c, b, fp32, fused, r.s_cap, ch, rp.listed);
+    if (fp32) r.fb = fallback_plan(c, b, r.s_cap, rp.listed);
+    r.ws_off = off;
+    off += std::max(r.main.ws_need, fp32 ? r.fb.ws_need : 0);
+  }
+  rp.ws_total = off;
+  return rp;
 }
 
 mhm_status ensure_ws(mhm_ctx c, size_t bytes) {
@@ -128,62 +243,221 @@ mhm_status ensure_ws(mhm_ctx c, size_t bytes) {
   return MHM_OK;
 }
 
-// One k_local pass (+ the FP64 fallback pass after an FP32 pass).
-mhm_status run_local(mhm_ctx c, const mhm_batch* b, mhm_prec prec, bool fused, const double* Ahat,
-                     const double* Btil, double* Lout, double* X, double* M, double* E, double* B, double* F,
-                     int32_t* info, int32_t* ir_iters, int max_iters) {
-  const bool fp32 = prec == MHM_FP32_IR;
-  Plan p = plan_local(c, b, fp32, fused, false);
-  Plan fb = plan_local(c, b, false, true, true);
-  size_t need = p.ws_need;
-  if (fp32) need = std::max(need, fb.ws_need);
-  mhm_status st = ensure_ws(c, need);
-  if (st != MHM_OK) return st;
+mhm_status ensure_streams(mhm_ctx c) {
+  if (c->fork) return MHM_OK;
+  hipError_t e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(c, e, "hipEventCreateWithFlags");
+  for (int k = 0; k < kNumClasses; ++k) {
+    e = hipStreamCreateWithFlags(&c->aux[k], hipStreamNonBlocking);   // default priority
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreateWithFlags");
+    e = hipEventCreateWithFlags(&c->join[k], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventCreateWithFlags");
+  }
+  return MHM_OK;
+}
 
+// Pointers of one run.
+struct RunIO {
+  const double* Ahat = nullptr;
+  const double* Btil = nullptr;
+  double* Lout = nullptr;
+  double *X = nullptr, *M = nullptr, *E = nullptr, *B = nullptr, *F = nullptr;
+  int32_t* info = nullptr;
+  int32_t* ir_iters = nullptr;
+  int max_iters = 0;
+};
+
+hipError_t launch_plan(const Plan& p, const mhm_batch* b, const mhm::LocalArgs& a, hipStream_t st) {
+  switch (p.ch.fam) {
+    case FAM_RR: return mhm::launch_local_rr(p.fused, b, a, p.lds, p.grid, st);
+    case FAM_LDS: return mhm::launch_local(p.fp32, true, p.fused, b, a, p.lds, p.grid, st);
+    case FAM_LL: return mhm::launch_local_ll(p.fp32, p.fused, p.ch.pw, p.nt, b, a, p.lds, p.grid, st);
+    default: return mhm::launch_local(p.fp32, false, p.fused, b, a, p.lds, p.grid, st);
+  }
+}
+
+mhm::LocalArgs local_args(const Plan& p, const RunIO& io, void* ws, const int32_t* elist, const int32_t* ecount) {
   mhm::LocalArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.Ahat = Ahat;
-  a.Btil = Btil;
-  a.Lout = Lout;
-  a.X = X;
-  a.M = M;
-  a.E = E;
-  a.B = B;
-  a.F = F;
-  a.info = info;
-  a.ir_iters = ir_iters;
-  a.max_iters = std::max(0, max_iters);
-  a.only_fallback = 0;
+  a.Ahat = io.Ahat;
+  a.Btil = io.Btil;
+  a.Lout = io.Lout;
+  a.X = io.X;
+  a.M = io.M;
+  a.E = io.E;
+  a.B = io.B;
+  a.F = io.F;
+  a.info = io.info;
+  a.ir_iters = io.ir_iters;
+  a.max_iters = std::max(0, io.max_iters);
   a.ir_tol = kIrTol;
-  a.ws = c->ws;
+  a.ws = ws;
   a.ws_slot = p.ws_slot;
   a.tile_cap = p.tile_cap;
   a.n_cap = p.n_cap;
   a.f_cap = p.f_cap;
   a.k_cap = p.k_cap;
-  hipError_t e = p.rr ? mhm::launch_local_rr(fused, b, a, p.lds, p.grid, c->stream)
-               : p.ll ? mhm::launch_local_ll(fp32, fused, p.nt, b, a, p.lds, p.grid, c->stream)
-                      : mhm::launch_local(fp32, p.in_lds, fused, b, a, p.lds, p.grid, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "k_local launch");
-  if (fp32) {
-    // FP64 recomputation of the elements whose refinement did not converge
-    mhm::LocalArgs f = a;
+  a.elist = elist;
+  a.ecount = ecount;
+  return a;
+}
+
+// One class: the main pass, then (FP32) the FP64 pass of the elements whose
+// refinement did not converge.
+mhm_status enqueue_class(mhm_ctx c, const ClassRun& r, const mhm_batch* b, const RunIO& io, char* ws,
+                         const int32_t* elist, const int32_t* ecount, hipStream_t st) {
+  mhm::LocalArgs a = local_args(r.main, io, ws + r.ws_off, elist, ecount);
+  hipError_t e = launch_plan(r.main, b, a, st);
+  if (e != hipSuccess) return hip_fail(c, e, "local kernel launch");
+  if (r.main.fp32) {
+    RunIO f = io;
     f.Ahat = nullptr;
     f.Btil = nullptr;
-    f.only_fallback = 1;
-    f.ws_slot = fb.ws_slot;
-    f.tile_cap = fb.tile_cap;
-    f.n_cap = fb.n_cap;
-    f.f_cap = fb.f_cap;
-    f.k_cap = 0;
-    if (!fused) {
-      f.M = f.E = f.B = f.F = nullptr;
-    }
-    e = fb.ll ? mhm::launch_local_ll(false, true, fb.nt, b, f, fb.lds, fb.grid, c->stream)
-              : mhm::launch_local(false, false, true, b, f, fb.lds, fb.grid, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "k_local fallback launch");
+    if (!r.main.fused) f.M = f.E = f.B = f.F = nullptr;
+    mhm::LocalArgs fa = local_args(r.fb, f, ws + r.ws_off, elist, ecount);
+    fa.only_fallback = 1;
+    e = launch_plan(r.fb, b, fa, st);
+    if (e != hipSuccess) return hip_fail(c, e, "FP64 fallback launch");
   }
   return MHM_OK;
+}
+
+mhm::BinClasses bin_classes() {
+  mhm::BinClasses bc;
+  std::memset(&bc, 0, sizeof(bc));
+  bc.n = kNumClasses;
+  for (int k = 0; k < kNumClasses; ++k) bc.s_hi[k] = kClassHi[k];
+  return bc;
+}
+
+// Enqueue a whole run on stream `st` (also under stream capture): binning,
+// then the classes, the largest on `st` and the others forked onto the
+// context's class streams and joined back.
+mhm_status enqueue_run(mhm_ctx c, const RunPlan& rp, const mhm_batch* b, const RunIO& io, void* ws_v, hipStream_t st) {
+  char* ws = static_cast<char*>(ws_v);
+  int32_t* lists = reinterpret_cast<int32_t*>(ws);
+  int32_t* counts = lists + (size_t)kNumClasses * b->n_elem;
+  if (rp.listed) {
+    hipError_t e = mhm::launch_bin(b, bin_classes(), lists, counts, st);
+    if (e != hipSuccess) return hip_fail(c, e, "k_bin launch");
+  }
+  const bool fork = rp.n_runs > 1;
+  if (fork) {
+    mhm_status s0 = ensure_streams(c);
+    if (s0 != MHM_OK) return s0;
+    hipError_t e = hipEventRecord(c->fork, st);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventRecord");
+    for (int i = 1; i < rp.n_runs; ++i) {
+      e = hipStreamWaitEvent(c->aux[i], c->fork, 0);
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamWaitEvent");
+    }
+  }
+  for (int i = 0; i < rp.n_runs; ++i) {
+    const ClassRun& r = rp.run[i];
+    const int32_t* el = rp.listed ? lists + (size_t)r.cls * b->n_elem : nullptr;
+    const int32_t* ec = rp.listed ? counts + r.cls : nullptr;
+    mhm_status s1 = enqueue_class(c, r, b, io, ws, el, ec, i == 0 ? st : c->aux[i]);
+    if (s1 != MHM_OK) return s1;
+  }
+  if (fork) {
+    for (int i = 1; i < rp.n_runs; ++i) {
+      hipError_t e = hipEventRecord(c->join[i], c->aux[i]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, c->join[i], 0);
+      if (e != hipSuccess) return hip_fail(c, e, "stream join");
+    }
+  }
+  return MHM_OK;
+}
+
+mhm_status run_local(mhm_ctx c, const mhm_batch* b, mhm_prec prec, bool fused, const RunIO& io) {
+  const RunPlan rp = make_run_plan(c, b, prec == MHM_FP32_IR, fused, nullptr);
+  mhm_status st = ensure_ws(c, rp.ws_total);
+  if (st != MHM_OK) return st;
+  return enqueue_run(c, rp, b, io, c->ws, c->stream);
+}
+
+RunIO fused_io(double* X, double* M, double* E, double* B, double* F, int32_t* info, int32_t* ir_iters,
+               int max_iters) {
+  RunIO io;
+  io.X = X;
+  io.M = M;
+  io.E = E;
+  io.B = B;
+  io.F = F;
+  io.info = info;
+  io.ir_iters = ir_iters;
+  io.max_iters = max_iters;
+  return io;
+}
+
+mhm_status check_fused(mhm_ctx c, const mhm_batch* b, mhm_prec prec, double* X, double* M, double* E, double* B,
+                       double* F, int32_t* info) {
+  mhm_status st = check_batch(c, b, false, false);
+  if (st != MHM_OK) return st;
+  if (prec != MHM_FP64 && prec != MHM_FP32_IR) return fail(c, MHM_E_ARG, "unknown precision");
+  if (b->n_elem > 0 && (!X || !M || !E || !B || !F || !info))
+    return fail(c, MHM_E_ARG, "X, M, E, B, F and info are required");
+  return MHM_OK;
+}
+
+// Autotuning of one class: every feasible family / panel width on up to
+// `cap` of its elements, timed with events; returns the fastest.
+Choice tune_class(mhm_ctx c, const mhm_batch* b, bool fp32, const RunPlan& base, int i, const RunIO& io,
+                  int32_t* dcount, int cap, int count, std::string& log, mhm_status& st) {
+  const ClassRun& r0 = base.run[i];
+  std::vector<Choice> cands;
+  const Choice all[] = {{FAM_RR, 0}, {FAM_LDS, 0}, {FAM_LL, 2}, {FAM_LL, 4}, {FAM_WS, 0}};
+  bool have_ll = false;
+  for (const Choice& ch : all) {
+    if (ch.fam == FAM_RR && c->no_rr) continue;
+    if (ch.fam == FAM_LL && c->no_ll) continue;
+    if (ch.fam == FAM_WS && have_ll) continue;   // the right-looking workspace kernel only without a left-looking one
+    if (plan_for(c, b, fp32, true, r0.s_cap, ch, base.listed).ok) {
+      cands.push_back(ch);
+      if (ch.fam == FAM_LL) have_ll = true;
+    }
+  }
+  Choice best = r0.main.ch;
+  if (cands.size() < 2) return best;
+  const int sub = std::min(count, cap);
+  hipError_t e = hipMemcpyAsync(dcount, &sub, sizeof(int), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) {
+    st = hip_fail(c, e, "hipMemcpyAsync");
+    return best;
+  }
+  const int32_t* el = nullptr;
+  if (base.listed) el = reinterpret_cast<int32_t*>(c->ws) + (size_t)r0.cls * b->n_elem;
+  hipEvent_t t0, t1;
+  (void)hipEventCreate(&t0);
+  (void)hipEventCreate(&t1);
+  float best_ms = 0.0f;
+  char buf[160];
+  for (const Choice& ch : cands) {
+    ClassRun r = r0;
+    r.main = plan_for(c, b, fp32, true, r.s_cap, ch, base.listed);
+    r.ws_off = base.list_bytes;   // classes are tuned one after another
+    float ms = 0.0f;
+    for (int rep = 0; rep < 3 && st == MHM_OK; ++rep) {   // first repetition warms up
+      (void)hipEventRecord(t0, c->stream);
+      st = enqueue_class(c, r, b, io, static_cast<char*>(c->ws), el, dcount, c->stream);
+      (void)hipEventRecord(t1, c->stream);
+      if (hipEventSynchronize(t1) != hipSuccess) st = fail(c, MHM_E_DEVICE, "tuning run failed");
+      float m = 0.0f;
+      (void)hipEventElapsedTime(&m, t0, t1);
+      if (rep > 0) ms += m / 2;
+    }
+    if (st != MHM_OK) break;
+    std::snprintf(buf, sizeof(buf), "%s{\"s_max\": %d, \"prec\": \"%s\", \"kernel\": \"%s\", \"pw\": %d, \"ms\": %.4f, \"elements\": %d}",
+                  log.empty() ? "" : ", ", r.s_cap, fp32 ? "fp32_ir" : "fp64", fam_name(ch.fam), ch.pw, ms, sub);
+    log += buf;
+    if (best_ms == 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = ch;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  return best;
 }
 
 }  // namespace
@@ -217,11 +491,17 @@ mhm_status mhm_create(mhm_ctx* out, int device, void* hip_stream) {
 
 mhm_status mhm_destroy(mhm_ctx c) {
   if (!c) return MHM_E_ARG;
-  if (c->ws) {
-    (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(c->ws);
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (int k = 0; k < kNumClasses; ++k) {
+    if (c->aux[k]) {
+      (void)hipStreamSynchronize(c->aux[k]);
+      (void)hipStreamDestroy(c->aux[k]);
+    }
+    if (c->join[k]) (void)hipEventDestroy(c->join[k]);
   }
+  if (c->fork) (void)hipEventDestroy(c->fork);
+  if (c->ws) (void)hipFree(c->ws);
   delete c;
   return MHM_OK;
 }
@@ -241,12 +521,10 @@ mhm_status mhm_sync(mhm_ctx c) {
 }
 
 size_t mhm_workspace_bytes(mhm_ctx c, const mhm_batch* b, mhm_prec prec) {
-  if (!c || !b || b->n_elem <= 0 || b->s_max < 1 || b->s_max > MHM_S_LIMIT) return 0;
+  if (!c || !b || b->n_elem <= 0 || b->s_max < 1 || b->s_max > MHM_S_LIMIT || b->s_min < 0 || b->s_min > b->s_max)
+    return 0;
   const bool fp32 = prec == MHM_FP32_IR;
-  size_t need = plan_local(c, b, fp32, true, false).ws_need;
-  need = std::max(need, plan_local(c, b, fp32, false, false).ws_need);
-  if (fp32) need = std::max(need, plan_local(c, b, false, true, true).ws_need);
-  return need;
+  return std::max(make_run_plan(c, b, fp32, true, nullptr).ws_total, make_run_plan(c, b, fp32, false, nullptr).ws_total);
 }
 
 mhm_status mhm_local_assemble(mhm_ctx c, const mhm_batch* b, double* Ahat, double* Btil, double* cvec,
@@ -268,8 +546,15 @@ mhm_status mhm_local_factor_solve(mhm_ctx c, const mhm_batch* b, mhm_prec prec, 
   if (!Ahat_io || !Btil || !X || !info) return fail(c, MHM_E_ARG, "Ahat_io, Btilde, X and info are required");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-  return run_local(c, b, prec, false, Ahat_io, Btil, Ahat_io, X, nullptr, nullptr, nullptr, nullptr, info,
-                   ir_iters, max_iters);
+  RunIO io;
+  io.Ahat = Ahat_io;
+  io.Btil = Btil;
+  io.Lout = Ahat_io;
+  io.X = X;
+  io.info = info;
+  io.ir_iters = ir_iters;
+  io.max_iters = max_iters;
+  return run_local(c, b, prec, false, io);
 }
 
 mhm_status mhm_skeleton_contrib(mhm_ctx c, const mhm_batch* b, const double* X, double* M, double* E, double* B,
@@ -285,13 +570,134 @@ mhm_status mhm_skeleton_contrib(mhm_ctx c, const mhm_batch* b, const double* X, 
 
 mhm_status mhm_local_batch_run(mhm_ctx c, const mhm_batch* b, mhm_prec prec, double* X, double* M, double* E,
                                double* B, double* F, int32_t* info, int32_t* ir_iters, int max_iters) {
-  mhm_status st = check_batch(c, b, false, false);
+  mhm_status st = check_fused(c, b, prec, X, M, E, B, F, info);
   if (st != MHM_OK || b->n_elem == 0) return st;
-  if (prec != MHM_FP64 && prec != MHM_FP32_IR) return fail(c, MHM_E_ARG, "unknown precision");
-  if (!X || !M || !E || !B || !F || !info) return fail(c, MHM_E_ARG, "X, M, E, B, F and info are required");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-  return run_local(c, b, prec, true, nullptr, nullptr, nullptr, X, M, E, B, F, info, ir_iters, max_iters);
+  return run_local(c, b, prec, true, fused_io(X, M, E, B, F, info, ir_iters, max_iters));
+}
+
+mhm_status mhm_autotune(mhm_ctx c, const mhm_batch* b, mhm_prec prec, double* X, double* M, double* E, double* B,
+                        double* F, int32_t* info, int32_t* ir_iters, int max_iters) {
+  mhm_status st = check_fused(c, b, prec, X, M, E, B, F, info);
+  if (st != MHM_OK || b->n_elem == 0) return st;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const bool fp32 = prec == MHM_FP32_IR;
+  const RunIO io = fused_io(X, M, E, B, F, info, ir_iters, max_iters);
+  for (int k = 0; k < kNumClasses; ++k) c->tuned[k][fp32][1] = Choice();
+  const RunPlan base = make_run_plan(c, b, fp32, true, nullptr);
+  // workspace: class lists, a tuning count, and the largest candidate slot set
+  size_t need = 0;
+  for (int i = 0; i < base.n_runs; ++i) {
+    for (const Choice ch : {Choice{FAM_RR, 0}, Choice{FAM_LDS, 0}, Choice{FAM_LL, 2}, Choice{FAM_LL, 4}, Choice{FAM_WS, 0}}) {
+      const Plan p = plan_for(c, b, fp32, true, base.run[i].s_cap, ch, base.listed);
+      if (p.ok) need = std::max(need, p.ws_need);
+    }
+    need = std::max(need, base.run[i].fb.ws_need);
+  }
+  const size_t cnt_off = base.list_bytes + need;
+  st = ensure_ws(c, std::max(base.ws_total, cnt_off + kAlign));
+  if (st != MHM_OK) return st;
+  int32_t* dcount = reinterpret_cast<int32_t*>(static_cast<char*>(c->ws) + cnt_off);
+  int counts[kNumClasses] = {};
+  if (base.listed) {
+    int32_t* lists = static_cast<int32_t*>(c->ws);
+    e = mhm::launch_bin(b, bin_classes(), lists, lists + (size_t)kNumClasses * b->n_elem, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(counts, lists + (size_t)kNumClasses * b->n_elem, sizeof(counts), hipMemcpyDeviceToHost,
+                         c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "binning for tuning");
+  } else {
+    counts[base.run[0].cls] = b->n_elem;
+  }
+  std::string log;
+  for (int i = 0; i < base.n_runs && st == MHM_OK; ++i) {
+    const int k = base.run[i].cls;
+    if (counts[k] == 0) continue;
+    const Choice best = tune_class(c, b, fp32, base, i, io, dcount, 4 * c->n_cu, counts[k], log, st);
+    c->tuned[k][fp32][1] = best;
+  }
+  c->tune_log = "[" + log + "]";
+  if (st != MHM_OK) return st;
+  return run_local(c, b, prec, true, io);   // leaves the outputs of the tuned run
+}
+
+size_t mhm_tune_report(mhm_ctx c, char* buf, size_t len) {
+  if (!c) return 0;
+  if (buf && len > 0) {
+    const size_t k = std::min(len - 1, c->tune_log.size());
+    std::memcpy(buf, c->tune_log.data(), k);
+    buf[k] = '\0';
+  }
+  return c->tune_log.size() + 1;
+}
+
+mhm_status mhm_graph_create(mhm_ctx c, const mhm_batch* b, mhm_prec prec, double* X, double* M, double* E, double* B,
+                            double* F, int32_t* info, int32_t* ir_iters, int max_iters, mhm_graph* out) {
+  if (!out) return fail(c, MHM_E_ARG, "graph is NULL");
+  *out = nullptr;
+  mhm_status st = check_fused(c, b, prec, X, M, E, B, F, info);
+  if (st != MHM_OK) return st;
+  if (b->n_elem == 0) return fail(c, MHM_E_ARG, "empty batch");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const RunPlan rp = make_run_plan(c, b, prec == MHM_FP32_IR, true, nullptr);
+  if (rp.n_runs > 1) {
+    st = ensure_streams(c);
+    if (st != MHM_OK) return st;
+  }
+  mhm_graph g = new mhm_graph_s();
+  g->ctx = c;
+  if (rp.ws_total > 0) {
+    e = hipMalloc(&g->ws, rp.ws_total);
+    if (e != hipSuccess) {
+      delete g;
+      return fail(c, MHM_E_NOMEM, "hipMalloc of the graph workspace failed");
+    }
+  }
+  hipStream_t cs = nullptr;
+  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    st = enqueue_run(c, rp, b, fused_io(X, M, E, B, F, info, ir_iters, max_iters), g->ws, cs);
+    const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+    if (st == MHM_OK && e2 != hipSuccess) st = hip_fail(c, e2, "hipStreamEndCapture");
+    if (st == MHM_OK) {
+      e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = hip_fail(c, e, "hipGraphInstantiate");
+    }
+  } else {
+    st = hip_fail(c, e, "hipStreamBeginCapture");
+  }
+  if (cs) (void)hipStreamDestroy(cs);
+  if (st != MHM_OK) {
+    mhm_graph_destroy(g);
+    return st;
+  }
+  *out = g;
+  return MHM_OK;
+}
+
+mhm_status mhm_graph_launch(mhm_graph g) {
+  if (!g || !g->exec) return MHM_E_ARG;
+  mhm_ctx c = g->ctx;
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipGraphLaunch(g->exec, c->stream);
+  return e == hipSuccess ? MHM_OK : hip_fail(c, e, "hipGraphLaunch");
+}
+
+mhm_status mhm_graph_destroy(mhm_graph g) {
+  if (!g) return MHM_E_ARG;
+  mhm_ctx c = g->ctx;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->ws) (void)hipFree(g->ws);
+  delete g;
+  return MHM_OK;
 }
 
 }  // extern "C"

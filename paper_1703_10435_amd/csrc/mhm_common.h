@@ -257,10 +257,11 @@ __device__ __forceinline__ float row_bcast(float x, int src) {
 // Step j takes the pivot from its lane, the pivot row across the 16-lane rows
 // (lane shuffle) and the pivot column inside each row (DPP broadcast).
 // Writes W = L^{-1} back to `t` (full tile, zero above the diagonal) and the
-// lower triangle of L to Lo (column-major n x n, may be null); returns the
-// first non-positive pivot (or -1).
+// lower triangle of L to Lo (column-major n x n, may be null) and L itself
+// as a stored tile to Ld (may be null); returns the first non-positive pivot
+// (or -1).
 template <typename T>
-__device__ __forceinline__ int potrf_c(T* t, T* Lo, int n, int k, int lane) {
+__device__ __forceinline__ int potrf_c(T* t, T* Lo, int n, int k, int lane, T* Ld = nullptr) {
   const int c = lane & 15, g = lane >> 4;
   T a[4], w[4];
 #pragma unroll
@@ -309,6 +310,13 @@ __device__ __forceinline__ int potrf_c(T* t, T* Lo, int n, int k, int lane) {
         const int r = g + 4 * v, p = 16 * k + r;
         if (r >= c && p < n) Lo[(int64_t)q * n + p] = a[v] * myrs;
       }
+    }
+  }
+  if (Ld) {   // L_kk as a stored tile (lower triangle, zero above)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = g + 4 * v;
+      Ld[r * TST + c] = r >= c ? a[v] * myrs : T(0);
     }
   }
   return bad;
@@ -398,7 +406,10 @@ __device__ __forceinline__ double ir_residual(const Elem& E, KAP kap, const doub
 }
 
 // Normwise backward-error test of every column from the per-wave maxima.
-__device__ __forceinline__ bool ir_converged(const double* wred, int nwaves, int r, double anorm, double tol) {
+// Normwise backward error of the current iterate, max over the columns:
+// max_p |r_pa| / (||Ahat||_inf max_p |x_pa| + max_p |b_pa|)  (NaN -> inf).
+__device__ __forceinline__ double ir_backward_error(const double* wred, int nwaves, int r, double anorm) {
+  double be = 0.0;
   for (int a = 0; a < r; ++a) {
     double rm = 0, xm = 0, bm = 0;
     for (int w = 0; w < nwaves; ++w) {
@@ -406,9 +417,27 @@ __device__ __forceinline__ bool ir_converged(const double* wred, int nwaves, int
       xm = fmax(xm, wred[(w * 3 + 1) * 16 + a]);
       bm = fmax(bm, wred[(w * 3 + 2) * 16 + a]);
     }
-    if (!(rm <= tol * (anorm * xm + bm))) return false;
+    const double e = rm / (anorm * xm + bm);
+    be = e == e ? fmax(be, e) : __builtin_inf();
   }
-  return true;
+  return be;
+}
+
+// Refinement decision after step `it` (0 = the first solve): 1 converged,
+// 0 continue, -1 give up.  Refinement contracts the error by a roughly
+// constant factor per step; when the observed factor (from the previous
+// step's backward error `prev`) says the tolerance cannot be reached within
+// the step budget, stop now and leave the element to the FP64 pass.
+__device__ __forceinline__ int ir_decide(double be, double prev, int it, int max_iters, double tol) {
+  if (be <= tol) return 1;
+  if (it >= max_iters) return -1;
+  if (it >= 1) {
+    const double rho = be / prev;
+    if (!(rho < 1.0)) return -1;
+    const double need = log(tol / be) / log(rho);
+    if (need > (double)(max_iters - it)) return -1;
+  }
+  return 0;
 }
 
 }  // namespace mhm

@@ -28,9 +28,23 @@ struct LocalArgs {
   int n_cap;            // largest n (length of the LDS c and source-load arrays)
   int f_cap;            // LDS doubles of the face-load table, 3 (l_max+1)(s_max+1)
   int k_cap;            // LDS doubles reserved for kappa (fused, LDS mode)
+  const int32_t* elist; // if set: process elements elist[0 .. *ecount) instead of 0 .. n_elem
+  const int32_t* ecount;
 };
 
+// Element k of a launch (identity, or through the element list of a size class).
+__device__ __forceinline__ int launch_count(const LocalArgs& a, int n_elem) { return a.ecount ? *a.ecount : n_elem; }
+__device__ __forceinline__ int launch_elem(const LocalArgs& a, int k) { return a.elist ? a.elist[k] : k; }
+
 constexpr int TILE_WORDS = 16 * 17;   // stored tile: 16 rows, padded stride 17
+
+// Size classes for ragged batches (upper s bound of each class, ascending).
+constexpr int BIN_MAX_CLASSES = 8;
+struct BinClasses {
+  int n;
+  int s_hi[BIN_MAX_CLASSES];
+};
+hipError_t launch_bin(const mhm_batch* bt, const BinClasses& cls, int32_t* elist, int32_t* counts, hipStream_t st);
 
 hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, double* c, double* area,
                            int32_t* info, int grid, hipStream_t st);
@@ -42,11 +56,14 @@ int local_face_cap(const mhm_batch* bt);
 size_t local_rr_lds_bytes(int n_cap, int f_cap, int k_cap);
 int local_rr_max_nt();
 hipError_t launch_local_rr(bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid, hipStream_t st);
-// Left-looking kernel for large elements (tiles in a workspace slot).
+// Left-looking kernel for large elements (tiles in a workspace slot), panel
+// width pw (block columns of pw tiles).
 int local_ll_rows_per_wave(int nt);
-size_t local_ll_lds_bytes(bool fp32, int n_cap, int f_cap);
-hipError_t launch_local_ll(bool fp32, bool fused, int nt_max, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
-                           hipStream_t st);
+int local_ll_default_panel(bool fp32);
+bool local_ll_has(bool fp32, int pw, int nt);
+size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap);
+hipError_t launch_local_ll(bool fp32, bool fused, int pw, int nt_max, const mhm_batch* bt, LocalArgs a, size_t lds,
+                           int grid, hipStream_t st);
 hipError_t launch_local(bool fp32, bool in_lds, bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
                         hipStream_t st);
 

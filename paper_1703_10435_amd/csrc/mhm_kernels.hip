@@ -131,6 +131,7 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
   typedef typename Mfma<T>::v4 V4;
   __shared__ Elem E;
   __shared__ int ok, bad, conv;
+  __shared__ double be_prev;
   __shared__ double red[48];
   __shared__ double colsum[16];
   __shared__ double cx[16];          // (c^T X) per column
@@ -141,7 +142,9 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
   const int NImax = 3 * (b.l_max + 1);
   const bool fp32 = sizeof(T) == 4;
 
-  for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
+  const int n_launch = launch_count(args, b.n_elem);
+  for (int k_el = blockIdx.x; k_el < n_launch; k_el += gridDim.x) {
+    const int e = launch_elem(args, k_el);
     __syncthreads();   // every thread is done with the previous element's shared flags
     if (tid == 0) {
       int st = INFO_OK;
@@ -401,9 +404,13 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
         __syncthreads();
         const double anorm = ir_residual<T, FUSED>(E, kap, X, c, cx, g, ft, bf, colsum, Btg,
                                                    [&](int J) -> T* { return tl(nt, J); }, &wred[0][0][0], red);
-        if (tid == 0) conv = ir_converged(&wred[0][0][0], NWAVES, r, anorm, args.ir_tol);
+        if (tid == 0) {
+          const double be = ir_backward_error(&wred[0][0][0], NWAVES, r, anorm);
+          conv = ir_decide(be, be_prev, it, args.max_iters, args.ir_tol);
+          be_prev = be;
+        }
         __syncthreads();
-        if (conv || it >= args.max_iters) break;
+        if (conv != 0) break;
         forward();
         backward();
         for (int idx = tid; idx < n * r; idx += NTHREADS) {
@@ -412,7 +419,7 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
         }
         __syncthreads();
       }
-      const bool cvd = conv;
+      const bool cvd = conv > 0;
       if (tid == 0) {
         if (args.ir_iters) args.ir_iters[e] = it;
         if (!cvd) args.info[e] = INFO_IR_FALLBACK;
@@ -463,6 +470,57 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
 
     if (FUSED && args.M) contrib_element(E, X, ft, colsum[E.NI], NImax, args.M, args.E, args.B, args.F, e);
   }
+}
+
+// ------------------------------------------------------- size-class binning
+// Element e goes to the first class c with s[e] <= s_hi[c] (an s outside
+// [1, MHM_S_LIMIT] to class 0, whose kernel reports the descriptor).  Class c's
+// list is elist[c * n_elem ...], in element order; counts[c] is its length.
+// One workgroup of 1024 threads, chunks of 1024 elements, wave ballots for
+// the in-chunk positions: nothing needs clearing beforehand.
+__global__ void __launch_bounds__(1024) k_bin(const int32_t* s, int n_elem, BinClasses cls, int32_t* elist,
+                                              int32_t* counts) {
+  __shared__ int wsum[16][BIN_MAX_CLASSES];
+  __shared__ int run[BIN_MAX_CLASSES];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid < cls.n) run[tid] = 0;
+  __syncthreads();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int base = 0; base < n_elem; base += 1024) {
+    const int e = base + tid;
+    int c = -1;
+    if (e < n_elem) {
+      const int se = s[e];
+      c = 0;
+      if (se >= 1 && se <= MHM_S_LIMIT)
+        while (c < cls.n - 1 && se > cls.s_hi[c]) ++c;
+    }
+    unsigned long long mine = 0;
+    for (int k = 0; k < cls.n; ++k) {
+      const unsigned long long m = __ballot64(c == k);
+      if (c == k) mine = m;
+      if (lane == 0) wsum[wave][k] = __popcll(m);
+    }
+    __syncthreads();
+    if (c >= 0) {
+      int pos = run[c] + __popcll(mine & below);
+      for (int w = 0; w < wave; ++w) pos += wsum[w][c];
+      elist[(int64_t)c * n_elem + pos] = e;
+    }
+    __syncthreads();
+    if (tid < cls.n) {
+      int t = 0;
+      for (int w = 0; w < 16; ++w) t += wsum[w][tid];
+      run[tid] += t;
+    }
+    __syncthreads();
+  }
+  if (tid < cls.n) counts[tid] = run[tid];
+}
+
+hipError_t launch_bin(const mhm_batch* bt, const BinClasses& cls, int32_t* elist, int32_t* counts, hipStream_t st) {
+  hipLaunchKernelGGL(k_bin, dim3(1), dim3(1024), 0, st, bt->s, bt->n_elem, cls, elist, counts);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------- host launchers

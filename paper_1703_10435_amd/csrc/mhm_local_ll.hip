@@ -1,551 +1,15 @@
-// Left-looking blocked local-problem kernel for large elements (gfx950).
-//
-// Same steps and results as k_local (a2-a6, FP64 or FP32 + FP64 refinement),
-// for elements whose tiles do not fit on chip (n up to 16 * 79 nodes).  One
-// workgroup of 8 waves handles one element at a time; the factor L (and the
-// right-hand-side row) lives in a per-workgroup slot of a device workspace.
-//
-// Block columns of PW tiles are built one after another:
-//   (a) the panel's tiles are initialised in registers straight from the
-//       operator (Ahat = A + gamma c c^T is never stored) and the right-hand
-//       sides, rows of 16 distributed over the waves (wave w owns rows
-//       j0 + w + 8 ri);
-//   (b) every earlier tile column m is applied, C_ij -= L_im L_jm^T, with the
-//       B operands (the PW tiles L_jm) staged in LDS and the A operands L_im
-//       loaded from the workspace (L2 / Infinity Cache resident);
-//   (c) the panel is factored in place (diagonal tile by one wave in LDS,
-//       panel solve and in-panel updates in registers) and written once.
-// Each tile of L is therefore written once and read once per later block
-// column, about n^3/(6*16*PW) tile reads per element instead of the
-// n^3/(3*16) read-modify-writes of a right-looking sweep.
-#include "mhm_common.h"
-#include "mhm_kernels.h"
+// Left-looking local-problem kernel: launch geometry and precision dispatch
+// (the kernel is in mhm_local_ll.h, its instances in mhm_local_ll_f32.hip and
+// mhm_local_ll_f64.hip).
+#include "mhm_local_ll.h"
 
 namespace mhm {
 
-namespace ll {
-constexpr int NW = 8;
-constexpr int NTHREADS = 64 * NW;
+hipError_t launch_local_ll_f32(bool fused, int pw, int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid,
+                               hipStream_t st);
+hipError_t launch_local_ll_f64(bool fused, int pw, int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid,
+                               hipStream_t st);
 
-// One block triangular sweep over the right-hand-side tile row of the factor
-// (tiles tl(nt, i) hold Z_i^T, 16 right-hand sides by 16 nodes; the diagonal
-// tiles tl(j, j) hold W_j = L_jj^{-1}):
-//   backward (BACK):  X_j^T = Z_j^T W_j,    Z_i^T -= X_j^T L_ji     (i < j)
-//   forward:          Y_j^T = Z_j^T W_j^T,  Z_i^T -= Y_j^T L_ij^T   (i > j)
-// Wave w keeps tiles i = w + NW ri in registers.  In the step for block
-// column j, after one barrier, every wave applies the published solution
-// tile of column j to its own tiles; the owner of the next column solves that
-// tile right after its last update and publishes it (LDS double buffer xb).
-// The L operands of a step are loaded one or two steps ahead, so their
-// global-memory latency overlaps the chain of column solves.  Every register
-// slot is addressed statically.
-template <typename T, int RPW, bool BACK, class TL>
-__device__ __forceinline__ void sweep(TL tl, int nt, T* xb, T* scr, int wave, int lane) {
-  typedef typename Mfma<T>::v4 V4;
-  constexpr int NB = RPW * (int)sizeof(T) <= 40 ? 2 : 1;   // operand buffers
-  V4 z[RPW];
-#pragma unroll
-  for (int ri = 0; ri < RPW; ++ri) {
-    const int i = wave + NW * ri;
-    if (i < nt) z[ri] = ld_acc<T>(tl(nt, i), lane);
-    else z[ri] = V4{0, 0, 0, 0};
-  }
-  auto colj = [&](int st) { return BACK ? nt - 1 - st : st; };
-  auto upd = [&](int i, int j) { return BACK ? i < j : (i > j && i < nt); };
-  auto ld_w = [&](int j, T (&w)[4]) {
-    const T* W = tl(j, j);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) w[c] = BACK ? ld_colrow(W, c, lane) : ld_rowcol(W, c, lane);
-  };
-  // operands of step st: L tiles applied to the own tiles, and W of the
-  // column solved during that step (owner only)
-  auto fetch = [&](int st, T (&b)[RPW][4], T (&w)[4]) {
-    if (st >= nt) return;
-    const int j = colj(st);
-#pragma unroll
-    for (int ri = 0; ri < RPW; ++ri) {
-      const int i = wave + NW * ri;
-      if (upd(i, j)) {
-        const T* L = BACK ? tl(j, i) : tl(i, j);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[ri][c] = BACK ? ld_colrow(L, c, lane) : ld_rowcol(L, c, lane);
-      }
-    }
-    if (st + 1 < nt && wave == colj(st + 1) % NW) ld_w(colj(st + 1), w);
-  };
-  auto solve_tile = [&](V4& zr, const T (&w)[4], T* dst) {
-    st_acc<T>(scr, zr, lane);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    V4 x = {0, 0, 0, 0};
-#pragma unroll
-    for (int c = 0; c < 4; ++c) x = Mfma<T>::op(ld_rowcol(scr, c, lane), w[c], x);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    zr = x;
-    st_acc<T>(dst, x, lane);
-  };
-  T bo[NB][RPW][4];
-  T wo[NB][4];
-  {
-    const int j = colj(0);
-    T w0[4];
-    if (wave == j % NW) ld_w(j, w0);
-#pragma unroll
-    for (int q = 0; q < NB; ++q) fetch(q, bo[q], wo[q]);
-#pragma unroll
-    for (int ri = 0; ri < RPW; ++ri)
-      if (wave + NW * ri == j) solve_tile(z[ri], w0, xb);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __syncthreads();
-  }
-  auto step_once = [&](int st, const T (&b)[RPW][4], const T (&w)[4]) {
-    const int j = colj(st);
-    const int jn = st + 1 < nt ? colj(st + 1) : -1;
-    const T* xj = xb + (st & 1) * TILE;
-    T* xn = xb + ((st + 1) & 1) * TILE;
-    T a[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) a[c] = -ld_rowcol(xj, c, lane);
-#pragma unroll
-    for (int ri = 0; ri < RPW; ++ri) {
-      const int i = wave + NW * ri;
-      if (upd(i, j)) {
-        V4 x = z[ri];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) x = Mfma<T>::op(a[c], b[ri][c], x);
-        z[ri] = x;
-        if (i == jn) solve_tile(z[ri], w, xn);
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __syncthreads();
-  };
-  if constexpr (NB == 2) {
-    for (int st = 0; st < nt; st += 2) {
-      step_once(st, bo[0], wo[0]);
-      fetch(st + 2, bo[0], wo[0]);
-      if (st + 1 < nt) {
-        step_once(st + 1, bo[1], wo[1]);
-        fetch(st + 3, bo[1], wo[1]);
-      }
-    }
-  } else {
-    for (int st = 0; st < nt; ++st) {
-      step_once(st, bo[0], wo[0]);
-      fetch(st + 1, bo[0], wo[0]);
-    }
-  }
-#pragma unroll
-  for (int ri = 0; ri < RPW; ++ri) {
-    const int i = wave + NW * ri;
-    if (i < nt) st_acc<T>(tl(nt, i), z[ri], lane);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __syncthreads();
-}
-}  // namespace ll
-
-template <typename T, bool FUSED, int PW, int RPW>
-__global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs args) {
-  using namespace ll;
-  typedef typename Mfma<T>::v4 V4;
-  __shared__ Elem E;
-  __shared__ int ok, bad, conv;
-  __shared__ double red[48];
-  __shared__ double colsum[16];
-  __shared__ double cx[16];
-  __shared__ double gam;
-  __shared__ double wred[NW][3][16];
-  extern __shared__ double dyn[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int NImax = 3 * (b.l_max + 1);
-  const bool fp32 = sizeof(T) == 4;
-
-  for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
-    __syncthreads();
-    if (tid == 0) {
-      int st = INFO_OK;
-      if (args.only_fallback && args.info[e] != INFO_IR_FALLBACK) {
-        ok = 0;
-      } else {
-        const bool good = load_elem(b, e, E) && E.rhs0 >= 0 && (FUSED || E.mat0 >= 0);
-        if (!good) st = INFO_BAD_DESC;
-        else if ((E.nt * (E.nt + 1)) / 2 + E.nt > args.tile_cap || E.n > args.n_cap || E.nt + 1 > NW * RPW ||
-                 (FUSED && E.NI * (E.s + 1) > args.f_cap))
-          st = INFO_TOO_LARGE;
-        ok = st == INFO_OK;
-        if (!ok || !args.only_fallback) args.info[e] = st;
-        if (args.ir_iters && !args.only_fallback) args.ir_iters[e] = 0;
-      }
-      bad = -1;
-      conv = 0;
-    }
-    __syncthreads();
-    if (!ok) continue;
-
-    const int s = E.s, n = E.n, r = E.r, nt = E.nt;
-    double* c = dyn;
-    double* bf = c + args.n_cap;
-    double* ft = bf + args.n_cap;
-    T* stage = reinterpret_cast<T*>(ft + args.f_cap);  // 2 x PW tiles
-    T* Wt = stage + 2 * PW * TILE;                       // current diagonal inverse
-    T* pub = Wt + TILE;                                  // PW published panel tiles
-    T* scr = pub + PW * TILE + wave * TILE;              // this wave's scratch tile
-    T* ws = reinterpret_cast<T*>(args.ws) + (int64_t)blockIdx.x * args.ws_slot;
-    auto tl = [&](int I, int J) -> T* { return ws + (int64_t)((I * (I + 1)) / 2 + J) * TILE; };
-    const double* kapg = b.kappa + E.tri0;
-    auto kap = [&](int t) -> double { return kapg[t]; };
-
-    // ------------------------------------------------------------- set-up
-    if (FUSED) face_table(E, ft);
-    __syncthreads();
-    {
-      double tr = 0.0, cc2 = 0.0, fs = 0.0;
-      const double* fp = b.f + E.tri0;
-      for (int p = tid; p < n; p += NTHREADS) {
-        int i, j;
-        node_ij(p, s, i, j);
-        const double cp = node_tri_count(i, j, s) * E.cunit;
-        c[p] = cp;
-        cc2 += cp * cp;
-        if (FUSED || fp32) tr += stencil(i, j, s, E.G, kap).d;
-        if (FUSED) {
-          const double bp = E.cunit * node_tri_sum(i, j, s, [&](int t) { return fp[t]; });
-          bf[p] = bp;
-          fs += bp;
-        }
-      }
-      block_sum3(tr, cc2, fs, red);
-      if (tid == 0) {
-        gam = tr / (n * cc2);
-        colsum[E.NI] = fs;
-      }
-      if (FUSED) face_colsums(E, ft, colsum);
-    }
-    __syncthreads();
-    const double g = gam;
-    T* Lo = nullptr;
-    if (!FUSED && args.Lout && E.mat0 >= 0) Lo = reinterpret_cast<T*>(args.Lout + E.mat0);
-
-    // Initial value of tile (I, J) in the MFMA result layout: Ahat for I < nt,
-    // the transposed right-hand sides Btilde^T for I == nt.
-    auto init_tile = [&](int I, int J) -> V4 {
-      V4 v4;
-      const int cl = lane & 15, grp = lane >> 4;
-      const int q = 16 * J + cl;
-      if (I == nt) {
-        int qi = 0, qj = 0;
-        if (FUSED && q < n) node_ij(q, s, qi, qj);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = Mfma<T>::row(grp, v);
-          double x = 0.0;
-          if (a < r && q < n) x = FUSED ? btilde_tab(E, ft, bf, c, colsum, a, q, qi, qj)
-                                        : args.Btil[E.rhs0 + (int64_t)a * n + q];
-          v4[v] = (T)x;
-        }
-        return v4;
-      }
-      if (FUSED) {
-        const bool band = 16 * (I - J) <= s + 17;
-        Stencil st = {0, 0, 0, 0, 0, 0, 0, 0};
-        int qj = 0;
-        if (band && q < n) {
-          int qi;
-          node_ij(q, s, qi, qj);
-          st = stencil(qi, qj, s, E.G, kap);
-        }
-        const int pE = q + 1, pW = q - 1, pN = q + (s + 1 - qj), pS = q - (s + 2 - qj), pNW = q + (s - qj),
-                  pSE = q - (s + 1 - qj);
-        const double gcq = q < n ? g * c[q] : 0.0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int p = 16 * I + Mfma<T>::row(grp, v);
-          double x;
-          if (p < n && q < n) {
-            x = gcq * c[p];
-            if (band) {
-              x += (p == q) ? st.d : 0.0;
-              x += (p == pE) ? st.e : 0.0;
-              x += (p == pW) ? st.w : 0.0;
-              x += (p == pN) ? st.n : 0.0;
-              x += (p == pS) ? st.so : 0.0;
-              x += (p == pNW) ? st.nw : 0.0;
-              x += (p == pSE) ? st.se : 0.0;
-            }
-          } else {
-            x = (p == q) ? 1.0 : 0.0;
-          }
-          v4[v] = (T)x;
-        }
-      } else {
-        const double* A = args.Ahat + E.mat0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int p = 16 * I + Mfma<T>::row(grp, v);
-          v4[v] = (T)((p < n && q < n) ? A[(int64_t)q * n + p] : (p == q ? 1.0 : 0.0));
-        }
-      }
-      return v4;
-    };
-
-    // ------------------------------------------------------ factorisation
-    for (int j0 = 0; j0 < nt; j0 += PW) {
-      const int pw = nt - j0 < PW ? nt - j0 : PW;
-      V4 acc[RPW][PW];
-      // (a) initial panel: rows are unrolled, the PW columns of a row run in
-      // a loop whose result is moved into its register slot by selects
-      // (a branch chain here would leave the panel array in scratch memory)
-#pragma unroll
-      for (int ri = 0; ri < RPW; ++ri) {
-        const int i = j0 + wave + NW * ri;
-#pragma unroll
-        for (int k = 0; k < PW; ++k) acc[ri][k] = V4{0, 0, 0, 0};
-        if (i <= nt) {
-#pragma unroll 1
-          for (int jj = 0; jj < pw; ++jj) {
-            if (i == nt || i >= j0 + jj) {
-              const V4 v = init_tile(i, j0 + jj);
-#pragma unroll
-              for (int k = 0; k < PW; ++k) acc[ri][k] = jj == k ? v : acc[ri][k];
-            }
-          }
-        }
-      }
-      // (b) earlier tile columns.  The operands of column m + 1 (A operands
-      // in registers, B tiles for the LDS stage) are loaded while the MFMAs
-      // of column m run; one barrier per column (stage buffers alternate).
-      if (j0 > 0) {
-        constexpr int SPT = (PW * TILE + NTHREADS - 1) / NTHREADS;
-        constexpr int NB = RPW <= 5 ? 2 : 1;   // operand buffers (register budget)
-        T ab[NB][RPW][4];
-        T sb[NB][SPT];
-        auto fetch = [&](int m, T (&a)[RPW][4], T (&sv)[SPT]) {
-          if (m >= j0) return;
-#pragma unroll
-          for (int ri = 0; ri < RPW; ++ri) {
-            const int i = j0 + wave + NW * ri;
-            if (i <= nt) {
-              const T* L = tl(i, m);
-#pragma unroll
-              for (int cch = 0; cch < 4; ++cch) a[ri][cch] = ld_rowcol(L, cch, lane);
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < SPT; ++q) {
-            const int idx = tid + q * NTHREADS;
-            if (idx < pw * TILE) sv[q] = tl(j0 + idx / TILE, m)[idx % TILE];
-          }
-        };
-        auto apply = [&](int m, const T (&a)[RPW][4], const T (&sv)[SPT]) {
-          T* st = stage + (m & 1) * PW * TILE;
-#pragma unroll
-          for (int q = 0; q < SPT; ++q) {
-            const int idx = tid + q * NTHREADS;
-            if (idx < pw * TILE) st[idx] = sv[q];
-          }
-          __syncthreads();
-#pragma unroll
-          for (int ri = 0; ri < RPW; ++ri) {
-            const int i = j0 + wave + NW * ri;
-            if (i <= nt) {
-#pragma unroll
-              for (int jj = 0; jj < PW; ++jj) {
-                if (jj < pw && (i == nt || i >= j0 + jj)) {
-                  V4 x = acc[ri][jj];
-#pragma unroll
-                  for (int cch = 0; cch < 4; ++cch)
-                    x = Mfma<T>::op(-a[ri][cch], ld_rowcol(st + jj * TILE, cch, lane), x);
-                  acc[ri][jj] = x;
-                }
-              }
-            }
-          }
-        };
-        if constexpr (NB == 2) {
-          fetch(0, ab[0], sb[0]);
-          fetch(1, ab[1], sb[1]);
-          for (int m = 0; m < j0; m += 2) {
-            apply(m, ab[0], sb[0]);
-            fetch(m + 2, ab[0], sb[0]);
-            if (m + 1 < j0) {
-              apply(m + 1, ab[1], sb[1]);
-              fetch(m + 3, ab[1], sb[1]);
-            }
-          }
-        } else {
-          for (int m = 0; m < j0; ++m) {
-            fetch(m, ab[0], sb[0]);
-            apply(m, ab[0], sb[0]);
-          }
-        }
-      }
-      // (c) factor the panel, one column at a time (run-time loop; the tile
-      // code that touches the register panel matches the column statically)
-#pragma unroll 1
-      for (int jj = 0; jj < pw; ++jj) {
-        const int col = j0 + jj;
-        // diagonal tile (row col is local row jj: wave jj, slot 0)
-        if (wave == jj) {
-#pragma unroll
-          for (int k = 0; k < PW; ++k)
-            if (k == jj) st_acc<T>(Wt, acc[0][k], lane);
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-          const int bj = potrf_c<T>(Wt, Lo, n, col, lane);
-          if (lane == 0 && bj >= 0 && bad < 0) bad = 16 * col + bj;
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-          T* dst = tl(col, col);
-          for (int idx = lane; idx < TILE; idx += 64) dst[idx] = Wt[idx];
-        }
-        __syncthreads();
-        // panel solve L_i,col = C_i,col W^T for the rows below, then the
-        // in-panel update C_i,j -= L_i,col L_j,col^T of the later columns
-#pragma unroll
-        for (int k = 0; k < PW; ++k) {
-          if (k == jj) {
-#pragma unroll
-            for (int ri = 0; ri < RPW; ++ri) {
-              const int i = j0 + wave + NW * ri;
-              if (i > col && i <= nt) {
-                st_acc<T>(scr, acc[ri][k], lane);
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                V4 x = {0, 0, 0, 0};
-#pragma unroll
-                for (int cch = 0; cch < 4; ++cch)
-                  x = Mfma<T>::op(ld_rowcol(scr, cch, lane), ld_rowcol(Wt, cch, lane), x);
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                acc[ri][k] = x;
-                st_acc<T>(tl(i, col), x, lane);
-                if (Lo && i < nt) store_L<T>(Lo, n, i, col, x, lane);
-                if (i < j0 + pw) st_acc<T>(pub + (i - j0) * TILE, x, lane);
-              }
-            }
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PW - 1; ++k) {
-          if (k == jj && jj + 1 < pw) {
-#pragma unroll
-            for (int ri = 0; ri < RPW; ++ri) {
-              const int i = j0 + wave + NW * ri;
-              if (i > col && i <= nt) {
-                st_acc<T>(scr, acc[ri][k], lane);
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                T a[4];
-#pragma unroll
-                for (int cch = 0; cch < 4; ++cch) a[cch] = -ld_rowcol(scr, cch, lane);
-#pragma unroll
-                for (int j2 = k + 1; j2 < PW; ++j2) {
-                  if (j2 < pw && (i == nt || i >= j0 + j2)) {
-                    V4 x = acc[ri][j2];
-#pragma unroll
-                    for (int cch = 0; cch < 4; ++cch) x = Mfma<T>::op(a[cch], ld_rowcol(pub + j2 * TILE, cch, lane), x);
-                    acc[ri][j2] = x;
-                  }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-              }
-            }
-          }
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      __syncthreads();
-    }
-
-    // ------------------------------------------------ solves on the RHS row
-    T* xb = stage;   // two published solution tiles (the staging area is free here)
-    auto backward = [&]() { ll::sweep<T, RPW, true>(tl, nt, xb, scr, wave, lane); };
-    auto forward = [&]() { ll::sweep<T, RPW, false>(tl, nt, xb, scr, wave, lane); };
-    backward();
-    const bool failed = bad >= 0;
-    double* X = args.X + E.rhs0;
-    const int ca = tid >> 4, cl16 = tid & 15;   // 32 groups of 16 lanes; groups 0..15 do column sums
-
-    if (fp32 && !failed) {
-      // --------------------------------------- FP64 refinement (FP32 path)
-      for (int idx = tid; idx < n * r; idx += NTHREADS) {
-        const int a = idx / n, p = idx - a * n;
-        X[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)];
-      }
-      __syncthreads();
-      const double* Btg = FUSED ? nullptr : args.Btil + E.rhs0;
-      int it = 0;
-      for (;; ++it) {
-        {
-          double v = 0.0;
-          if (ca < r)
-            for (int p = cl16; p < n; p += 16) v += c[p] * X[(int64_t)ca * n + p];
-          v = group16_sum(v);
-          if (cl16 == 0 && ca < 16) cx[ca] = v;
-        }
-        __syncthreads();
-        const double anorm = ir_residual<T, FUSED>(E, kap, X, c, cx, g, ft, bf, colsum, Btg,
-                                                   [&](int J) -> T* { return tl(nt, J); }, &wred[0][0][0], red);
-        if (tid == 0) conv = ir_converged(&wred[0][0][0], NW, r, anorm, args.ir_tol);
-        __syncthreads();
-        if (conv || it >= args.max_iters) break;
-        forward();
-        backward();
-        for (int idx = tid; idx < n * r; idx += NTHREADS) {
-          const int a = idx / n, p = idx - a * n;
-          X[idx] += (double)tl(nt, p >> 4)[a * TST + (p & 15)];
-        }
-        __syncthreads();
-      }
-      const bool cvd = conv;
-      if (tid == 0) {
-        if (args.ir_iters) args.ir_iters[e] = it;
-        if (!cvd) args.info[e] = INFO_IR_FALLBACK;
-      }
-      if (!cvd) continue;
-      {
-        double v = 0.0;
-        if (ca < r)
-          for (int p = cl16; p < n; p += 16) v += c[p] * X[(int64_t)ca * n + p];
-        v = group16_sum(v);
-        if (cl16 == 0 && ca < 16) cx[ca] = v * E.inv_area;
-      }
-      __syncthreads();
-      for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] -= cx[idx / n];
-      __syncthreads();
-    } else if (fp32) {
-      if (tid == 0) args.info[e] = INFO_IR_FALLBACK;
-      continue;
-    } else if (failed) {
-      for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] = __builtin_nan("");
-      if (tid == 0) args.info[e] = bad + 1;
-      if (FUSED && args.M) {
-        for (int idx = tid; idx < NImax * NImax; idx += NTHREADS)
-          args.M[(int64_t)e * NImax * NImax + idx] = __builtin_nan("");
-        if (tid < NImax) {
-          args.E[(int64_t)e * NImax + tid] = __builtin_nan("");
-          args.B[(int64_t)e * NImax + tid] = __builtin_nan("");
-        }
-        if (tid == 0) args.F[e] = __builtin_nan("");
-      }
-      continue;
-    } else {
-      {
-        double v = 0.0;
-        if (ca < r)
-          for (int p = cl16; p < n; p += 16) v += c[p] * (double)tl(nt, p >> 4)[ca * TST + (p & 15)];
-        v = group16_sum(v);
-        if (cl16 == 0 && ca < 16) cx[ca] = v * E.inv_area;
-      }
-      __syncthreads();
-      for (int idx = tid; idx < n * r; idx += NTHREADS) {
-        const int a = idx / n, p = idx - a * n;
-        X[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)] - cx[a];
-      }
-      __syncthreads();
-    }
-    if (FUSED && args.M) contrib_element(E, X, ft, colsum[E.NI], NImax, args.M, args.E, args.B, args.F, e);
-  }
-}
-
-// ------------------------------------------------------------------ launch
 int local_ll_rows_per_wave(int nt) {
   const int rows = nt + 1;
   if (rows <= 2 * ll::NW) return 2;
@@ -554,42 +18,28 @@ int local_ll_rows_per_wave(int nt) {
   if (rows <= 10 * ll::NW) return 10;
   return -1;
 }
-int local_ll_panel(bool fp32) { return fp32 ? 4 : 2; }
 
-size_t local_ll_lds_bytes(bool fp32, int n_cap, int f_cap) {
-  const int pw = local_ll_panel(fp32);
+int local_ll_default_panel(bool fp32) { return fp32 ? 4 : 2; }
+
+bool local_ll_has(bool fp32, int pw, int nt) {
+  const int rpw = local_ll_rows_per_wave(nt);
+  if (rpw < 0) return false;
+  if (fp32) return pw == 2 || pw == 4;
+  return pw == 2 || (pw == 4 && rpw <= 3);
+}
+
+size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap) {
   return sizeof(double) * (2 * (size_t)n_cap + (size_t)f_cap) +
          (size_t)(2 * pw + 1 + pw + ll::NW) * TILE * (fp32 ? sizeof(float) : sizeof(double));
 }
 
-template <typename T, bool FUSED, int PW, int RPW>
-static hipError_t launch_ll_t(const BatchDev& d, LocalArgs a, size_t lds, int grid, hipStream_t st) {
-  auto kern = k_local_ll<T, FUSED, PW, RPW>;
-  hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(ll::NTHREADS), lds, st, d, a);
-  return hipGetLastError();
-}
-
-template <typename T, bool FUSED, int PW>
-static hipError_t launch_ll_rpw(int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid, hipStream_t st) {
-  switch (rpw) {
-    case 2: return launch_ll_t<T, FUSED, PW, 2>(d, a, lds, grid, st);
-    case 3: return launch_ll_t<T, FUSED, PW, 3>(d, a, lds, grid, st);
-    case 5: return launch_ll_t<T, FUSED, PW, 5>(d, a, lds, grid, st);
-    case 10: return launch_ll_t<T, FUSED, PW, 10>(d, a, lds, grid, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_local_ll(bool fp32, bool fused, int nt_max, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
-                           hipStream_t st) {
+hipError_t launch_local_ll(bool fp32, bool fused, int pw, int nt_max, const mhm_batch* bt, LocalArgs a, size_t lds,
+                           int grid, hipStream_t st) {
+  if (!local_ll_has(fp32, pw, nt_max)) return hipErrorInvalidValue;
   const int rpw = local_ll_rows_per_wave(nt_max);
   const BatchDev d = to_dev(bt);
-  if (fp32) return fused ? launch_ll_rpw<float, true, 4>(rpw, d, a, lds, grid, st)
-                         : launch_ll_rpw<float, false, 4>(rpw, d, a, lds, grid, st);
-  return fused ? launch_ll_rpw<double, true, 2>(rpw, d, a, lds, grid, st)
-               : launch_ll_rpw<double, false, 2>(rpw, d, a, lds, grid, st);
+  return fp32 ? launch_local_ll_f32(fused, pw, rpw, d, a, lds, grid, st)
+              : launch_local_ll_f64(fused, pw, rpw, d, a, lds, grid, st);
 }
 
 }  // namespace mhm

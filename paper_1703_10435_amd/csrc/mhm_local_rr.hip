@@ -228,7 +228,9 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
 
   V4 acc[S];
 
-  for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
+  const int n_launch = launch_count(args, b.n_elem);
+  for (int k_el = blockIdx.x; k_el < n_launch; k_el += gridDim.x) {
+    const int e = launch_elem(args, k_el);
     __syncthreads();
     if (tid == 0) {
       int st = INFO_OK;

@@ -32,6 +32,39 @@ def run_fused(ctx: abi.Context, db: DeviceBatch, prec: int = abi.MHM_FP64, out: 
     return out
 
 
+def autotune(ctx: abi.Context, db: DeviceBatch, prec: int = abi.MHM_FP64, out: dict | None = None,
+             max_iters: int = 10) -> dict:
+    """Choose the kernel family / panel width per size class by timing
+    (mhm_autotune); the outputs are those of one fused run."""
+    if out is None:
+        out = db.alloc_outputs(three_call=False)
+    ctx.autotune(db, prec, out["X"], out["M"], out["E"], out["B"], out["F"], out["info"], out["ir_iters"],
+                 max_iters)
+    return out
+
+
+def capture_fused(ctx: abi.Context, db: DeviceBatch, prec: int = abi.MHM_FP64, out: dict | None = None,
+                  max_iters: int = 10):
+    """A HIP graph of one fused run (binning, per-class launches, fallback
+    passes); ``graph.launch()`` replays it on the context's stream."""
+    if out is None:
+        out = db.alloc_outputs(three_call=False)
+    g = ctx.graph_create(db, prec, out["X"], out["M"], out["E"], out["B"], out["F"], out["info"], out["ir_iters"],
+                         max_iters)
+    return g, out
+
+
+def run_three_call_bucketed(ctx: abi.Context, sub_batches: list, prec: int = abi.MHM_FP64, outs: list | None = None,
+                            max_iters: int = 10) -> list:
+    """The plain unfused form over a ragged batch: the three calls launched
+    once per size bucket (each bucket a DeviceBatch of its own)."""
+    if outs is None:
+        outs = [db.alloc_outputs(three_call=True) for db in sub_batches]
+    for db, out in zip(sub_batches, outs):
+        run_three_call(ctx, db, prec, out, max_iters)
+    return outs
+
+
 def solve_batch(batch: dict, prec: int = abi.MHM_FP64, mode: str = "fused", ctx: abi.Context | None = None,
                 max_iters: int = 10):
     """Upload a host batch, run it, return per-element results (numpy)."""

@@ -261,12 +261,19 @@ def test_assemble_outputs_match_definition(ctx, which):
         assert ar[e] == pytest.approx(ora["area"], rel=1e-15)
 
 
-def test_factor_output_reproduces_ahat(ctx):
-    b = _random_batch(22, [16, 4, 24], [2, 1, 3], "factor")
-    db, A0, B0, c0, ar, info_a, L0 = _assemble_and_factor(ctx, b)
-    for e in range(b["n_elem"]):
-        n = int(db.n[e])
-        Ah = A0[db.mat_off[e]:db.mat_off[e + 1]].reshape(n, n).T
-        L = np.tril(L0[db.mat_off[e]:db.mat_off[e + 1]].reshape(n, n).T)
-        err = np.abs(L @ L.T - Ah).max() / np.abs(Ah).max()
-        assert err < 1e-14, (e, err)
+@pytest.mark.parametrize("sizes", [[16, 4, 24], [34, 3, 48]])
+def test_factor_output_reproduces_ahat(ctx, sizes):
+    """L L^T = Ahat for the FP64 factor written in place (register, LDS and
+    left-looking kernels), and the FP32 factor within FP32 accuracy."""
+    b = _random_batch(22, sizes, [2, 1, 3], "factor")
+    for prec, tol in ((0, 1e-14), (1, 1e-6)):
+        db, A0, B0, c0, ar, info_a, L0 = _assemble_and_factor(ctx, b, prec)
+        for e in range(b["n_elem"]):
+            n = int(db.n[e])
+            Ah = A0[db.mat_off[e]:db.mat_off[e + 1]].reshape(n, n).T
+            seg = L0[db.mat_off[e]:db.mat_off[e + 1]]
+            if prec == 1:   # FP32 factor in the first n*n floats of the slot
+                seg = seg.view(np.float32)[:n * n].astype(np.float64)
+            L = np.tril(seg.reshape(n, n).T)
+            err = np.abs(L @ L.T - Ah).max() / np.abs(Ah).max()
+            assert err < tol, (prec, e, err)
