@@ -407,7 +407,8 @@ __device__ __forceinline__ double ir_residual(const Elem& E, KAP kap, const doub
 
 // Normwise backward-error test of every column from the per-wave maxima.
 // Normwise backward error of the current iterate, max over the columns:
-// max_p |r_pa| / (||Ahat||_inf max_p |x_pa| + max_p |b_pa|)  (NaN -> inf).
+// max_p |r_pa| / (||Ahat||_inf max_p |x_pa| + max_p |b_pa|)  (0 for a zero
+// residual, inf for NaN).
 __device__ __forceinline__ double ir_backward_error(const double* wred, int nwaves, int r, double anorm) {
   double be = 0.0;
   for (int a = 0; a < r; ++a) {
@@ -417,7 +418,8 @@ __device__ __forceinline__ double ir_backward_error(const double* wred, int nwav
       xm = fmax(xm, wred[(w * 3 + 1) * 16 + a]);
       bm = fmax(bm, wred[(w * 3 + 2) * 16 + a]);
     }
-    const double e = rm / (anorm * xm + bm);
+    // a zero residual is converged (a zero right-hand side has zero solution)
+    const double e = rm == 0.0 ? 0.0 : rm / (anorm * xm + bm);
     be = e == e ? fmax(be, e) : __builtin_inf();
   }
   return be;
@@ -425,17 +427,20 @@ __device__ __forceinline__ double ir_backward_error(const double* wred, int nwav
 
 // Refinement decision after step `it` (0 = the first solve): 1 converged,
 // 0 continue, -1 give up.  Refinement contracts the error by a roughly
-// constant factor per step; when the observed factor (from the previous
-// step's backward error `prev`) says the tolerance cannot be reached within
-// the step budget, stop now and leave the element to the FP64 pass.
+// constant factor per step; when the backward error grows, or from the
+// second correction on the observed factor (against the previous step's
+// backward error `prev`) says the tolerance cannot be reached within the
+// step budget, stop now and leave the element to the FP64 pass.
 __device__ __forceinline__ int ir_decide(double be, double prev, int it, int max_iters, double tol) {
   if (be <= tol) return 1;
   if (it >= max_iters) return -1;
   if (it >= 1) {
     const double rho = be / prev;
-    if (!(rho < 1.0)) return -1;
-    const double need = log(tol / be) / log(rho);
-    if (need > (double)(max_iters - it)) return -1;
+    if (!(rho < 1.0)) return -1;   // no contraction at all
+    if (it >= 2) {                 // the first step's contraction can be atypical
+      const double need = log(tol / be) / log(rho);
+      if (need > (double)(max_iters - it)) return -1;
+    }
   }
   return 0;
 }

@@ -130,6 +130,9 @@ def test_c3_fp32_refinement_sampled(ctx):
     its = np.array([r["ir_iters"] for r in res])
     say(f"  C3 fallbacks {int(np.sum(info == -1))} / {b['n_elem']}, IR steps min {its.min()} max {its.max()}")
     assert np.all((info == 0) | (info == -1))
+    # only elements crossed by a K = 1e4 channel are too ill-conditioned for
+    # FP32 factors; the others must converge in refinement
+    assert np.mean(info == -1) < 0.5, int(np.sum(info == -1))
     _check(res, b, [0, 5, 63, 127], 1, "C3 FP32+IR fused")
 
 
@@ -266,14 +269,17 @@ def test_factor_output_reproduces_ahat(ctx, sizes):
     """L L^T = Ahat for the FP64 factor written in place (register, LDS and
     left-looking kernels), and the FP32 factor within FP32 accuracy."""
     b = _random_batch(22, sizes, [2, 1, 3], "factor")
-    for prec, tol in ((0, 1e-14), (1, 1e-6)):
+    for prec in (0, 1):
         db, A0, B0, c0, ar, info_a, L0 = _assemble_and_factor(ctx, b, prec)
         for e in range(b["n_elem"]):
             n = int(db.n[e])
             Ah = A0[db.mat_off[e]:db.mat_off[e + 1]].reshape(n, n).T
             seg = L0[db.mat_off[e]:db.mat_off[e + 1]]
-            if prec == 1:   # FP32 factor in the first n*n floats of the slot
-                seg = seg.view(np.float32)[:n * n].astype(np.float64)
+            if prec == 1:   # FP32 factor in the first n*n floats of the slot (upper part unspecified)
+                with np.errstate(invalid="ignore", over="ignore"):
+                    seg = seg.view(np.float32)[:n * n].astype(np.float64)
             L = np.tril(seg.reshape(n, n).T)
             err = np.abs(L @ L.T - Ah).max() / np.abs(Ah).max()
-            assert err < tol, (prec, e, err)
+            # Cholesky backward error: |L L^T - A| <= (n+1) u |L| |L^T| / (1 - (n+1) u)
+            tol = 1e-14 if prec == 0 else 4.0 * (n + 1) * 2.0 ** -24
+            assert err < tol, (prec, e, err, tol)
