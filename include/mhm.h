@@ -173,6 +173,31 @@ mhm_status mhm_local_batch_run(mhm_ctx ctx, const mhm_batch* batch, mhm_prec pre
                                double* X, double* M, double* E, double* B, double* F,
                                int32_t* info, int32_t* ir_iters, int max_iters);
 
+/* Factor reuse (Section 3: the local matrix is factored once and reused
+ * for further load vectors, e.g. over time steps): mhm_local_batch_run with
+ * each element's factor kept in a caller-owned device store.
+ *   factors       device store; element e's factor occupies
+ *                 mhm_factor_bytes(s_e, prec) bytes at byte offset
+ *                 factor_off[e] (a multiple of 256; regions of elements in
+ *                 one call must not overlap).  The layout is internal
+ *                 (16x16 tiles of L with the inverse diagonal blocks) and
+ *                 tied to prec.
+ *   factor_state  [n_elem] device int8: 0 = factor Ahat and store the factor,
+ *                 1 = reuse the stored factor of an earlier call for the same
+ *                 element data (s, geometry, kappa); only the right-hand
+ *                 sides (any l) are built and solved.
+ * A stored factor is valid after a call that reported info[e] == 0 for it
+ * (after info > 0 the store holds no factor; after -1 it holds the FP32
+ * factor whose refinement did not converge, which a reuse would again
+ * recompute in FP64).  Requires s <= 48 (the left-looking kernel).
+ * Outputs as mhm_local_batch_run. */
+size_t mhm_factor_bytes(int s, mhm_prec prec);
+mhm_status mhm_local_batch_run_cached(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec,
+                                      void* factors, const int64_t* factor_off,
+                                      const int8_t* factor_state,
+                                      double* X, double* M, double* E, double* B, double* F,
+                                      int32_t* info, int32_t* ir_iters, int max_iters);
+
 /* Batching: choose, per size class present in the batch, the kernel family
  * and panel width ("tile shape": register-resident tiles, LDS tiles,
  * left-looking panels of 2 or 4 tile columns, or the right-looking
@@ -205,6 +230,77 @@ mhm_status mhm_graph_create(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec,
 mhm_status mhm_graph_launch(mhm_graph graph);
 /* Waits for the context's stream, then frees the graph and its workspace. */
 mhm_status mhm_graph_destroy(mhm_graph graph);
+
+/* ------------------------------------------------------------- serving
+ * A request loop for local problems that arrive one at a time (the
+ * solveLocalProblem calls of Algorithm 1 issued as a stream).  A worker
+ * thread keeps up to in_flight launches on the device, each on its own
+ * stream with its own context; a free launch slot takes every queued
+ * request that fits (continuous batching, arrival order) and runs them as
+ * one ragged mhm_local_batch_run_cached.  Factors of keyed requests stay in
+ * a device LRU cache, so a repeated key solves only its new right-hand sides
+ * (any l).  All device memory of the server (slot buffers, an upper bound of
+ * the workspaces, the factor arena) fits in hbm_budget; a request whose
+ * factor does not fit after evicting every unpinned factor waits until
+ * running launches finish. */
+typedef struct mhm_server_s* mhm_server;
+
+typedef struct {
+  int32_t prec;               /* mhm_prec of every request                     */
+  int32_t max_iters;          /* refinement step limit (MHM_FP32_IR)           */
+  int32_t max_batch;          /* requests per launch, 1..65536                 */
+  int32_t in_flight;          /* launches on the device at once, 1..8          */
+  int32_t s_max;              /* largest s accepted, <= 48                     */
+  int32_t l_max;              /* largest l accepted, <= MHM_L_LIMIT            */
+  int32_t reuse;              /* nonzero: keep factors of keyed requests       */
+  int32_t reserved;
+  uint64_t hbm_budget;        /* device bytes the server may hold              */
+  uint64_t factor_cache_max;  /* cap on the factor arena (0: rest of budget)   */
+} mhm_server_config;
+
+typedef struct {
+  uint64_t key_hi, key_lo;    /* content key of (geometry, s, kappa); 0,0 = never
+                                 reused.  Equal keys must mean equal data.    */
+  int32_t s, l;
+  double vert[6];             /* as in mhm_batch                               */
+  int8_t sigma[3], flip[3];
+  int8_t pad[2];
+  const double* kappa;        /* HOST [s*s], copied by mhm_server_submit       */
+  const double* f;            /* HOST [s*s]                                    */
+  double t_arrival;           /* caller's arrival time, mhm_server_now() clock */
+} mhm_request;
+
+typedef struct {
+  uint64_t ticket;
+  int32_t info, ir_iters;     /* as in mhm_local_batch_run                     */
+  int32_t cache_hit;          /* the factor came from the cache                */
+  int32_t s, l, n, r;
+  int32_t pad;
+  double t_arrival, t_done;   /* t_done: results on the host (server clock)    */
+  const double* X;            /* HOST n x r column-major; M NI x NI, E, B NI   */
+  const double* M;            /* (NI = r - 1); valid until the next poll       */
+  const double* E;
+  const double* B;
+  double F;
+} mhm_result;
+
+typedef struct {
+  int64_t submitted, completed, launches, cache_hits, ir_fallbacks, errors;
+  int64_t queued, max_batch_seen, cache_entries, cache_bytes, cache_evictions;
+  int64_t arena_bytes, fixed_bytes;
+} mhm_server_stats;
+
+double mhm_server_now(void);   /* seconds on the server's monotonic clock */
+mhm_status mhm_server_create(int device, const mhm_server_config* cfg, mhm_server* server);
+/* Queue n requests; tickets[k] (may be NULL) identifies request k's result. */
+mhm_status mhm_server_submit(mhm_server server, const mhm_request* reqs, int n, uint64_t* tickets);
+/* Move up to max finished results into out; returns how many (-1 on a bad
+ * argument).  Result arrays stay valid until the next poll. */
+int mhm_server_poll(mhm_server server, mhm_result* out, int max);
+mhm_status mhm_server_stats_get(mhm_server server, mhm_server_stats* stats);
+const char* mhm_server_last_error(mhm_server server);
+/* Stops the worker (queued requests are dropped), frees everything. */
+mhm_status mhm_server_destroy(mhm_server server);
 
 #ifdef __cplusplus
 }

@@ -183,3 +183,30 @@ def request_stream(n_req: int, rate: float = 20000.0, reuse_p: float = 0.5):
 
 def c5_field():
     return GaussianField(seed=5000, ell=0.05)
+
+
+def served_requests(n_req: int, rate: float = 20000.0, reuse_p: float = 0.5) -> dict:
+    """The C5 stream with its element data: ``keys`` is a batch holding each
+    distinct (element, s) once (K = exp(2 g), g the seeded unit Gaussian
+    field of correlation length 0.05; f manufactured), and per request
+    ``key_idx``, ``l`` and the arrival time ``t`` (seconds from 0)."""
+    mesh, reqs = request_stream(n_req, rate, reuse_p)
+    uniq = {}
+    key_idx = np.empty(n_req, dtype=np.int64)
+    for k, q in enumerate(reqs):
+        key_idx[k] = uniq.setdefault((q["elem"], q["s"]), len(uniq))
+    pairs = sorted(uniq.items(), key=lambda kv: kv[1])
+    elems = np.array([p[0][0] for p in pairs], dtype=np.int64)
+    s_arr = np.array([p[0][1] for p in pairs], dtype=np.int32)
+    g = c5_field()
+    keys = build_batch(mesh, elems, s_arr, np.full(elems.size, 3), lambda p: np.exp(2.0 * g(p)),
+                       manufactured_source, "C5-keys")
+    return dict(keys=keys, key_idx=key_idx, l=np.array([q["l"] for q in reqs], dtype=np.int32),
+                t=np.array([q["t_arrival"] for q in reqs]))
+
+
+def request_batch(stream: dict, k: int) -> dict:
+    """Request k of a served stream as a one-element batch (for the oracle)."""
+    b = sub_batch(stream["keys"], [int(stream["key_idx"][k])])
+    b["l"] = np.array([stream["l"][k]], dtype=np.int32)
+    return b

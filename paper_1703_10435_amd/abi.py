@@ -22,6 +22,7 @@ EXPORTS = (
     "mhm_create", "mhm_destroy", "mhm_set_stream", "mhm_last_error", "mhm_sync", "mhm_workspace_bytes",
     "mhm_local_assemble", "mhm_local_factor_solve", "mhm_skeleton_contrib", "mhm_local_batch_run",
     "mhm_autotune", "mhm_tune_report", "mhm_graph_create", "mhm_graph_launch", "mhm_graph_destroy",
+    "mhm_factor_bytes", "mhm_local_batch_run_cached",
 )
 
 
@@ -73,6 +74,8 @@ def load(path: str = LIB_PATH):
         "mhm_graph_create": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(vp)]),
         "mhm_graph_launch": (i32, [vp]),
         "mhm_graph_destroy": (i32, [vp]),
+        "mhm_factor_bytes": (ctypes.c_size_t, [i32, i32]),
+        "mhm_local_batch_run_cached": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -80,6 +83,11 @@ def load(path: str = LIB_PATH):
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def factor_bytes(s: int, prec: int) -> int:
+    """Device bytes of one element's stored factor (mhm_factor_bytes)."""
+    return int(load().mhm_factor_bytes(s, prec))
 
 
 def _ptr(t):
@@ -149,6 +157,12 @@ class Context:
     def autotune(self, batch, prec, X, M, E, B, F, info, ir_iters=None, max_iters: int = 10):
         self._check(self.lib.mhm_autotune(self.h, ctypes.byref(batch.desc), prec, _ptr(X), _ptr(M), _ptr(E),
                                           _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters), max_iters))
+
+    def local_batch_run_cached(self, batch, prec, factors, factor_off, factor_state, X, M, E, B, F, info,
+                              ir_iters=None, max_iters: int = 10):
+        self._check(self.lib.mhm_local_batch_run_cached(
+            self.h, ctypes.byref(batch.desc), prec, _ptr(factors), _ptr(factor_off), _ptr(factor_state), _ptr(X),
+            _ptr(M), _ptr(E), _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters), max_iters))
 
     def tune_report(self) -> str:
         n = int(self.lib.mhm_tune_report(self.h, None, 0))

@@ -120,7 +120,8 @@ struct Plan {
   int64_t ws_slot = 0;
 };
 
-Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_cap, Choice ch, bool listed) {
+Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_cap, Choice ch, bool listed,
+              bool cached = false) {
   Plan p;
   p.fp32 = fp32;
   p.fused = fused;
@@ -152,6 +153,7 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
       p.lds = mhm::local_ll_lds_bytes(fp32, ch.pw, p.n_cap, p.f_cap);
       p.grid = slots;
       p.tile_cap += p.nt;   // the diagonal factor tiles kept for the factor output
+      if (cached) p.tile_cap = p.nt;   // factor in the caller's store: the RHS row only
       p.ws_slot = (int64_t)p.tile_cap * mhm::TILE_WORDS;
       break;
     default:
@@ -161,7 +163,7 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
       p.ws_slot = (int64_t)p.tile_cap * mhm::TILE_WORDS;
       break;
   }
-  p.ok = p.ok && p.lds + kStaticLds <= c->lds_limit;
+  p.ok = p.ok && p.lds + kStaticLds <= c->lds_limit && (!cached || ch.fam == FAM_LL);
   p.ws_need = align_up((size_t)p.grid * (size_t)p.ws_slot * tsz);
   return p;
 }
@@ -201,7 +203,8 @@ struct RunPlan {
 
 // `over`: force this choice for every class (tuning); otherwise the tuned
 // or default choice per class.
-RunPlan make_run_plan(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, const Choice* over) {
+RunPlan make_run_plan(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, const Choice* over,
+                      bool cached = false) {
   RunPlan rp;
   const int s_lo = b->s_min > 0 ? b->s_min : 1;
   const int c_lo = class_of(s_lo), c_hi = class_of(b->s_max);
@@ -214,9 +217,13 @@ RunPlan make_run_plan(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused
     r.cls = k;
     r.s_cap = rp.listed ? std::min(kClassHi[k], b->s_max) : b->s_max;
     Choice ch = over ? *over : c->tuned[k][fp32][fused];
-    if (ch.fam < 0 || !plan_for(c, b, fp32, fused, r.s_cap, ch, rp.listed).ok)
+    if (cached) {
+      // stored factors: the left-looking kernel (tuned panel width if any)
+      if (ch.fam != FAM_LL) ch = Choice{FAM_LL, mhm::local_ll_default_panel(fp32)};
+    } else if (ch.fam < 0 || !plan_for(c, b, fp32, fused, r.s_cap, ch, rp.listed).ok) {
       ch = default_choice(c, b, fp32, fused, r.s_cap, rp.listed);
-    r.main = plan_for(c, b, fp32, fused, r.s_cap, ch, rp.listed);
+    }
+    r.main = plan_for(c, b, fp32, fused, r.s_cap, ch, rp.listed, cached);
     if (fp32) r.fb = fallback_plan(c, b, r.s_cap, rp.listed);
     r.ws_off = off;
     off += std::max(r.main.ws_need, fp32 ? r.fb.ws_need : 0);
@@ -265,6 +272,9 @@ struct RunIO {
   int32_t* info = nullptr;
   int32_t* ir_iters = nullptr;
   int max_iters = 0;
+  void* fac = nullptr;              // factor store (left-looking kernel only)
+  const int64_t* fac_off = nullptr;
+  const int8_t* fac_state = nullptr;
 };
 
 hipError_t launch_plan(const Plan& p, const mhm_batch* b, const mhm::LocalArgs& a, hipStream_t st) {
@@ -299,6 +309,9 @@ mhm::LocalArgs local_args(const Plan& p, const RunIO& io, void* ws, const int32_
   a.k_cap = p.k_cap;
   a.elist = elist;
   a.ecount = ecount;
+  a.fac = io.fac;
+  a.fac_off = io.fac_off;
+  a.fac_state = io.fac_state;
   return a;
 }
 
@@ -313,6 +326,9 @@ mhm_status enqueue_class(mhm_ctx c, const ClassRun& r, const mhm_batch* b, const
     RunIO f = io;
     f.Ahat = nullptr;
     f.Btil = nullptr;
+    f.fac = nullptr;   // the FP64 recomputation does not store its factor
+    f.fac_off = nullptr;
+    f.fac_state = nullptr;
     if (!r.main.fused) f.M = f.E = f.B = f.F = nullptr;
     mhm::LocalArgs fa = local_args(r.fb, f, ws + r.ws_off, elist, ecount);
     fa.only_fallback = 1;
@@ -370,7 +386,11 @@ mhm_status enqueue_run(mhm_ctx c, const RunPlan& rp, const mhm_batch* b, const R
 }
 
 mhm_status run_local(mhm_ctx c, const mhm_batch* b, mhm_prec prec, bool fused, const RunIO& io) {
-  const RunPlan rp = make_run_plan(c, b, prec == MHM_FP32_IR, fused, nullptr);
+  const bool cached = io.fac != nullptr;
+  const RunPlan rp = make_run_plan(c, b, prec == MHM_FP32_IR, fused, nullptr, cached);
+  if (cached)
+    for (int i = 0; i < rp.n_runs; ++i)
+      if (!rp.run[i].main.ok) return fail(c, MHM_E_UNSUPPORTED, "stored factors need s <= 48");
   mhm_status st = ensure_ws(c, rp.ws_total);
   if (st != MHM_OK) return st;
   return enqueue_run(c, rp, b, io, c->ws, c->stream);
@@ -575,6 +595,29 @@ mhm_status mhm_local_batch_run(mhm_ctx c, const mhm_batch* b, mhm_prec prec, dou
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   return run_local(c, b, prec, true, fused_io(X, M, E, B, F, info, ir_iters, max_iters));
+}
+
+size_t mhm_factor_bytes(int s, mhm_prec prec) {
+  if (s < 1 || s > MHM_S_LIMIT) return 0;
+  const int nt = (n_of(s) + 15) / 16;
+  const size_t tsz = prec == MHM_FP32_IR ? sizeof(float) : sizeof(double);
+  return align_up((size_t)(nt * (nt + 1) / 2) * mhm::TILE_WORDS * tsz);
+}
+
+mhm_status mhm_local_batch_run_cached(mhm_ctx c, const mhm_batch* b, mhm_prec prec, void* factors,
+                                      const int64_t* factor_off, const int8_t* factor_state, double* X, double* M,
+                                      double* E, double* B, double* F, int32_t* info, int32_t* ir_iters,
+                                      int max_iters) {
+  mhm_status st = check_fused(c, b, prec, X, M, E, B, F, info);
+  if (st != MHM_OK || b->n_elem == 0) return st;
+  if (!factors || !factor_off || !factor_state) return fail(c, MHM_E_ARG, "factors, factor_off and factor_state are required");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  RunIO io = fused_io(X, M, E, B, F, info, ir_iters, max_iters);
+  io.fac = factors;
+  io.fac_off = factor_off;
+  io.fac_state = factor_state;
+  return run_local(c, b, prec, true, io);
 }
 
 mhm_status mhm_autotune(mhm_ctx c, const mhm_batch* b, mhm_prec prec, double* X, double* M, double* E, double* B,

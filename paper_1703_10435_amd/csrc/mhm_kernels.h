@@ -30,6 +30,11 @@ struct LocalArgs {
   int k_cap;            // LDS doubles reserved for kappa (fused, LDS mode)
   const int32_t* elist; // if set: process elements elist[0 .. *ecount) instead of 0 .. n_elem
   const int32_t* ecount;
+  // factor store (left-looking kernel): element e's factor tiles at byte
+  // offset fac_off[e] of fac; fac_state[e] 0 = factor and store, 1 = reuse
+  void* fac;
+  const int64_t* fac_off;
+  const int8_t* fac_state;
 };
 
 // Element k of a launch (identity, or through the element list of a size class).

@@ -173,7 +173,8 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
       } else {
         const bool good = load_elem(b, e, E) && E.rhs0 >= 0 && (FUSED || E.mat0 >= 0);
         if (!good) st = INFO_BAD_DESC;
-        else if ((E.nt * (E.nt + 1)) / 2 + 2 * E.nt > args.tile_cap || E.n > args.n_cap || E.nt + 1 > NW * RPW ||
+        else if ((args.fac ? E.nt : (E.nt * (E.nt + 1)) / 2 + 2 * E.nt) > args.tile_cap || E.n > args.n_cap ||
+                 E.nt + 1 > NW * RPW || (args.fac && args.fac_off[e] < 0) ||
                  (FUSED && E.NI * (E.s + 1) > args.f_cap))
           st = INFO_TOO_LARGE;
         ok = st == INFO_OK;
@@ -195,9 +196,18 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
     T* pub = Wt + TILE;                                  // PW published panel tiles
     T* scr = pub + PW * TILE + wave * TILE;              // this wave's scratch tile
     T* ws = reinterpret_cast<T*>(args.ws) + (int64_t)blockIdx.x * args.ws_slot;
-    auto tl = [&](int I, int J) -> T* { return ws + (int64_t)((I * (I + 1)) / 2 + J) * TILE; };
-    // L_jj tiles (factor output only), after the lower triangle and the RHS row
-    auto ldiag = [&](int J) -> T* { return ws + (int64_t)((nt * (nt + 1)) / 2 + nt + J) * TILE; };
+    // Tiles of the factor (lower triangle, W_jj = L_jj^{-1} on the diagonal):
+    // in the workgroup's workspace slot, or in the caller's factor store
+    // (kept for later right-hand sides), with the right-hand-side row then
+    // alone in the slot.
+    T* Lb = args.fac ? reinterpret_cast<T*>(static_cast<char*>(args.fac) + args.fac_off[e]) : ws;
+    T* rhs_row = args.fac ? ws : ws + (int64_t)((nt * (nt + 1)) / 2) * TILE;
+    const bool reuse = args.fac && args.fac_state && args.fac_state[e] == 1;
+    auto tl = [&](int I, int J) -> T* {
+      return I == nt ? rhs_row + (int64_t)J * TILE : Lb + (int64_t)((I * (I + 1)) / 2 + J) * TILE;
+    };
+    // L_jj tiles (factor output only), after the right-hand-side row
+    auto ldiag = [&](int J) -> T* { return rhs_row + (int64_t)(nt + J) * TILE; };
     const double* kapg = b.kappa + E.tri0;
     auto kap = [&](int t) -> double { return kapg[t]; };
 
@@ -294,8 +304,19 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
       return v4;
     };
 
+    T* xb = stage;   // two published solution tiles of the sweeps (staging area)
+    auto backward = [&]() { ll::sweep<T, RPW, true>(tl, nt, xb, scr, wave, lane); };
+    auto forward = [&]() { ll::sweep<T, RPW, false>(tl, nt, xb, scr, wave, lane); };
+
     // ------------------------------------------------------ factorisation
-    for (int j0 = 0; j0 < nt; j0 += PW) {
+    if (reuse) {
+      // stored factor: only the new right-hand sides, Y = L^{-1} Btilde
+      for (int J = wave; J < nt; J += NW) st_acc<T>(tl(nt, J), init_tile(nt, J), lane);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __syncthreads();
+      forward();
+    }
+    for (int j0 = 0; j0 < (reuse ? 0 : nt); j0 += PW) {
       const int pw = nt - j0 < PW ? nt - j0 : PW;
       V4 acc[RPW][PW];
       // (a) initial panel: rows are unrolled, the PW columns of a row run in
@@ -478,9 +499,6 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
     }
 
     // ------------------------------------------------ solves on the RHS row
-    T* xb = stage;   // two published solution tiles (the staging area is free here)
-    auto backward = [&]() { ll::sweep<T, RPW, true>(tl, nt, xb, scr, wave, lane); };
-    auto forward = [&]() { ll::sweep<T, RPW, false>(tl, nt, xb, scr, wave, lane); };
     backward();
     const bool failed = bad >= 0;
     double* X = args.X + E.rhs0;

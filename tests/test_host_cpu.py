@@ -24,10 +24,11 @@ def _declared():
 
 
 def test_library_exports_every_declared_symbol():
+    from paper_1703_10435_amd import serve
     path = ensure_built()
     lib = ctypes.CDLL(path)
     names = _declared()
-    assert set(names) == set(abi.EXPORTS)
+    assert set(names) == set(abi.EXPORTS) | set(serve.SERVER_EXPORTS)
     for name in names:
         assert hasattr(lib, name), name
 
@@ -42,9 +43,33 @@ def test_missing_library_fails_loudly(tmp_path):
         abi._lib = saved
 
 
-def test_descriptor_struct_matches_header_layout():
-    # 4 int32, 11 pointers, 4 int64 on LP64
-    assert ctypes.sizeof(abi.mhm_batch) == 16 + 11 * 8 + 4 * 8
+def test_structs_match_header_layout(tmp_path):
+    """sizeof and every field offset of the ctypes mirrors against the C
+    compiler's view of include/mhm.h."""
+    import shutil
+    import subprocess
+    from paper_1703_10435_amd import serve
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"mhm_batch": abi.mhm_batch, "mhm_server_config": serve.ServerConfig, "mhm_request": serve.Request,
+               "mhm_result": serve.Result, "mhm_server_stats": serve.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mhm.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in mirrors.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_layout_offsets():
