@@ -93,6 +93,20 @@ def _pool_init(batch):
     os.environ["OMP_NUM_THREADS"] = "1"
 
 
+def oracle_solve(batch, e):
+    """The FP64 oracle's results for one element (error checks)."""
+    from oracle import local
+    return local.solve_element(batch, e)
+
+
+def oracle_cond(ora):
+    """2-norm condition number of Ahat = A + gamma c c^T (gamma = tr(A)/(n c^T c))
+    from the oracle's A and c."""
+    A, c = ora["A"], ora["c"]
+    n = A.shape[0]
+    return float(np.linalg.cond(A + (np.trace(A) / (n * (c @ c))) * np.outer(c, c)))
+
+
 def cpu_baseline(batch, sample_idx, cores):
     """Time the FP64 oracle (one element per task, one thread per process) on
     a bounded sample of the workload; return rate and its results."""
@@ -106,6 +120,131 @@ def cpu_baseline(batch, sample_idx, cores):
     cpu = sum(o[1] for o in out)
     return dict(rate=len(sample_idx) / wall, wall=wall, cpu_seconds=cpu,
                 results={o[0]: dict(X=o[2], M=o[3], E=o[4], B=o[5], F=o[6]) for o in out})
+
+
+# ----------------------------------------------------------- further legs
+def _ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def _rel_err(gpu, ora):
+    """Max-norm relative error of X (whole n x r block) and of the
+    contribution block (M, B, E, F), the larger of the two."""
+    ex = np.max(np.abs(gpu["X"] - ora["X"])) / max(np.max(np.abs(ora["X"])), 1e-300)
+    blk = lambda r: np.concatenate([np.ravel(r["M"]), np.ravel(r["B"]), np.ravel(r["E"]), [r["F"]]])  # noqa: E731
+    eb = np.max(np.abs(blk(gpu) - blk(ora))) / max(np.max(np.abs(blk(ora))), 1e-300)
+    return float(max(ex, eb))
+
+
+def _batched_leg(torch, ctx, name, sample_per_size, checks, reps=3):
+    """FP32+IR batched form (autotuned, one HIP-graph launch) against the
+    plain FP64 form (the three calls per size bucket, unfused, no graph)."""
+    from mhm_inputs import configs
+    from paper_1703_10435_amd import abi, engine
+    from paper_1703_10435_amd.batch import DeviceBatch
+    b = configs.make(name)
+    db = DeviceBatch(b)
+    E = b["n_elem"]
+    rng = np.random.default_rng(9)
+    idx = np.concatenate([rng.choice(np.flatnonzero(b["s"] == s), size=sample_per_size, replace=False)
+                          for s in np.unique(b["s"])])
+    leg = {"n_elem": E, "s": sorted(int(x) for x in np.unique(b["s"]))}
+    for prec, tag in ((abi.MHM_FP32_IR, "fp32_ir"), (abi.MHM_FP64, "fp64")):
+        o = db.alloc_outputs(three_call=False)
+        engine.autotune(ctx, db, prec, o)
+        g, go = engine.capture_fused(ctx, db, prec)
+        ms = _ms(torch, g.launch, reps)
+        g.close()
+        info = go["info"].cpu().numpy()[:E]
+        its = go["ir_iters"].cpu().numpy()[:E]
+        leg[f"{tag}_graph_ms"] = ms
+        leg[f"{tag}_graph_problems_per_s"] = E / (ms * 1e-3)
+        leg[f"{tag}_fallbacks"] = int(np.sum(info == -1))
+        leg[f"{tag}_bad"] = int(np.sum((info != 0) & (info != -1)))
+        if prec == abi.MHM_FP32_IR:
+            leg["fp32_ir_steps_mean"] = float(its[info == 0].mean()) if np.any(info == 0) else None
+        res = db.unpack(go)
+        checks += [(name, f"{tag}_max_rel_err_sampled", b, int(e), 0, res[int(e)]) for e in idx]
+        leg[f"{tag}_tuning"] = ctx.tune_report()
+    subs = [DeviceBatch(configs.sub_batch(b, np.flatnonzero(b["s"] == s))) for s in np.unique(b["s"])]
+    outs = [d.alloc_outputs(three_call=True) for d in subs]
+    ms3 = _ms(torch, lambda: engine.run_three_call_bucketed(ctx, subs, abi.MHM_FP64, outs), reps)
+    leg["fp64_three_call_per_bucket_ms"] = ms3
+    leg["fp64_three_call_problems_per_s"] = E / (ms3 * 1e-3)
+    leg["fp32_ir_batched_vs_plain_fp64"] = ms3 / leg["fp32_ir_graph_ms"]
+    leg["sample"] = f"{len(idx)} elements ({sample_per_size} per s) against the FP64 oracle"
+    del outs, subs, db
+    torch.cuda.empty_cache()
+    return leg
+
+
+def _serve_leg(seconds, checks, rate=20000.0):
+    """C5: open-loop Poisson stream through the serving runtime."""
+    from mhm_inputs import configs
+    from paper_1703_10435_amd import abi
+    from paper_1703_10435_amd.serve import Server, content_key, run_open_loop
+    n = int(rate * seconds)
+    st = configs.served_requests(n, rate=rate)
+    keys = st["keys"]
+    kk = [content_key(keys["vert"][e], int(keys["s"][e]), keys["kappa"][keys["tri_off"][e]:keys["tri_off"][e + 1]])
+          for e in range(keys["n_elem"])]
+    reqs = []
+    for k in range(n):
+        e = int(st["key_idx"][k])
+        o0, o1 = keys["tri_off"][e], keys["tri_off"][e + 1]
+        reqs.append(dict(s=int(keys["s"][e]), l=int(st["l"][k]), vert=keys["vert"][e], sigma=keys["sigma"][e],
+                         flip=keys["flip"][e], kappa=keys["kappa"][o0:o1], f=keys["f"][o0:o1], key=kk[e]))
+    srv = Server(prec=abi.MHM_FP32_IR, max_batch=1024, in_flight=4, s_max=48, l_max=3, reuse=True,
+                 hbm_budget=64 << 30)
+    try:
+        run_open_loop(srv, reqs[:256], np.zeros(256))          # warm-up burst (not timed)
+        warm = srv.stats()
+        out = run_open_loop(srv, reqs, st["t"], copy_arrays=True)
+        s = srv.stats()
+    finally:
+        srv.close()
+    lat = out["latency"]
+    rng = np.random.default_rng(11)
+    for k in rng.choice(n, size=8, replace=False):
+        checks.append(("C5", "max_rel_err_sampled", configs.request_batch(st, int(k)), 0, int(k),
+                       out["results"][int(k)]))
+    return {"requests": n, "arrival_rate_per_s": rate, "throughput_per_s": out["throughput"],
+            "p50_ms": float(np.median(lat) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "cache_hit_rate": (s["cache_hits"] - warm["cache_hits"]) / n,
+            "launches": s["launches"] - warm["launches"], "ir_fallbacks": s["ir_fallbacks"] - warm["ir_fallbacks"],
+            "hbm_budget_gb": 64, "factor_arena_gb": s["arena_bytes"] / 2 ** 30, "errors": s["errors"],
+            "sample": "8 requests against the FP64 oracle",
+            "latency": "scheduled arrival to contribution on the host"}
+
+
+def extra_legs(torch, ctx, db, out, args, checks):
+    from paper_1703_10435_amd import abi, engine
+    E = db.n_elem
+    ex = {}
+    legs = [x.strip().upper() for x in args.legs.split(",") if x.strip()]
+    if "C2" in legs:
+        ms3 = _ms(torch, lambda: engine.run_three_call(ctx, db, abi.MHM_FP64, out), args.steps)
+        fp32 = db.alloc_outputs(three_call=False)
+        ms32 = _ms(torch, lambda: engine.run_fused(ctx, db, abi.MHM_FP32_IR, fp32), args.steps)
+        info = fp32["info"].cpu().numpy()[:E]
+        ex["C2"] = {"fp64_three_call_ms": ms3, "fp32_ir_fused_ms": ms32,
+                    "fp32_ir_steps_mean": float(fp32["ir_iters"].cpu().numpy()[:E].mean()),
+                    "fp32_ir_fallbacks": int(np.sum(info == -1))}
+    if "C3" in legs:
+        ex["C3"] = _batched_leg(torch, ctx, "C3", 3, checks)
+    if "C4" in legs:
+        ex["C4"] = _batched_leg(torch, ctx, "C4", 2, checks)
+    if "C5" in legs:
+        ex["C5"] = _serve_leg(args.serve_seconds, checks)
+    return ex
 
 
 # -------------------------------------------------------------------- timing
@@ -135,7 +274,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: auto)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra", action="store_true", help="also time the three-call and FP32+IR forms")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the C2 FP32+IR, C3, C4 (batching) and C5 (serving) legs")
+    ap.add_argument("--serve-seconds", type=float, default=1.0, help="length of the C5 open-loop stream")
+    ap.add_argument("--legs", default="C2,C3,C4,C5", help="which extra legs to run (comma list)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -193,19 +335,10 @@ def main():
                      "flops_per_element": "n^3/3 + 2 n^2 r (Cholesky + forward/backward solves)"},
     }
 
-    if args.extra:
-        three = lambda: engine.run_three_call(ctx, db, abi.MHM_FP64, out)  # noqa: E731
-        t3, p3 = time_launches(torch, three, args.steps, args.warmup)
-        fp32 = lambda: engine.run_fused(ctx, db, abi.MHM_FP32_IR, out)  # noqa: E731
-        t4, p4 = time_launches(torch, fp32, args.steps, args.warmup)
-        its = out["ir_iters"].cpu().numpy()[:E]
-        line["extra"] = {
-            "three_call_fp64_ms": t3 / args.steps,
-            "fused_fp32_ir_ms": t4 / args.steps,
-            "fp32_ir_steps_mean": float(its.mean()),
-            "fp32_ir_fallbacks": int(np.sum(out["info"].cpu().numpy()[:E] == -1)),
-        }
-        # leave the FP64 results in `out` for the error check below
+    checks = []   # (leg, field, batch, element, request, GPU result): compared with the oracle below
+    if not args.no_extra:
+        line["extra"] = extra_legs(torch, ctx, db, out, args, checks)
+        # leave the FP64 results of the headline workload in `out` for the error check below
         step()
         torch.cuda.synchronize()
         res = db.unpack(out)
@@ -213,15 +346,31 @@ def main():
     if not args.no_cpu:
         cores = len(os.sched_getaffinity(0))
         cores = min(cores, 16)
-        n_s = args.cpu_sample or max(64, min(E, int(25.0 / 0.04)))
+        n_s = args.cpu_sample or E   # the whole batch: about 30 CPU-s of oracle work
         rng = np.random.default_rng(1)
         idx = np.sort(rng.choice(E, size=min(n_s, E), replace=False))
         cb = cpu_baseline(batch, idx, cores)
         errs = []
         for e, o in cb["results"].items():
-            g = res[e]
-            ex = np.max(np.abs(g["X"] - o["X"])) / np.max(np.abs(o["X"]))
-            errs.append(ex)
+            errs.append(_rel_err(res[e], o))
+        # Acceptance per sampled element: 1e-10 (FP64 forms) or 1e-8 (FP32 +
+        # refinement, the served stream), widened to 10 kappa(Ahat) u64 where
+        # the element's conditioning puts the forward error of any FP64 solve
+        # above that (the K = 1e4 channels of C3 reach kappa ~ 1e7).
+        verdict = {}
+        for leg, field, b, e, _, g in checks:
+            ora = oracle_solve(b, e)
+            err = _rel_err(g, ora)
+            kap = oracle_cond(ora)
+            base = 1e-10 if field.startswith("fp64") else 1e-8
+            tol = max(base, 10.0 * kap * 2.0 ** -53)
+            d = line["extra"][leg]
+            d[field] = max(d.get(field) or 0.0, err)
+            d["max_cond_sampled"] = max(d.get("max_cond_sampled") or 0.0, kap)
+            verdict[leg] = verdict.get(leg, True) and err <= tol
+        for leg, ok in verdict.items():
+            line["extra"][leg]["error_check"] = "pass" if ok else "FAIL"
+            line["extra"][leg]["tolerance"] = "max(1e-10 FP64 | 1e-8 FP32+IR, 10 cond2(Ahat) u64) per element"
         line["cpu_baseline"] = {"value": cb["rate"], "unit": "local problems/s", "cores": cores, "kind": "oracle",
                                 "sample": f"{len(idx)} of the {E} elements (seeded), one element per task, "
                                           f"{cb['cpu_seconds']:.1f} CPU-s in {cb['wall']:.1f} s wall"}
