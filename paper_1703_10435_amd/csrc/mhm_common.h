@@ -25,6 +25,12 @@ __device__ __forceinline__ double group16_sum(double v) {
   for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+// max over the 16 lanes of a lane group
+__device__ __forceinline__ double group16_max(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
 // Block-wide sums of three values; every thread gets the results.
 // `red` holds 48 doubles (up to 16 waves).
 __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* red) {
@@ -354,72 +360,153 @@ namespace mhm {
 
 // FP64 residual of the refinement, R = Btilde - (A X + gamma c (c^T X)),
 // matrix-free from kappa (the 7-point stencil of each node), written as T
-// into the right-hand-side tiles (rtile(J)[a][p%16]).  Sweeps one column a
-// at a time; the per-wave maxima of |R|, |X| and |Btilde| for column a go to
-// wred[(wave*3 + k)*16 + a].  Returns the row-sum norm of Ahat (all threads).
+// into the right-hand-side tiles (tile J holds rows 16J.. of R^T; cx holds
+// c^T X per column).  Returns the row-sum norm of Ahat (all threads).
 // Btilde comes from the tables (fused) or from Btg (column-major n x r).
-template <typename T, bool FUSED, class KAP, class RT>
-__device__ __forceinline__ double ir_residual(const Elem& E, KAP kap, const double* X, const double* c,
-                                              const double* cx, double g, const double* ft, const double* bf,
-                                              const double* colsum, const double* Btg, RT rtile, double* wred,
-                                              double* red) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nthr = blockDim.x;
+template <typename T, bool FUSED>
+__device__ __noinline__ double ir_residual(const Elem& E, const double* kapp, const double* X, const double* c,
+                                           const double* cx, double g, const double* ft, const double* bf,
+                                           const double* colsum, const double* Btg, T* rhs_row, double* red) {
+  // (a separate function: its registers do not add to the calling kernel's;
+  // kapp, rhs_row and the small arrays may point to LDS or global memory)
+  auto kap = [=](int t) -> double { return kapp[t]; };
+  const int tid = threadIdx.x, nthr = blockDim.x;
   const int s = E.s, n = E.n, r = E.r, nt = E.nt;
-  for (int p = tid; p < 16 * nt; p += nthr) {
-    T* rt = rtile(p >> 4);
-    for (int a = (p >= n ? 0 : r); a < 16; ++a) rt[a * TST + (p & 15)] = T(0);
+  for (int p = tid; p < 16 * nt; p += nthr) {   // padding rows and columns of the tiles
+    T* rt = rhs_row + (int64_t)(p >> 4) * TILE + (p & 15);
+    for (int a = (p >= n ? 0 : r); a < 16; ++a) rt[a * TST] = T(0);
   }
+  // node-outer: one stencil per node, then its right-hand sides
   double anorm = 0.0;
-  for (int a = 0; a < r; ++a) {
-    double rm = 0.0, xm = 0.0, bm = 0.0;
-    const double* xa = X + (int64_t)a * n;
-    const double gcx = g * cx[a];
-    for (int p = tid; p < n; p += nthr) {
-      int i, j;
-      node_ij(p, s, i, j);
-      const Stencil st = stencil(i, j, s, E.G, kap);
-      const double cp = c[p];
-      if (a == 0)
-        anorm = fmax(anorm, fabs(st.d) + fabs(st.e) + fabs(st.w) + fabs(st.n) + fabs(st.so) + fabs(st.nw) +
-                                fabs(st.se) + g * cp * E.area);
-      double ax = st.d * xa[p] + cp * gcx;
-      if (i + j <= s - 1) ax += st.e * xa[p + 1] + st.n * xa[p + (s + 1 - j)];
-      if (i >= 1) ax += st.w * xa[p - 1] + st.nw * xa[p + (s - j)];
-      if (j >= 1) ax += st.so * xa[p - (s + 2 - j)] + st.se * xa[p - (s + 1 - j)];
-      const double bv = FUSED ? btilde_tab(E, ft, bf, c, colsum, a, p, i, j) : Btg[(int64_t)a * n + p];
-      const double rv = bv - ax;
-      rtile(p >> 4)[a * TST + (p & 15)] = (T)rv;
-      rm = fmax(rm, fabs(rv));
-      xm = fmax(xm, fabs(xa[p]));
-      bm = fmax(bm, fabs(bv));
-    }
-    rm = wave_max(rm);
-    xm = wave_max(xm);
-    bm = wave_max(bm);
-    if (lane == 0) {
-      wred[(wave * 3 + 0) * 16 + a] = rm;
-      wred[(wave * 3 + 1) * 16 + a] = xm;
-      wred[(wave * 3 + 2) * 16 + a] = bm;
+  for (int p = tid; p < n; p += nthr) {
+    int i, j;
+    node_ij(p, s, i, j);
+    const Stencil st = stencil(i, j, s, E.G, kap);
+    const double cp = c[p];
+    anorm = fmax(anorm, fabs(st.d) + fabs(st.e) + fabs(st.w) + fabs(st.n) + fabs(st.so) + fabs(st.nw) +
+                            fabs(st.se) + g * cp * E.area);
+    const bool hasE = i + j <= s - 1, hasW = i >= 1, hasS = j >= 1;
+    const int pE = p + 1, pN = p + (s + 1 - j), pW = p - 1, pNW = p + (s - j), pS = p - (s + 2 - j),
+              pSE = p - (s + 1 - j);
+    T* rt = rhs_row + (int64_t)(p >> 4) * TILE + (p & 15);
+#pragma unroll 4
+    for (int a = 0; a < r; ++a) {
+      const double* xa = X + (int64_t)a * n;
+      double ax = st.d * xa[p] + cp * (g * cx[a]);
+      if (hasE) ax += st.e * xa[pE] + st.n * xa[pN];
+      if (hasW) ax += st.w * xa[pW] + st.nw * xa[pNW];
+      if (hasS) ax += st.so * xa[pS] + st.se * xa[pSE];
+      const double b = FUSED ? btilde_tab(E, ft, bf, c, colsum, a, p, i, j) : Btg[(int64_t)a * n + p];
+      rt[a * TST] = (T)(b - ax);
     }
   }
-  return block_max(anorm, red);   // its barriers also publish wred
+  return block_max(anorm, red);   // its barriers also publish the residual tiles
 }
 
-// Normwise backward-error test of every column from the per-wave maxima.
+// Per-column maxima, column a by 16-lane groups: of |residual| from the
+// right-hand-side tiles (b == null), or of |Btilde| (first refinement step).
+template <typename T, bool FUSED>
+__device__ __noinline__ void ir_colmax(const Elem& E, const T* rhs_row, const double* ft, const double* bf,
+                                       const double* c, const double* colsum, const double* Btg, bool of_b,
+                                       double* out, double* part) {
+  const int tid = threadIdx.x, grp = tid >> 4, cl = tid & 15;
+  const int gpc = blockDim.x >> 8;
+  const int a = grp & 15, k = grp >> 4;
+  const int n = E.n, r = E.r, s = E.s;
+  double v = 0.0;
+  if (a < r) {
+    const int step = 16 * gpc;
+    for (int p = 16 * k + cl; p < n; p += step) {
+      double x;
+      if (of_b) {
+        int i, j;
+        node_ij(p, s, i, j);
+        x = FUSED ? btilde_tab(E, ft, bf, c, colsum, a, p, i, j) : Btg[(int64_t)a * n + p];
+      } else {
+        x = (double)rhs_row[(int64_t)(p >> 4) * TILE + a * TST + (p & 15)];
+      }
+      v = fmax(v, fabs(x));
+    }
+  }
+  v = group16_max(v);
+  if (cl == 0) part[k * 16 + a] = v;
+  __syncthreads();
+  if (tid < r) {
+    double m = 0.0;
+    for (int q = 0; q < gpc; ++q) m = fmax(m, part[q * 16 + tid]);
+    out[tid] = m;
+  }
+  __syncthreads();
+}
+
+// X (n x r, FP64, column-major) = tiles (init) or X + tiles, from the
+// solved right-hand-side row (tile J holds rows 16J.. of X^T), and at the
+// same time cx[a] = c^T X[:, a] and xmax[a] = max |X[:, a]|.  Column a is
+// handled by 16-lane groups (blockDim/256 of them, on interleaved nodes),
+// four nodes in flight per lane; part[] (LDS, 32 * blockDim/256 doubles)
+// combines the groups.
+template <typename T>
+__device__ __noinline__ void ir_accumulate(double* X, const T* rhs_row, const double* c, int n, int r, bool init,
+                                           double* cx, double* xmax, double* part) {
+  const int tid = threadIdx.x, grp = tid >> 4, cl = tid & 15;
+  const int gpc = blockDim.x >> 8;          // groups per column
+  const int a = grp & 15, k = grp >> 4;
+  double v = 0.0, xm = 0.0;
+  if (a < r) {
+    double* xa = X + (int64_t)a * n;
+    const int step = 16 * gpc;
+    for (int p0 = 16 * k + cl; p0 < n; p0 += 4 * step) {
+      double t[4], x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = p0 + u * step;
+        t[u] = 0.0;
+        x[u] = 0.0;
+        if (p < n) {
+          t[u] = (double)rhs_row[(int64_t)(p >> 4) * TILE + a * TST + (p & 15)];
+          if (!init) x[u] = xa[p];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = p0 + u * step;
+        if (p < n) {
+          const double xn = x[u] + t[u];
+          xa[p] = xn;
+          v += c[p] * xn;
+          xm = fmax(xm, fabs(xn));
+        }
+      }
+    }
+  }
+  v = group16_sum(v);
+  xm = group16_max(xm);
+  if (cl == 0) {
+    part[k * 16 + a] = v;
+    part[(gpc + k) * 16 + a] = xm;
+  }
+  __syncthreads();
+  if (tid < r) {
+    double sum = 0.0, m = 0.0;
+    for (int q = 0; q < gpc; ++q) {
+      sum += part[q * 16 + tid];
+      m = fmax(m, part[(gpc + q) * 16 + tid]);
+    }
+    cx[tid] = sum;
+    xmax[tid] = m;
+  }
+  __syncthreads();
+}
+
 // Normwise backward error of the current iterate, max over the columns:
 // max_p |r_pa| / (||Ahat||_inf max_p |x_pa| + max_p |b_pa|)  (0 for a zero
 // residual, inf for NaN).
-__device__ __forceinline__ double ir_backward_error(const double* wred, int nwaves, int r, double anorm) {
+__device__ __forceinline__ double ir_backward_error(const double* rmax, const double* xmax, const double* bmax, int r,
+                                                    double anorm) {
   double be = 0.0;
   for (int a = 0; a < r; ++a) {
-    double rm = 0, xm = 0, bm = 0;
-    for (int w = 0; w < nwaves; ++w) {
-      rm = fmax(rm, wred[(w * 3 + 0) * 16 + a]);
-      xm = fmax(xm, wred[(w * 3 + 1) * 16 + a]);
-      bm = fmax(bm, wred[(w * 3 + 2) * 16 + a]);
-    }
     // a zero residual is converged (a zero right-hand side has zero solution)
-    const double e = rm == 0.0 ? 0.0 : rm / (anorm * xm + bm);
+    const double e = rmax[a] == 0.0 ? 0.0 : rmax[a] / (anorm * xmax[a] + bmax[a]);
     be = e == e ? fmax(be, e) : __builtin_inf();
   }
   return be;

@@ -136,7 +136,8 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
   __shared__ double colsum[16];
   __shared__ double cx[16];          // (c^T X) per column
   __shared__ double gam;
-  __shared__ double wred[NWAVES][3][16];
+  __shared__ double part_s[32 * (NTHREADS / 256)];
+  __shared__ double rmax[16], xmax[16], bmax[16];
   extern __shared__ double dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int NImax = 3 * (b.l_max + 1);
@@ -385,27 +386,16 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
 
     if (fp32 && !failed) {
       // --------------------------------------- FP64 refinement (FP32 path)
-      for (int idx = tid; idx < n * r; idx += NTHREADS) {
-        const int a = idx / n, p = idx - a * n;
-        X[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)];
-      }
-      __syncthreads();
+      ir_accumulate<T>(X, tl(nt, 0), c, n, r, true, cx, xmax, part_s);
       const double* Btg = FUSED ? nullptr : args.Btil + E.rhs0;
       const double g = gam;
       int it = 0;
       for (;; ++it) {
-        {  // c^T X per column
-          double v = 0.0;
-          if (ca < r)
-            for (int p = cl16; p < n; p += 16) v += c[p] * X[(int64_t)ca * n + p];
-          v = group16_sum(v);
-          if (cl16 == 0) cx[ca] = v;
-        }
-        __syncthreads();
-        const double anorm = ir_residual<T, FUSED>(E, kap, X, c, cx, g, ft, bf, colsum, Btg,
-                                                   [&](int J) -> T* { return tl(nt, J); }, &wred[0][0][0], red);
+        const double anorm = ir_residual<T, FUSED>(E, kap_lds ? kapl : kapg, X, c, cx, g, ft, bf, colsum, Btg, tl(nt, 0), red);
+        if (it == 0) ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, true, bmax, part_s);
+        ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, false, rmax, part_s);
         if (tid == 0) {
-          const double be = ir_backward_error(&wred[0][0][0], NWAVES, r, anorm);
+          const double be = ir_backward_error(rmax, xmax, bmax, r, anorm);
           conv = ir_decide(be, be_prev, it, args.max_iters, args.ir_tol);
           be_prev = be;
         }
@@ -413,11 +403,7 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
         if (conv != 0) break;
         forward();
         backward();
-        for (int idx = tid; idx < n * r; idx += NTHREADS) {
-          const int a = idx / n, p = idx - a * n;
-          X[idx] += (double)tl(nt, p >> 4)[a * TST + (p & 15)];
-        }
-        __syncthreads();
+        ir_accumulate<T>(X, tl(nt, 0), c, n, r, false, cx, xmax, part_s);
       }
       const bool cvd = conv > 0;
       if (tid == 0) {
@@ -425,15 +411,8 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
         if (!cvd) args.info[e] = INFO_IR_FALLBACK;
       }
       if (!cvd) continue;   // recomputed by the FP64 fallback pass
-      {  // zero-mean projection of the FP64 iterate
-        double v = 0.0;
-        if (ca < r)
-          for (int p = cl16; p < n; p += 16) v += c[p] * X[(int64_t)ca * n + p];
-        v = group16_sum(v);
-        if (cl16 == 0) cx[ca] = v * E.inv_area;
-      }
-      __syncthreads();
-      for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] -= cx[idx / n];
+      // zero-mean projection of the FP64 iterate (cx is c^T X of the converged iterate)
+      for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] -= cx[idx / n] * E.inv_area;
       __syncthreads();
     } else if (fp32) {
       // FP32 pivot failure: recomputed by the FP64 fallback pass

@@ -40,10 +40,15 @@ constexpr int NTHREADS = 64 * NW;
 // The L operands of a step are loaded one or two steps ahead, so their
 // global-memory latency overlaps the chain of column solves.  Every register
 // slot is addressed statically.
-template <typename T, int RPW, bool BACK, class TL>
-__device__ __forceinline__ void sweep(TL tl, int nt, T* xb, T* scr, int wave, int lane) {
+template <typename T, int RPW, bool BACK>
+__device__ __forceinline__ void sweep_body(T* Lb, T* rhs_row, int nt, T* xb, T* scr, int wave, int lane) {
   typedef typename Mfma<T>::v4 V4;
-  constexpr int NB = RPW * (int)sizeof(T) <= 40 ? 2 : 1;   // operand buffers
+  auto tl = [=](int I, int J) -> T* {
+    return I == nt ? rhs_row + (int64_t)J * TILE : Lb + (int64_t)((I * (I + 1)) / 2 + J) * TILE;
+  };
+  // operand buffers (prefetch depth): FP32 sweeps run in their own function
+  // with registers to spare; FP64 ones are inlined in the kernel
+  constexpr int NB = sizeof(T) == 4 ? (RPW <= 5 ? 3 : 2) : (RPW <= 5 ? 2 : 1);
   V4 z[RPW];
 #pragma unroll
   for (int ri = 0; ri < RPW; ++ri) {
@@ -120,19 +125,13 @@ __device__ __forceinline__ void sweep(TL tl, int nt, T* xb, T* scr, int wave, in
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __syncthreads();
   };
-  if constexpr (NB == 2) {
-    for (int st = 0; st < nt; st += 2) {
-      step_once(st, bo[0], wo[0]);
-      fetch(st + 2, bo[0], wo[0]);
-      if (st + 1 < nt) {
-        step_once(st + 1, bo[1], wo[1]);
-        fetch(st + 3, bo[1], wo[1]);
+  for (int st = 0; st < nt; st += NB) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (st + q < nt) {
+        step_once(st + q, bo[q], wo[q]);
+        fetch(st + q + NB, bo[q], wo[q]);
       }
-    }
-  } else {
-    for (int st = 0; st < nt; ++st) {
-      step_once(st, bo[0], wo[0]);
-      fetch(st + 1, bo[0], wo[0]);
     }
   }
 #pragma unroll
@@ -142,6 +141,17 @@ __device__ __forceinline__ void sweep(TL tl, int nt, T* xb, T* scr, int wave, in
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __syncthreads();
+}
+// The same sweep as a separate function (the FP32 refinement loop calls it
+// twice per step: inlined copies would add their registers to the kernel's).
+template <typename T, int RPW, bool BACK>
+__device__ __noinline__ void sweep_call(T* Lb, T* rhs_row, int nt, T* xb, T* scr, int wave, int lane) {
+  sweep_body<T, RPW, BACK>(Lb, rhs_row, nt, xb, scr, wave, lane);
+}
+template <typename T, int RPW, bool BACK>
+__device__ __forceinline__ void sweep(T* Lb, T* rhs_row, int nt, T* xb, T* scr, int wave, int lane) {
+  if constexpr (sizeof(T) == 4) sweep_call<T, RPW, BACK>(Lb, rhs_row, nt, xb, scr, wave, lane);
+  else sweep_body<T, RPW, BACK>(Lb, rhs_row, nt, xb, scr, wave, lane);
 }
 }  // namespace ll
 
@@ -156,7 +166,8 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
   __shared__ double colsum[16];
   __shared__ double cx[16];
   __shared__ double gam;
-  __shared__ double wred[NW][3][16];
+  __shared__ double part_s[32 * (NTHREADS / 256)];
+  __shared__ double rmax[16], xmax[16], bmax[16];
   extern __shared__ double dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int NImax = 3 * (b.l_max + 1);
@@ -305,8 +316,8 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
     };
 
     T* xb = stage;   // two published solution tiles of the sweeps (staging area)
-    auto backward = [&]() { ll::sweep<T, RPW, true>(tl, nt, xb, scr, wave, lane); };
-    auto forward = [&]() { ll::sweep<T, RPW, false>(tl, nt, xb, scr, wave, lane); };
+    auto backward = [&]() { ll::sweep<T, RPW, true>(Lb, rhs_row, nt, xb, scr, wave, lane); };
+    auto forward = [&]() { ll::sweep<T, RPW, false>(Lb, rhs_row, nt, xb, scr, wave, lane); };
 
     // ------------------------------------------------------ factorisation
     if (reuse) {
@@ -343,7 +354,11 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
       // of column m run; one barrier per column (stage buffers alternate).
       if (j0 > 0) {
         constexpr int SPT = (PW * TILE + NTHREADS - 1) / NTHREADS;
-        constexpr int NB = RPW <= 5 ? 2 : 1;   // operand buffers (register budget)
+        // operand buffers (prefetch depth) within a register estimate
+        constexpr int W = (int)sizeof(T) / 4;
+        constexpr int NB = RPW * PW * 4 * W + 3 * (RPW * 4 + SPT) * W <= 144   ? 3
+                           : RPW * PW * 4 * W + 2 * (RPW * 4 + SPT) * W <= 160 ? 2
+                                                                               : 1;
         T ab[NB][RPW][4];
         T sb[NB][SPT];
         auto fetch = [&](int m, T (&a)[RPW][4], T (&sv)[SPT]) {
@@ -388,21 +403,22 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
             }
           }
         };
-        if constexpr (NB == 2) {
-          fetch(0, ab[0], sb[0]);
-          fetch(1, ab[1], sb[1]);
-          for (int m = 0; m < j0; m += 2) {
-            apply(m, ab[0], sb[0]);
-            fetch(m + 2, ab[0], sb[0]);
-            if (m + 1 < j0) {
-              apply(m + 1, ab[1], sb[1]);
-              fetch(m + 3, ab[1], sb[1]);
-            }
-          }
-        } else {
+        if constexpr (NB == 1) {
           for (int m = 0; m < j0; ++m) {
             fetch(m, ab[0], sb[0]);
             apply(m, ab[0], sb[0]);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < NB; ++q) fetch(q, ab[q], sb[q]);
+          for (int m = 0; m < j0; m += NB) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              if (m + q < j0) {
+                apply(m + q, ab[q], sb[q]);
+                fetch(m + q + NB, ab[q], sb[q]);
+              }
+            }
           }
         }
       }
@@ -506,26 +522,16 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
 
     if (fp32 && !failed) {
       // --------------------------------------- FP64 refinement (FP32 path)
-      for (int idx = tid; idx < n * r; idx += NTHREADS) {
-        const int a = idx / n, p = idx - a * n;
-        X[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)];
-      }
-      __syncthreads();
+      double* part = part_s;
+      ir_accumulate<T>(X, tl(nt, 0), c, n, r, true, cx, xmax, part);
       const double* Btg = FUSED ? nullptr : args.Btil + E.rhs0;
       int it = 0;
       for (;; ++it) {
-        {
-          double v = 0.0;
-          if (ca < r)
-            for (int p = cl16; p < n; p += 16) v += c[p] * X[(int64_t)ca * n + p];
-          v = group16_sum(v);
-          if (cl16 == 0 && ca < 16) cx[ca] = v;
-        }
-        __syncthreads();
-        const double anorm = ir_residual<T, FUSED>(E, kap, X, c, cx, g, ft, bf, colsum, Btg,
-                                                   [&](int J) -> T* { return tl(nt, J); }, &wred[0][0][0], red);
+        const double anorm = ir_residual<T, FUSED>(E, kapg, X, c, cx, g, ft, bf, colsum, Btg, tl(nt, 0), red);
+        if (it == 0) ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, true, bmax, part);
+        ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, false, rmax, part);
         if (tid == 0) {
-          const double be = ir_backward_error(&wred[0][0][0], NW, r, anorm);
+          const double be = ir_backward_error(rmax, xmax, bmax, r, anorm);
           conv = ir_decide(be, be_prev, it, args.max_iters, args.ir_tol);
           be_prev = be;
         }
@@ -533,11 +539,7 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
         if (conv != 0) break;
         forward();
         backward();
-        for (int idx = tid; idx < n * r; idx += NTHREADS) {
-          const int a = idx / n, p = idx - a * n;
-          X[idx] += (double)tl(nt, p >> 4)[a * TST + (p & 15)];
-        }
-        __syncthreads();
+        ir_accumulate<T>(X, tl(nt, 0), c, n, r, false, cx, xmax, part);
       }
       const bool cvd = conv > 0;
       if (tid == 0) {
@@ -545,15 +547,8 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
         if (!cvd) args.info[e] = INFO_IR_FALLBACK;
       }
       if (!cvd) continue;
-      {
-        double v = 0.0;
-        if (ca < r)
-          for (int p = cl16; p < n; p += 16) v += c[p] * X[(int64_t)ca * n + p];
-        v = group16_sum(v);
-        if (cl16 == 0 && ca < 16) cx[ca] = v * E.inv_area;
-      }
-      __syncthreads();
-      for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] -= cx[idx / n];
+      // zero-mean projection: cx still holds c^T X of the converged iterate
+      for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] -= cx[idx / n] * E.inv_area;
       __syncthreads();
     } else if (fp32) {
       if (tid == 0) args.info[e] = INFO_IR_FALLBACK;

@@ -1,0 +1,45 @@
+// Left-looking local-problem kernel: launch geometry and precision dispatch
+// (the kernel is in mhm_local_ll.h, its instances in mhm_local_ll_f32.hip and
+// mhm_local_ll_f64.hip).
+#include "mhm_local_ll.h"
+
+namespace mhm {
+
+hipError_t launch_local_ll_f32(bool fused, int pw, int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid,
+                               hipStream_t st);
+hipError_t launch_local_ll_f64(bool fused, int pw, int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid,
+                               hipStream_t st);
+
+int local_ll_rows_per_wave(int nt) {
+  const int rows = nt + 1;
+  if (rows <= 2 * ll::NW) return 2;
+  if (rows <= 3 * ll::NW) return 3;
+  if (rows <= 5 * ll::NW) return 5;
+  if (rows <= 10 * ll::NW) return 10;
+  return -1;
+}
+
+int local_ll_default_panel(bool fp32) { return fp32 ? 4 : 2; }
+
+bool local_ll_has(bool fp32, int pw, int nt) {
+  const int rpw = local_ll_rows_per_wave(nt);
+  if (rpw < 0) return false;
+  if (fp32) return pw == 2 || pw == 4;
+  return pw == 2 || (pw == 4 && rpw <= 3);
+}
+
+size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap) {
+  return sizeof(double) * (2 * (size_t)n_cap + (size_t)f_cap) +
+         (size_t)(2 * pw + 1 + pw + ll::NW) * TILE * (fp32 ? sizeof(float) : sizeof(double));
+}
+
+hipError_t launch_local_ll(bool fp32, bool fused, int pw, int nt_max, const mhm_batch* bt, LocalArgs a, size_t lds,
+                           int grid, hipStream_t st) {
+  if (!local_ll_has(fp32, pw, nt_max)) return hipErrorInvalidValue;
+  const int rpw = local_ll_rows_per_wave(nt_max);
+  const BatchDev d = to_dev(bt);
+  return fp32 ? launch_local_ll_f32(fused, pw, rpw, d, a, lds, grid, st)
+              : launch_local_ll_f64(fused, pw, rpw, d, a, lds, grid, st);
+}
+
+}  // namespace mhm
