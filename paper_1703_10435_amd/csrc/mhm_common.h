@@ -364,11 +364,10 @@ namespace mhm {
 // c^T X per column).  Returns the row-sum norm of Ahat (all threads).
 // Btilde comes from the tables (fused) or from Btg (column-major n x r).
 template <typename T, bool FUSED>
-__device__ __noinline__ double ir_residual(const Elem& E, const double* kapp, const double* X, const double* c,
-                                           const double* cx, double g, const double* ft, const double* bf,
-                                           const double* colsum, const double* Btg, T* rhs_row, double* red) {
-  // (a separate function: its registers do not add to the calling kernel's;
-  // kapp, rhs_row and the small arrays may point to LDS or global memory)
+__device__ __forceinline__ double ir_residual_body(const Elem& E, const double* kapp, const double* X,
+                                                   const double* c, const double* cx, double g, const double* ft,
+                                                   const double* bf, const double* colsum, const double* Btg,
+                                                   T* rhs_row, double* red) {
   auto kap = [=](int t) -> double { return kapp[t]; };
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int s = E.s, n = E.n, r = E.r, nt = E.nt;
@@ -406,9 +405,9 @@ __device__ __noinline__ double ir_residual(const Elem& E, const double* kapp, co
 // Per-column maxima, column a by 16-lane groups: of |residual| from the
 // right-hand-side tiles (b == null), or of |Btilde| (first refinement step).
 template <typename T, bool FUSED>
-__device__ __noinline__ void ir_colmax(const Elem& E, const T* rhs_row, const double* ft, const double* bf,
-                                       const double* c, const double* colsum, const double* Btg, bool of_b,
-                                       double* out, double* part) {
+__device__ __forceinline__ void ir_colmax_body(const Elem& E, const T* rhs_row, const double* ft, const double* bf,
+                                               const double* c, const double* colsum, const double* Btg, bool of_b,
+                                               double* out, double* part) {
   const int tid = threadIdx.x, grp = tid >> 4, cl = tid & 15;
   const int gpc = blockDim.x >> 8;
   const int a = grp & 15, k = grp >> 4;
@@ -446,8 +445,8 @@ __device__ __noinline__ void ir_colmax(const Elem& E, const T* rhs_row, const do
 // four nodes in flight per lane; part[] (LDS, 32 * blockDim/256 doubles)
 // combines the groups.
 template <typename T>
-__device__ __noinline__ void ir_accumulate(double* X, const T* rhs_row, const double* c, int n, int r, bool init,
-                                           double* cx, double* xmax, double* part) {
+__device__ __forceinline__ void ir_accumulate_body(double* X, const T* rhs_row, const double* c, int n, int r,
+                                                   bool init, double* cx, double* xmax, double* part) {
   const int tid = threadIdx.x, grp = tid >> 4, cl = tid & 15;
   const int gpc = blockDim.x >> 8;          // groups per column
   const int a = grp & 15, k = grp >> 4;
@@ -496,6 +495,27 @@ __device__ __noinline__ void ir_accumulate(double* X, const T* rhs_row, const do
     xmax[tid] = m;
   }
   __syncthreads();
+}
+
+// The three refinement passes as separate functions, for kernels whose
+// registers are already taken by their tiles (pointers may be to LDS or
+// global memory); kernels with tiles in LDS inline the bodies instead.
+template <typename T, bool FUSED>
+__device__ __noinline__ double ir_residual(const Elem& E, const double* kapp, const double* X, const double* c,
+                                           const double* cx, double g, const double* ft, const double* bf,
+                                           const double* colsum, const double* Btg, T* rhs_row, double* red) {
+  return ir_residual_body<T, FUSED>(E, kapp, X, c, cx, g, ft, bf, colsum, Btg, rhs_row, red);
+}
+template <typename T, bool FUSED>
+__device__ __noinline__ void ir_colmax(const Elem& E, const T* rhs_row, const double* ft, const double* bf,
+                                       const double* c, const double* colsum, const double* Btg, bool of_b,
+                                       double* out, double* part) {
+  ir_colmax_body<T, FUSED>(E, rhs_row, ft, bf, c, colsum, Btg, of_b, out, part);
+}
+template <typename T>
+__device__ __noinline__ void ir_accumulate(double* X, const T* rhs_row, const double* c, int n, int r, bool init,
+                                           double* cx, double* xmax, double* part) {
+  ir_accumulate_body<T>(X, rhs_row, c, n, r, init, cx, xmax, part);
 }
 
 // Normwise backward error of the current iterate, max over the columns:

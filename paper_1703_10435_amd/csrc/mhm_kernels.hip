@@ -386,14 +386,14 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
 
     if (fp32 && !failed) {
       // --------------------------------------- FP64 refinement (FP32 path)
-      ir_accumulate<T>(X, tl(nt, 0), c, n, r, true, cx, xmax, part_s);
+      ir_accumulate_body<T>(X, tl(nt, 0), c, n, r, true, cx, xmax, part_s);
       const double* Btg = FUSED ? nullptr : args.Btil + E.rhs0;
       const double g = gam;
       int it = 0;
       for (;; ++it) {
-        const double anorm = ir_residual<T, FUSED>(E, kap_lds ? kapl : kapg, X, c, cx, g, ft, bf, colsum, Btg, tl(nt, 0), red);
-        if (it == 0) ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, true, bmax, part_s);
-        ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, false, rmax, part_s);
+        const double anorm = ir_residual_body<T, FUSED>(E, kap_lds ? kapl : kapg, X, c, cx, g, ft, bf, colsum, Btg, tl(nt, 0), red);
+        if (it == 0) ir_colmax_body<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, true, bmax, part_s);
+        ir_colmax_body<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, false, rmax, part_s);
         if (tid == 0) {
           const double be = ir_backward_error(rmax, xmax, bmax, r, anorm);
           conv = ir_decide(be, be_prev, it, args.max_iters, args.ir_tol);
@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
         if (conv != 0) break;
         forward();
         backward();
-        ir_accumulate<T>(X, tl(nt, 0), c, n, r, false, cx, xmax, part_s);
+        ir_accumulate_body<T>(X, tl(nt, 0), c, n, r, false, cx, xmax, part_s);
       }
       const bool cvd = conv > 0;
       if (tid == 0) {
