@@ -42,12 +42,12 @@ def _flops_per_element(n, r):
 
 
 def _source_hash():
-    """sha256 over the library sources (the same recipe as profiles/*_counters.md)."""
-    import glob
+    """sha256 over the sources the headline kernel (k_local_rr) is built from
+    (the same recipe as profiles/*_counters.md)."""
     import hashlib
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1703_10435_amd", "csrc", "*.hip"))
-                   + glob.glob(os.path.join(ROOT, "paper_1703_10435_amd", "csrc", "*.h"))
-                   + [os.path.join(ROOT, "include", "mhm.h")])
+    csrc = os.path.join(ROOT, "paper_1703_10435_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in ("mhm_device.h", "mhm_kernels.h", "mhm_local_rr.hip")]
+    files.append(os.path.join(ROOT, "include", "mhm.h"))
     h = hashlib.sha256()
     for f in files:
         h.update(os.path.basename(f).encode())
