@@ -65,10 +65,10 @@ hipError_t launch_local_rr(bool fused, const mhm_batch* bt, LocalArgs a, size_t 
 // width pw (block columns of pw tiles).
 int local_ll_rows_per_wave(int nt);
 int local_ll_default_panel(bool fp32);
-bool local_ll_has(bool fp32, int pw, int nt);
+bool local_ll_has(bool fp32, int pw, int nt, int occ);
 size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap);
-hipError_t launch_local_ll(bool fp32, bool fused, int pw, int nt_max, const mhm_batch* bt, LocalArgs a, size_t lds,
-                           int grid, hipStream_t st);
+hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nt_max, const mhm_batch* bt, LocalArgs a,
+                           size_t lds, int grid, hipStream_t st);
 hipError_t launch_local(bool fp32, bool in_lds, bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
                         hipStream_t st);
 

@@ -40,7 +40,7 @@ constexpr int NTHREADS = 64 * NW;
 // The L operands of a step are loaded one or two steps ahead, so their
 // global-memory latency overlaps the chain of column solves.  Every register
 // slot is addressed statically.
-template <typename T, int RPW, bool BACK>
+template <typename T, int RPW, bool BACK, int OCC>
 __device__ __forceinline__ void sweep_body(T* Lb, T* rhs_row, int nt, T* xb, T* scr, int wave, int lane) {
   typedef typename Mfma<T>::v4 V4;
   auto tl = [=](int I, int J) -> T* {
@@ -48,7 +48,8 @@ __device__ __forceinline__ void sweep_body(T* Lb, T* rhs_row, int nt, T* xb, T* 
   };
   // operand buffers (prefetch depth): FP32 sweeps run in their own function
   // with registers to spare; FP64 ones are inlined in the kernel
-  constexpr int NB = sizeof(T) == 4 ? (RPW <= 5 ? 3 : 2) : (RPW <= 5 ? 2 : 1);
+  // (two workgroups per CU: half the registers, one buffer)
+  constexpr int NB = OCC == 2 ? 1 : sizeof(T) == 4 ? (RPW <= 5 ? 3 : 2) : (RPW <= 5 ? 2 : 1);
   V4 z[RPW];
 #pragma unroll
   for (int ri = 0; ri < RPW; ++ri) {
@@ -144,19 +145,22 @@ __device__ __forceinline__ void sweep_body(T* Lb, T* rhs_row, int nt, T* xb, T* 
 }
 // The same sweep as a separate function (the FP32 refinement loop calls it
 // twice per step: inlined copies would add their registers to the kernel's).
-template <typename T, int RPW, bool BACK>
+template <typename T, int RPW, bool BACK, int OCC>
 __device__ __noinline__ void sweep_call(T* Lb, T* rhs_row, int nt, T* xb, T* scr, int wave, int lane) {
-  sweep_body<T, RPW, BACK>(Lb, rhs_row, nt, xb, scr, wave, lane);
+  sweep_body<T, RPW, BACK, OCC>(Lb, rhs_row, nt, xb, scr, wave, lane);
 }
-template <typename T, int RPW, bool BACK>
+template <typename T, int RPW, bool BACK, int OCC>
 __device__ __forceinline__ void sweep(T* Lb, T* rhs_row, int nt, T* xb, T* scr, int wave, int lane) {
-  if constexpr (sizeof(T) == 4) sweep_call<T, RPW, BACK>(Lb, rhs_row, nt, xb, scr, wave, lane);
-  else sweep_body<T, RPW, BACK>(Lb, rhs_row, nt, xb, scr, wave, lane);
+  if constexpr (sizeof(T) == 4) sweep_call<T, RPW, BACK, OCC>(Lb, rhs_row, nt, xb, scr, wave, lane);
+  else sweep_body<T, RPW, BACK, OCC>(Lb, rhs_row, nt, xb, scr, wave, lane);
 }
 }  // namespace ll
 
-template <typename T, bool FUSED, int PW, int RPW>
-__global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs args) {
+// OCC = 2: the register budget of two resident workgroups per CU (4 waves
+// per SIMD, at most 128 registers per lane; two
+// elements interleave their latencies), with one operand buffer.
+template <typename T, bool FUSED, int PW, int RPW, int OCC>
+__global__ void __launch_bounds__(ll::NTHREADS, 2 * OCC) k_local_ll(BatchDev b, LocalArgs args) {
   using namespace ll;
   typedef typename Mfma<T>::v4 V4;
   __shared__ Elem E;
@@ -316,8 +320,8 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
     };
 
     T* xb = stage;   // two published solution tiles of the sweeps (staging area)
-    auto backward = [&]() { ll::sweep<T, RPW, true>(Lb, rhs_row, nt, xb, scr, wave, lane); };
-    auto forward = [&]() { ll::sweep<T, RPW, false>(Lb, rhs_row, nt, xb, scr, wave, lane); };
+    auto backward = [&]() { ll::sweep<T, RPW, true, OCC>(Lb, rhs_row, nt, xb, scr, wave, lane); };
+    auto forward = [&]() { ll::sweep<T, RPW, false, OCC>(Lb, rhs_row, nt, xb, scr, wave, lane); };
 
     // ------------------------------------------------------ factorisation
     if (reuse) {
@@ -356,7 +360,8 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
         constexpr int SPT = (PW * TILE + NTHREADS - 1) / NTHREADS;
         // operand buffers (prefetch depth) within a register estimate
         constexpr int W = (int)sizeof(T) / 4;
-        constexpr int NB = RPW * PW * 4 * W + 3 * (RPW * 4 + SPT) * W <= 144   ? 3
+        constexpr int NB = OCC == 2                                                ? 1
+                           : RPW * PW * 4 * W + 3 * (RPW * 4 + SPT) * W <= 144 ? 3
                            : RPW * PW * 4 * W + 2 * (RPW * 4 + SPT) * W <= 160 ? 2
                                                                                : 1;
         T ab[NB][RPW][4];
@@ -585,9 +590,9 @@ __global__ void __launch_bounds__(ll::NTHREADS) k_local_ll(BatchDev b, LocalArgs
   }
 }
 
-template <typename T, bool FUSED, int PW, int RPW>
+template <typename T, bool FUSED, int PW, int RPW, int OCC>
 static hipError_t launch_ll_t(const BatchDev& d, LocalArgs a, size_t lds, int grid, hipStream_t st) {
-  auto kern = k_local_ll<T, FUSED, PW, RPW>;
+  auto kern = k_local_ll<T, FUSED, PW, RPW, OCC>;
   hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(ll::NTHREADS), lds, st, d, a);

@@ -5,10 +5,10 @@
 
 namespace mhm {
 
-hipError_t launch_local_ll_f32(bool fused, int pw, int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid,
-                               hipStream_t st);
-hipError_t launch_local_ll_f64(bool fused, int pw, int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid,
-                               hipStream_t st);
+hipError_t launch_local_ll_f32(bool fused, int pw, int occ, int rpw, const BatchDev& d, LocalArgs a, size_t lds,
+                               int grid, hipStream_t st);
+hipError_t launch_local_ll_f64(bool fused, int pw, int occ, int rpw, const BatchDev& d, LocalArgs a, size_t lds,
+                               int grid, hipStream_t st);
 
 int local_ll_rows_per_wave(int nt) {
   const int rows = nt + 1;
@@ -21,9 +21,11 @@ int local_ll_rows_per_wave(int nt) {
 
 int local_ll_default_panel(bool fp32) { return fp32 ? 4 : 2; }
 
-bool local_ll_has(bool fp32, int pw, int nt) {
+bool local_ll_has(bool fp32, int pw, int nt, int occ) {
   const int rpw = local_ll_rows_per_wave(nt);
   if (rpw < 0) return false;
+  if (occ == 2) return pw == 2 && (fp32 || rpw <= 3);
+  if (occ != 1) return false;
   if (fp32) return pw == 2 || pw == 4;
   return pw == 2 || (pw == 4 && rpw <= 3);
 }
@@ -33,13 +35,13 @@ size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap) {
          (size_t)(2 * pw + 1 + pw + ll::NW) * TILE * (fp32 ? sizeof(float) : sizeof(double));
 }
 
-hipError_t launch_local_ll(bool fp32, bool fused, int pw, int nt_max, const mhm_batch* bt, LocalArgs a, size_t lds,
-                           int grid, hipStream_t st) {
-  if (!local_ll_has(fp32, pw, nt_max)) return hipErrorInvalidValue;
+hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nt_max, const mhm_batch* bt, LocalArgs a,
+                           size_t lds, int grid, hipStream_t st) {
+  if (!local_ll_has(fp32, pw, nt_max, occ)) return hipErrorInvalidValue;
   const int rpw = local_ll_rows_per_wave(nt_max);
   const BatchDev d = to_dev(bt);
-  return fp32 ? launch_local_ll_f32(fused, pw, rpw, d, a, lds, grid, st)
-              : launch_local_ll_f64(fused, pw, rpw, d, a, lds, grid, st);
+  return fp32 ? launch_local_ll_f32(fused, pw, occ, rpw, d, a, lds, grid, st)
+              : launch_local_ll_f64(fused, pw, occ, rpw, d, a, lds, grid, st);
 }
 
 }  // namespace mhm

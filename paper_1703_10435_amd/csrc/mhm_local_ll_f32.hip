@@ -1,23 +1,28 @@
-// FP32 instances of the left-looking kernel (panel widths 2 and 4).
+// FP32 instances of the left-looking kernel (panel widths 2 and 4; panel
+// width 2 also with two resident workgroups per CU).
 #include "mhm_local_ll.h"
 
 namespace mhm {
 
-template <bool FUSED, int PW>
+template <bool FUSED, int PW, int OCC>
 static hipError_t launch_rpw(int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid, hipStream_t st) {
   switch (rpw) {
-    case 2: return launch_ll_t<float, FUSED, PW, 2>(d, a, lds, grid, st);
-    case 3: return launch_ll_t<float, FUSED, PW, 3>(d, a, lds, grid, st);
-    case 5: return launch_ll_t<float, FUSED, PW, 5>(d, a, lds, grid, st);
-    case 10: return launch_ll_t<float, FUSED, PW, 10>(d, a, lds, grid, st);
+    case 2: return launch_ll_t<float, FUSED, PW, 2, OCC>(d, a, lds, grid, st);
+    case 3: return launch_ll_t<float, FUSED, PW, 3, OCC>(d, a, lds, grid, st);
+    case 5: return launch_ll_t<float, FUSED, PW, 5, OCC>(d, a, lds, grid, st);
+    case 10: return launch_ll_t<float, FUSED, PW, 10, OCC>(d, a, lds, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_local_ll_f32(bool fused, int pw, int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid,
-                               hipStream_t st) {
-  if (pw == 4) return fused ? launch_rpw<true, 4>(rpw, d, a, lds, grid, st) : launch_rpw<false, 4>(rpw, d, a, lds, grid, st);
-  if (pw == 2) return fused ? launch_rpw<true, 2>(rpw, d, a, lds, grid, st) : launch_rpw<false, 2>(rpw, d, a, lds, grid, st);
+hipError_t launch_local_ll_f32(bool fused, int pw, int occ, int rpw, const BatchDev& d, LocalArgs a, size_t lds,
+                               int grid, hipStream_t st) {
+  if (occ == 2) {
+    if (pw != 2) return hipErrorInvalidValue;
+    return fused ? launch_rpw<true, 2, 2>(rpw, d, a, lds, grid, st) : launch_rpw<false, 2, 2>(rpw, d, a, lds, grid, st);
+  }
+  if (pw == 4) return fused ? launch_rpw<true, 4, 1>(rpw, d, a, lds, grid, st) : launch_rpw<false, 4, 1>(rpw, d, a, lds, grid, st);
+  if (pw == 2) return fused ? launch_rpw<true, 2, 1>(rpw, d, a, lds, grid, st) : launch_rpw<false, 2, 1>(rpw, d, a, lds, grid, st);
   return hipErrorInvalidValue;
 }
 

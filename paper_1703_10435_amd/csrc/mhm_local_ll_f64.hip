@@ -1,5 +1,6 @@
 // FP64 instances of the left-looking kernel (panel width 2; width 4 for up to
-// 24 tile rows, where the register panel still fits).
+// 24 tile rows, where the register panel still fits; width 2 with two
+// resident workgroups per CU for up to 24 tile rows).
 #include "mhm_local_ll.h"
 
 namespace mhm {
@@ -7,24 +8,36 @@ namespace mhm {
 template <bool FUSED>
 static hipError_t launch_rpw2(int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid, hipStream_t st) {
   switch (rpw) {
-    case 2: return launch_ll_t<double, FUSED, 2, 2>(d, a, lds, grid, st);
-    case 3: return launch_ll_t<double, FUSED, 2, 3>(d, a, lds, grid, st);
-    case 5: return launch_ll_t<double, FUSED, 2, 5>(d, a, lds, grid, st);
-    case 10: return launch_ll_t<double, FUSED, 2, 10>(d, a, lds, grid, st);
+    case 2: return launch_ll_t<double, FUSED, 2, 2, 1>(d, a, lds, grid, st);
+    case 3: return launch_ll_t<double, FUSED, 2, 3, 1>(d, a, lds, grid, st);
+    case 5: return launch_ll_t<double, FUSED, 2, 5, 1>(d, a, lds, grid, st);
+    case 10: return launch_ll_t<double, FUSED, 2, 10, 1>(d, a, lds, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
 template <bool FUSED>
 static hipError_t launch_rpw4(int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid, hipStream_t st) {
   switch (rpw) {
-    case 2: return launch_ll_t<double, FUSED, 4, 2>(d, a, lds, grid, st);
-    case 3: return launch_ll_t<double, FUSED, 4, 3>(d, a, lds, grid, st);
+    case 2: return launch_ll_t<double, FUSED, 4, 2, 1>(d, a, lds, grid, st);
+    case 3: return launch_ll_t<double, FUSED, 4, 3, 1>(d, a, lds, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+template <bool FUSED>
+static hipError_t launch_occ2(int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid, hipStream_t st) {
+  switch (rpw) {
+    case 2: return launch_ll_t<double, FUSED, 2, 2, 2>(d, a, lds, grid, st);
+    case 3: return launch_ll_t<double, FUSED, 2, 3, 2>(d, a, lds, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_local_ll_f64(bool fused, int pw, int rpw, const BatchDev& d, LocalArgs a, size_t lds, int grid,
-                               hipStream_t st) {
+hipError_t launch_local_ll_f64(bool fused, int pw, int occ, int rpw, const BatchDev& d, LocalArgs a, size_t lds,
+                               int grid, hipStream_t st) {
+  if (occ == 2) {
+    if (pw != 2) return hipErrorInvalidValue;
+    return fused ? launch_occ2<true>(rpw, d, a, lds, grid, st) : launch_occ2<false>(rpw, d, a, lds, grid, st);
+  }
   if (pw == 2) return fused ? launch_rpw2<true>(rpw, d, a, lds, grid, st) : launch_rpw2<false>(rpw, d, a, lds, grid, st);
   if (pw == 4) return fused ? launch_rpw4<true>(rpw, d, a, lds, grid, st) : launch_rpw4<false>(rpw, d, a, lds, grid, st);
   return hipErrorInvalidValue;

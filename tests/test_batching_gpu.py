@@ -69,10 +69,12 @@ def test_every_size_class_in_one_batch(ctx, prec):
         _check(res, b, range(b["n_elem"]), prec, f"all-classes prec={prec} {mode}")
 
 
-@pytest.mark.parametrize("env", [{"MHM_NO_RR": "1"}, {"MHM_NO_LL": "1"}, {"MHM_NO_RR": "1", "MHM_NO_LL": "1"}])
+@pytest.mark.parametrize("env", [{"MHM_NO_RR": "1"}, {"MHM_NO_LL": "1"}, {"MHM_NO_RR": "1", "MHM_NO_LL": "1"},
+                                 {"MHM_NO_RR": "1", "MHM_LL_OCC2": "1"}])
 def test_kernel_families_agree_with_oracle(env):
     """The families the defaults do not pick (LDS tiles for small FP64
-    elements, the right-looking workspace kernel for large ones)."""
+    elements, the right-looking workspace kernel for large ones, the
+    left-looking kernel built for two workgroups per CU)."""
     from paper_1703_10435_amd import engine
     c = _ctx(env)
     try:
