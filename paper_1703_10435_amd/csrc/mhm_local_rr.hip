@@ -388,6 +388,24 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
     double* Lo = (!FUSED && args.Lout && E.mat0 >= 0) ? args.Lout + E.mat0 : nullptr;
     __syncthreads();
 
+    // Tile coordinates of this wave's slots (tile 4 sl + wave of the
+    // column-major lower triangle; -1 past its end), wave-uniform registers:
+    // the slot tests of every step need no table reads.
+    int sI[S], sJ[S];
+    {
+      const int wv = __builtin_amdgcn_readfirstlane(wave);
+#pragma unroll
+      for (int sl = 0; sl < S; ++sl) {
+        int t = NWAVES * sl + wv, J = 0;
+        while (J < nt && t >= nt - J) {
+          t -= nt - J;
+          ++J;
+        }
+        sI[sl] = J < nt ? J + t : -1;
+        sJ[sl] = J < nt ? J : -1;
+      }
+    }
+
     // ------------------------------------------------------- factorisation
     // Step k = -1 only hands tile (0, 0) to the factor.  The RHS row is
     // eliminated with the matrix and ends holding Y^T = (L^{-1} Btilde)^T.
@@ -397,9 +415,8 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
         // published to P[i]; Y_k^T = Z_k^T W_k^T by wave k%4
 #pragma unroll
         for (int sl = 0; sl < S; ++sl) {
-          const int t = NWAVES * sl + wave;
-          if (t < ntiles && tij[t][1] == k && tij[t][0] > k) {
-            const int I = tij[t][0];
+          if (sJ[sl] == k && sI[sl] > k) {
+            const int I = sI[sl];
             st_acc<double>(Pt(I), acc[sl], lane);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             V4 x = {0, 0, 0, 0};
@@ -429,8 +446,7 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
       bool mine = false;
 #pragma unroll
       for (int sl = 0; sl < S; ++sl) {
-        const int t = NWAVES * sl + wave;
-        if (t < ntiles && tij[t][0] == k + 1 && tij[t][1] == k + 1) {
+        if (sI[sl] == k + 1 && sJ[sl] == k + 1) {
           V4 x = acc[sl];
           if (k >= 0) {
 #pragma unroll
@@ -450,13 +466,13 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
       if (k >= 0) {
 #pragma unroll
         for (int sl = 0; sl < S; sl += 2) {
-          const int t0 = NWAVES * sl + wave, t1 = t0 + NWAVES;
-          const bool a0 = t0 < ntiles && tij[t0][1] > k && !(tij[t0][0] == k + 1 && tij[t0][1] == k + 1);
-          const bool a1 = sl + 1 < S && t1 < ntiles && tij[t1][1] > k &&
-                          !(tij[t1][0] == k + 1 && tij[t1][1] == k + 1);
+          const int I0 = sI[sl], J0 = sJ[sl];
+          const int I1 = sl + 1 < S ? sI[sl + 1] : -1, J1 = sl + 1 < S ? sJ[sl + 1] : -1;
+          const bool a0 = J0 > k && !(I0 == k + 1 && J0 == k + 1);
+          const bool a1 = J1 > k && !(I1 == k + 1 && J1 == k + 1);
           if (a0 || a1) {
-            const int i0 = a0 ? tij[t0][0] : tij[t1][0], j0 = a0 ? tij[t0][1] : tij[t1][1];
-            const int i1 = a1 ? tij[t1][0] : i0, j1 = a1 ? tij[t1][1] : j0;
+            const int i0 = a0 ? I0 : I1, j0 = a0 ? J0 : J1;
+            const int i1 = a1 ? I1 : i0, j1 = a1 ? J1 : j0;
             V4 x0 = acc[sl];
             V4 x1 = sl + 1 < S ? acc[sl + 1] : acc[sl];
 #pragma unroll
@@ -496,9 +512,8 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
       // are the B operand
 #pragma unroll
       for (int sl = 0; sl < S; ++sl) {
-        const int t = NWAVES * sl + wave;
-        if (t < ntiles && tij[t][0] == j && tij[t][1] < j) {
-          const int I = tij[t][1];
+        if (sI[sl] == j && sJ[sl] >= 0 && sJ[sl] < j) {
+          const int I = sJ[sl];
           V4 z = ld_acc<double>(Rt(I), lane);
 #pragma unroll
           for (int cch = 0; cch < 4; ++cch) z = Mfma<double>::op(-ld_rowcol(Rt(j), cch, lane), acc[sl][cch], z);
