@@ -48,6 +48,7 @@ struct Choice {
   int fam = -1;
   int pw = 0;    // panel width (left-looking)
   int occ = 1;   // resident workgroups per CU the kernel is built for (left-looking)
+  int nw = 8;    // waves per element (left-looking)
 };
 
 }  // namespace
@@ -60,6 +61,7 @@ struct mhm_ctx_s {
   bool no_rr = false;          // MHM_NO_RR=1: never use the register-tile kernel
   bool no_ll = false;          // MHM_NO_LL=1: never use the left-looking kernel
   bool ll_occ2 = false;        // MHM_LL_OCC2=1: left-looking default with two workgroups per CU
+  bool ll_nw16 = false;        // MHM_LL_NW16=1: left-looking default with 16 waves where it applies
   void* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t aux[kNumClasses] = {};   // class streams of ragged runs
@@ -151,8 +153,8 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
       p.grid = one_each;
       break;
     case FAM_LL:
-      p.ok = mhm::local_ll_has(fp32, ch.pw, p.nt, ch.occ);
-      p.lds = mhm::local_ll_lds_bytes(fp32, ch.pw, p.n_cap, p.f_cap);
+      p.ok = mhm::local_ll_has(fp32, ch.pw, p.nt, ch.occ, ch.nw);
+      p.lds = mhm::local_ll_lds_bytes(fp32, ch.pw, p.n_cap, p.f_cap, ch.nw);
       p.grid = slots;
       p.tile_cap += p.nt;   // the diagonal factor tiles kept for the factor output
       if (cached) p.tile_cap = p.nt;   // factor in the caller's store: the RHS row only
@@ -173,7 +175,8 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
 // Default family when nothing was tuned.
 Choice default_choice(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_cap, bool listed) {
   const Choice ll = c->ll_occ2 ? Choice{FAM_LL, 2, 2} : Choice{FAM_LL, mhm::local_ll_default_panel(fp32), 1};
-  const Choice cands[] = {{FAM_RR, 0}, {FAM_LDS, 0}, ll, {FAM_WS, 0}};
+  const Choice ll16{FAM_LL, 2, 1, 16};
+  const Choice cands[] = {{FAM_RR, 0}, {FAM_LDS, 0}, c->ll_nw16 ? ll16 : ll, ll, {FAM_WS, 0}};
   for (const Choice& ch : cands) {
     if (ch.fam == FAM_RR && c->no_rr) continue;
     if (ch.fam == FAM_LL && c->no_ll) continue;
@@ -284,7 +287,8 @@ hipError_t launch_plan(const Plan& p, const mhm_batch* b, const mhm::LocalArgs& 
   switch (p.ch.fam) {
     case FAM_RR: return mhm::launch_local_rr(p.fused, b, a, p.lds, p.grid, st);
     case FAM_LDS: return mhm::launch_local(p.fp32, true, p.fused, b, a, p.lds, p.grid, st);
-    case FAM_LL: return mhm::launch_local_ll(p.fp32, p.fused, p.ch.pw, p.ch.occ, p.nt, b, a, p.lds, p.grid, st);
+    case FAM_LL:
+      return mhm::launch_local_ll(p.fp32, p.fused, p.ch.pw, p.ch.occ, p.ch.nw, p.nt, b, a, p.lds, p.grid, st);
     default: return mhm::launch_local(p.fp32, false, p.fused, b, a, p.lds, p.grid, st);
   }
 }
@@ -429,7 +433,8 @@ Choice tune_class(mhm_ctx c, const mhm_batch* b, bool fp32, const RunPlan& base,
                   int32_t* dcount, int cap, int count, std::string& log, mhm_status& st) {
   const ClassRun& r0 = base.run[i];
   std::vector<Choice> cands;
-  const Choice all[] = {{FAM_RR, 0, 1}, {FAM_LDS, 0, 1}, {FAM_LL, 2, 1}, {FAM_LL, 4, 1}, {FAM_LL, 2, 2}, {FAM_WS, 0, 1}};
+  const Choice all[] = {{FAM_RR, 0, 1},  {FAM_LDS, 0, 1},    {FAM_LL, 2, 1},    {FAM_LL, 4, 1},
+                        {FAM_LL, 2, 2},  {FAM_LL, 2, 1, 16}, {FAM_LL, 4, 1, 16}, {FAM_WS, 0, 1}};
   bool have_ll = false;
   for (const Choice& ch : all) {
     if (ch.fam == FAM_RR && c->no_rr) continue;
@@ -471,9 +476,10 @@ Choice tune_class(mhm_ctx c, const mhm_batch* b, bool fp32, const RunPlan& base,
     }
     if (st != MHM_OK) break;
     std::snprintf(buf, sizeof(buf),
-                  "%s{\"s_max\": %d, \"prec\": \"%s\", \"kernel\": \"%s\", \"pw\": %d, \"wg_per_cu\": %d, \"ms\": %.4f, "
-                  "\"elements\": %d}",
-                  log.empty() ? "" : ", ", r.s_cap, fp32 ? "fp32_ir" : "fp64", fam_name(ch.fam), ch.pw, ch.occ, ms, sub);
+                  "%s{\"s_max\": %d, \"prec\": \"%s\", \"kernel\": \"%s\", \"pw\": %d, \"wg_per_cu\": %d, "
+                  "\"waves\": %d, \"ms\": %.4f, \"elements\": %d}",
+                  log.empty() ? "" : ", ", r.s_cap, fp32 ? "fp32_ir" : "fp64", fam_name(ch.fam), ch.pw, ch.occ,
+                  ch.fam == FAM_LL ? ch.nw : 4, ms, sub);
     log += buf;
     if (best_ms == 0.0f || ms < best_ms) {
       best_ms = ms;
@@ -507,6 +513,8 @@ mhm_status mhm_create(mhm_ctx* out, int device, void* hip_stream) {
   c->no_ll = nll && nll[0] == '1';
   const char* occ2 = std::getenv("MHM_LL_OCC2");
   c->ll_occ2 = occ2 && occ2[0] == '1';
+  const char* nw16 = std::getenv("MHM_LL_NW16");
+  c->ll_nw16 = nw16 && nw16[0] == '1';
   c->stream = static_cast<hipStream_t>(hip_stream);
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0) c->n_cu = v;
@@ -641,7 +649,8 @@ mhm_status mhm_autotune(mhm_ctx c, const mhm_batch* b, mhm_prec prec, double* X,
   size_t need = 0;
   for (int i = 0; i < base.n_runs; ++i) {
     for (const Choice ch : {Choice{FAM_RR, 0, 1}, Choice{FAM_LDS, 0, 1}, Choice{FAM_LL, 2, 1}, Choice{FAM_LL, 4, 1},
-                            Choice{FAM_LL, 2, 2}, Choice{FAM_WS, 0, 1}}) {
+                            Choice{FAM_LL, 2, 2}, Choice{FAM_LL, 2, 1, 16}, Choice{FAM_LL, 4, 1, 16},
+                            Choice{FAM_WS, 0, 1}}) {
       const Plan p = plan_for(c, b, fp32, true, base.run[i].s_cap, ch, base.listed);
       if (p.ok) need = std::max(need, p.ws_need);
     }

@@ -63,12 +63,12 @@ int local_rr_max_nt();
 hipError_t launch_local_rr(bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid, hipStream_t st);
 // Left-looking kernel for large elements (tiles in a workspace slot), panel
 // width pw (block columns of pw tiles).
-int local_ll_rows_per_wave(int nt);
+int local_ll_rows_per_wave(int nt, int nw);
 int local_ll_default_panel(bool fp32);
-bool local_ll_has(bool fp32, int pw, int nt, int occ);
-size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap);
-hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nt_max, const mhm_batch* bt, LocalArgs a,
-                           size_t lds, int grid, hipStream_t st);
+bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw);
+size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap, int nw);
+hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, int nt_max, const mhm_batch* bt,
+                           LocalArgs a, size_t lds, int grid, hipStream_t st);
 hipError_t launch_local(bool fp32, bool in_lds, bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
                         hipStream_t st);
 

@@ -25,8 +25,6 @@
 namespace mhm {
 
 namespace ll {
-constexpr int NW = 8;
-constexpr int NTHREADS = 64 * NW;
 
 // One block triangular sweep over the right-hand-side tile row of the factor
 // (tiles tl(nt, i) hold Z_i^T, 16 right-hand sides by 16 nodes; the diagonal
@@ -40,7 +38,7 @@ constexpr int NTHREADS = 64 * NW;
 // The L operands of a step are loaded one or two steps ahead, so their
 // global-memory latency overlaps the chain of column solves.  Every register
 // slot is addressed statically.
-template <typename T, int RPW, bool BACK, int OCC>
+template <typename T, int RPW, bool BACK, int OCC, int NW>
 __device__ __forceinline__ void sweep_body(T* Lb, T* rhs_row, int nt, T* xb, T* scr, int wave, int lane) {
   typedef typename Mfma<T>::v4 V4;
   auto tl = [=](int I, int J) -> T* {
@@ -48,8 +46,8 @@ __device__ __forceinline__ void sweep_body(T* Lb, T* rhs_row, int nt, T* xb, T* 
   };
   // operand buffers (prefetch depth): FP32 sweeps run in their own function
   // with registers to spare; FP64 ones are inlined in the kernel
-  // (two workgroups per CU: half the registers, one buffer)
-  constexpr int NB = OCC == 2 ? 1 : sizeof(T) == 4 ? (RPW <= 5 ? 3 : 2) : (RPW <= 5 ? 2 : 1);
+  // (two workgroups per CU or 16 waves: half the registers, one buffer)
+  constexpr int NB = (OCC == 2 || NW == 16) ? 1 : sizeof(T) == 4 ? (RPW <= 5 ? 3 : 2) : (RPW <= 5 ? 2 : 1);
   V4 z[RPW];
 #pragma unroll
   for (int ri = 0; ri < RPW; ++ri) {
@@ -145,24 +143,27 @@ __device__ __forceinline__ void sweep_body(T* Lb, T* rhs_row, int nt, T* xb, T* 
 }
 // The same sweep as a separate function (the FP32 refinement loop calls it
 // twice per step: inlined copies would add their registers to the kernel's).
-template <typename T, int RPW, bool BACK, int OCC>
+template <typename T, int RPW, bool BACK, int OCC, int NW>
 __device__ __noinline__ void sweep_call(T* Lb, T* rhs_row, int nt, T* xb, T* scr, int wave, int lane) {
-  sweep_body<T, RPW, BACK, OCC>(Lb, rhs_row, nt, xb, scr, wave, lane);
+  sweep_body<T, RPW, BACK, OCC, NW>(Lb, rhs_row, nt, xb, scr, wave, lane);
 }
-template <typename T, int RPW, bool BACK, int OCC>
+template <typename T, int RPW, bool BACK, int OCC, int NW>
 __device__ __forceinline__ void sweep(T* Lb, T* rhs_row, int nt, T* xb, T* scr, int wave, int lane) {
-  if constexpr (sizeof(T) == 4) sweep_call<T, RPW, BACK, OCC>(Lb, rhs_row, nt, xb, scr, wave, lane);
-  else sweep_body<T, RPW, BACK, OCC>(Lb, rhs_row, nt, xb, scr, wave, lane);
+  if constexpr (sizeof(T) == 4) sweep_call<T, RPW, BACK, OCC, NW>(Lb, rhs_row, nt, xb, scr, wave, lane);
+  else sweep_body<T, RPW, BACK, OCC, NW>(Lb, rhs_row, nt, xb, scr, wave, lane);
 }
 }  // namespace ll
 
 // OCC = 2: the register budget of two resident workgroups per CU (4 waves
-// per SIMD, at most 128 registers per lane; two
-// elements interleave their latencies), with one operand buffer.
-template <typename T, bool FUSED, int PW, int RPW, int OCC>
-__global__ void __launch_bounds__(ll::NTHREADS, 2 * OCC) k_local_ll(BatchDev b, LocalArgs args) {
-  using namespace ll;
+// per SIMD, at most 128 registers per lane; two elements interleave their
+// latencies), with one operand buffer.  NWV = 16: 16 waves per element
+// (half the rows per wave, at most 128 registers per lane, twice the waves
+// in flight).
+template <typename T, bool FUSED, int PW, int RPW, int OCC, int NWV>
+__global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev b, LocalArgs args) {
   typedef typename Mfma<T>::v4 V4;
+  constexpr int NW = NWV;
+  constexpr int NTHREADS = 64 * NW;
   __shared__ Elem E;
   __shared__ int ok, bad, conv;
   __shared__ double be_prev;
@@ -320,8 +321,8 @@ __global__ void __launch_bounds__(ll::NTHREADS, 2 * OCC) k_local_ll(BatchDev b, 
     };
 
     T* xb = stage;   // two published solution tiles of the sweeps (staging area)
-    auto backward = [&]() { ll::sweep<T, RPW, true, OCC>(Lb, rhs_row, nt, xb, scr, wave, lane); };
-    auto forward = [&]() { ll::sweep<T, RPW, false, OCC>(Lb, rhs_row, nt, xb, scr, wave, lane); };
+    auto backward = [&]() { ll::sweep<T, RPW, true, OCC, NW>(Lb, rhs_row, nt, xb, scr, wave, lane); };
+    auto forward = [&]() { ll::sweep<T, RPW, false, OCC, NW>(Lb, rhs_row, nt, xb, scr, wave, lane); };
 
     // ------------------------------------------------------ factorisation
     if (reuse) {
@@ -360,10 +361,12 @@ __global__ void __launch_bounds__(ll::NTHREADS, 2 * OCC) k_local_ll(BatchDev b, 
         constexpr int SPT = (PW * TILE + NTHREADS - 1) / NTHREADS;
         // operand buffers (prefetch depth) within a register estimate
         constexpr int W = (int)sizeof(T) / 4;
-        constexpr int NB = OCC == 2                                                ? 1
-                           : RPW * PW * 4 * W + 3 * (RPW * 4 + SPT) * W <= 144 ? 3
-                           : RPW * PW * 4 * W + 2 * (RPW * 4 + SPT) * W <= 160 ? 2
-                                                                               : 1;
+        // (budgets for 256 registers per lane, or 128 with 16 waves)
+        constexpr int B3 = NW == 16 ? 72 : 144, B2 = NW == 16 ? 96 : 160;
+        constexpr int NB = OCC == 2                                               ? 1
+                           : RPW * PW * 4 * W + 3 * (RPW * 4 + SPT) * W <= B3 ? 3
+                           : RPW * PW * 4 * W + 2 * (RPW * 4 + SPT) * W <= B2 ? 2
+                                                                              : 1;
         T ab[NB][RPW][4];
         T sb[NB][SPT];
         auto fetch = [&](int m, T (&a)[RPW][4], T (&sv)[SPT]) {
@@ -590,12 +593,12 @@ __global__ void __launch_bounds__(ll::NTHREADS, 2 * OCC) k_local_ll(BatchDev b, 
   }
 }
 
-template <typename T, bool FUSED, int PW, int RPW, int OCC>
+template <typename T, bool FUSED, int PW, int RPW, int OCC, int NWV = 8>
 static hipError_t launch_ll_t(const BatchDev& d, LocalArgs a, size_t lds, int grid, hipStream_t st) {
-  auto kern = k_local_ll<T, FUSED, PW, RPW, OCC>;
+  auto kern = k_local_ll<T, FUSED, PW, RPW, OCC, NWV>;
   hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(ll::NTHREADS), lds, st, d, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NWV), lds, st, d, a);
   return hipGetLastError();
 }
 

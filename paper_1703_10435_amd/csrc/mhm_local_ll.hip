@@ -5,24 +5,27 @@
 
 namespace mhm {
 
-hipError_t launch_local_ll_f32(bool fused, int pw, int occ, int rpw, const BatchDev& d, LocalArgs a, size_t lds,
-                               int grid, hipStream_t st);
-hipError_t launch_local_ll_f64(bool fused, int pw, int occ, int rpw, const BatchDev& d, LocalArgs a, size_t lds,
-                               int grid, hipStream_t st);
+hipError_t launch_local_ll_f32(bool fused, int pw, int occ, int nw, int rpw, const BatchDev& d, LocalArgs a,
+                               size_t lds, int grid, hipStream_t st);
+hipError_t launch_local_ll_f64(bool fused, int pw, int occ, int nw, int rpw, const BatchDev& d, LocalArgs a,
+                               size_t lds, int grid, hipStream_t st);
 
-int local_ll_rows_per_wave(int nt) {
+int local_ll_rows_per_wave(int nt, int nw) {
   const int rows = nt + 1;
-  if (rows <= 2 * ll::NW) return 2;
-  if (rows <= 3 * ll::NW) return 3;
-  if (rows <= 5 * ll::NW) return 5;
-  if (rows <= 10 * ll::NW) return 10;
+  if (rows <= 2 * nw) return 2;
+  if (rows <= 3 * nw) return 3;
+  if (rows <= 5 * nw) return 5;
+  if (rows <= 10 * nw && nw == 8) return 10;
   return -1;
 }
 
 int local_ll_default_panel(bool fp32) { return fp32 ? 4 : 2; }
 
-bool local_ll_has(bool fp32, int pw, int nt, int occ) {
-  const int rpw = local_ll_rows_per_wave(nt);
+bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw) {
+  if (nw == 16)   // built for the largest elements only (49 to 80 tile rows)
+    return occ == 1 && nt + 1 > 48 && local_ll_rows_per_wave(nt, 16) == 5 && (pw == 2 || (fp32 && pw == 4));
+  if (nw != 8) return false;
+  const int rpw = local_ll_rows_per_wave(nt, 8);
   if (rpw < 0) return false;
   if (occ == 2) return pw == 2 && (fp32 || rpw <= 3);
   if (occ != 1) return false;
@@ -30,18 +33,18 @@ bool local_ll_has(bool fp32, int pw, int nt, int occ) {
   return pw == 2 || (pw == 4 && rpw <= 3);
 }
 
-size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap) {
+size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap, int nw) {
   return sizeof(double) * (2 * (size_t)n_cap + (size_t)f_cap) +
-         (size_t)(2 * pw + 1 + pw + ll::NW) * TILE * (fp32 ? sizeof(float) : sizeof(double));
+         (size_t)(2 * pw + 1 + pw + nw) * TILE * (fp32 ? sizeof(float) : sizeof(double));
 }
 
-hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nt_max, const mhm_batch* bt, LocalArgs a,
-                           size_t lds, int grid, hipStream_t st) {
-  if (!local_ll_has(fp32, pw, nt_max, occ)) return hipErrorInvalidValue;
-  const int rpw = local_ll_rows_per_wave(nt_max);
+hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, int nt_max, const mhm_batch* bt,
+                           LocalArgs a, size_t lds, int grid, hipStream_t st) {
+  if (!local_ll_has(fp32, pw, nt_max, occ, nw)) return hipErrorInvalidValue;
+  const int rpw = local_ll_rows_per_wave(nt_max, nw);
   const BatchDev d = to_dev(bt);
-  return fp32 ? launch_local_ll_f32(fused, pw, occ, rpw, d, a, lds, grid, st)
-              : launch_local_ll_f64(fused, pw, occ, rpw, d, a, lds, grid, st);
+  return fp32 ? launch_local_ll_f32(fused, pw, occ, nw, rpw, d, a, lds, grid, st)
+              : launch_local_ll_f64(fused, pw, occ, nw, rpw, d, a, lds, grid, st);
 }
 
 }  // namespace mhm

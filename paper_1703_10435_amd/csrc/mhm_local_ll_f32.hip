@@ -1,5 +1,6 @@
 // FP32 instances of the left-looking kernel (panel widths 2 and 4; panel
-// width 2 also with two resident workgroups per CU).
+// width 2 also with two resident workgroups per CU; 16 waves per element
+// for the largest elements).
 #include "mhm_local_ll.h"
 
 namespace mhm {
@@ -15,8 +16,16 @@ static hipError_t launch_rpw(int rpw, const BatchDev& d, LocalArgs a, size_t lds
   }
 }
 
-hipError_t launch_local_ll_f32(bool fused, int pw, int occ, int rpw, const BatchDev& d, LocalArgs a, size_t lds,
-                               int grid, hipStream_t st) {
+hipError_t launch_local_ll_f32(bool fused, int pw, int occ, int nw, int rpw, const BatchDev& d, LocalArgs a,
+                               size_t lds, int grid, hipStream_t st) {
+  if (nw == 16) {
+    if (rpw != 5 || occ != 1) return hipErrorInvalidValue;
+    if (pw == 2) return fused ? launch_ll_t<float, true, 2, 5, 1, 16>(d, a, lds, grid, st)
+                              : launch_ll_t<float, false, 2, 5, 1, 16>(d, a, lds, grid, st);
+    if (pw == 4) return fused ? launch_ll_t<float, true, 4, 5, 1, 16>(d, a, lds, grid, st)
+                              : launch_ll_t<float, false, 4, 5, 1, 16>(d, a, lds, grid, st);
+    return hipErrorInvalidValue;
+  }
   if (occ == 2) {
     if (pw != 2) return hipErrorInvalidValue;
     return fused ? launch_rpw<true, 2, 2>(rpw, d, a, lds, grid, st) : launch_rpw<false, 2, 2>(rpw, d, a, lds, grid, st);

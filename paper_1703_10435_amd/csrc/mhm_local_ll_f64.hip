@@ -1,6 +1,7 @@
 // FP64 instances of the left-looking kernel (panel width 2; width 4 for up to
 // 24 tile rows, where the register panel still fits; width 2 with two
-// resident workgroups per CU for up to 24 tile rows).
+// resident workgroups per CU for up to 24 tile rows; 16 waves per element
+// for the largest elements).
 #include "mhm_local_ll.h"
 
 namespace mhm {
@@ -32,8 +33,13 @@ static hipError_t launch_occ2(int rpw, const BatchDev& d, LocalArgs a, size_t ld
   }
 }
 
-hipError_t launch_local_ll_f64(bool fused, int pw, int occ, int rpw, const BatchDev& d, LocalArgs a, size_t lds,
-                               int grid, hipStream_t st) {
+hipError_t launch_local_ll_f64(bool fused, int pw, int occ, int nw, int rpw, const BatchDev& d, LocalArgs a,
+                               size_t lds, int grid, hipStream_t st) {
+  if (nw == 16) {
+    if (rpw != 5 || occ != 1 || pw != 2) return hipErrorInvalidValue;
+    return fused ? launch_ll_t<double, true, 2, 5, 1, 16>(d, a, lds, grid, st)
+                 : launch_ll_t<double, false, 2, 5, 1, 16>(d, a, lds, grid, st);
+  }
   if (occ == 2) {
     if (pw != 2) return hipErrorInvalidValue;
     return fused ? launch_occ2<true>(rpw, d, a, lds, grid, st) : launch_occ2<false>(rpw, d, a, lds, grid, st);

@@ -177,16 +177,6 @@ __device__ __forceinline__ int potrf_inv(double* t, double* Lo, int n, int k, in
   return bad;
 }
 
-// acc[sl] = x for a run-time slot index (each case uses a fixed register set)
-#define RR_SET_SLOT(ACC, SL, X)                                                            \
-  switch (SL) {                                                                           \
-    case 0: ACC[0] = X; break;   case 1: ACC[1] = X; break;   case 2: ACC[2] = X; break;   \
-    case 3: ACC[3] = X; break;   case 4: ACC[4] = X; break;   case 5: ACC[5] = X; break;   \
-    case 6: ACC[6] = X; break;   case 7: ACC[7] = X; break;   case 8: ACC[8] = X; break;   \
-    case 9: ACC[9] = X; break;   case 10: ACC[10] = X; break; case 11: ACC[11] = X; break; \
-    case 12: ACC[12] = X; break; default: ACC[13] = X; break;                               \
-  }
-static_assert(S == 14, "RR_SET_SLOT covers 14 slots");
 
 __device__ __forceinline__ void store_L(double* Lo, int n, int I, int J, const V4& acc, int lane) {
   const int q = 16 * J + (lane & 15);
@@ -209,7 +199,6 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
   __shared__ double colsum[16];
   __shared__ double cx[16];
   __shared__ double gam;
-  __shared__ short tij[NTILES][2];     // tile number -> (I, J), column-major over the lower triangle
   extern __shared__ double dyn[];      // c | bf | ft | kap | stencil[8 n] | P[NT] | W[NT] | R[NT]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int NImax = 3 * (b.l_max + 1);
@@ -247,6 +236,26 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
     if (!ok) continue;
     const int s = E.s, n = E.n, r = E.r, nt = E.nt, T2 = s * s;
     const int ntiles = nt * (nt + 1) / 2;
+    // Tile coordinates of this wave's slots (tile 4 sl + wave of the
+    // column-major lower triangle, whose column J starts at tile
+    // J nt - J (J - 1) / 2; -1 past its end), wave-uniform registers: the
+    // slot tests of every step need no table reads.
+    int sI[S], sJ[S];
+    {
+      const int wv = __builtin_amdgcn_readfirstlane(wave);
+      const float b2 = 2.0f * nt + 1.0f;
+#pragma unroll
+      for (int sl = 0; sl < S; ++sl) {
+        const int t = NWAVES * sl + wv;
+        int J = (int)((b2 - sqrtf(b2 * b2 - 8.0f * t)) * 0.5f);
+        J = J < 0 ? 0 : (J > nt - 1 ? nt - 1 : J);
+        while (J > 0 && J * nt - (J * (J - 1)) / 2 > t) --J;
+        while (J < nt - 1 && (J + 1) * nt - ((J + 1) * J) / 2 <= t) ++J;
+        const bool in = t < ntiles;
+        sI[sl] = in ? J + t - (J * nt - (J * (J - 1)) / 2) : -1;
+        sJ[sl] = in ? J : -1;
+      }
+    }
     const double* kapg = b.kappa + E.tri0;
     auto kap = [&](int t) -> double { return FUSED ? kapl[t] : kapg[t]; };
 
@@ -259,15 +268,6 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
         const int ef = a / lp1, q = a - ef * lp1;
         ft[idx] = face_load(E, ef, q, k);
       }
-    }
-    if (tid == 0) {
-      int t = 0;
-      for (int J = 0; J < nt; ++J)
-        for (int I = J; I < nt; ++I) {
-          tij[t][0] = (short)I;
-          tij[t][1] = (short)J;
-          ++t;
-        }
     }
     __syncthreads();
     {
@@ -310,12 +310,11 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
       const double g = gam;
       const int cl = lane & 15, grp = lane >> 4;
       const double* A = FUSED ? nullptr : args.Ahat + E.mat0;
-#pragma unroll 1
+#pragma unroll
       for (int sl = 0; sl < S; ++sl) {
-        const int t = NWAVES * sl + wave;
         V4 v4 = {0, 0, 0, 0};
-        if (t < ntiles) {
-          const int I = tij[t][0], J = tij[t][1];
+        if (sI[sl] >= 0) {
+          const int I = sI[sl], J = sJ[sl];
           const int q = 16 * J + cl;
           if (FUSED) {
             // stencil couplings reach |p - q| <= s + 2: only tiles near the diagonal
@@ -358,11 +357,13 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
             }
           }
         }
-        RR_SET_SLOT(acc, sl, v4)
+        acc[sl] = v4;
       }
       // right-hand-side row
       const double* Bt = FUSED ? nullptr : args.Btil + E.rhs0;
-      for (int J = 0; J < nt; ++J) {
+#pragma unroll
+      for (int J = 0; J < NT; ++J) {
+        if (J >= nt) break;
         const int a = tid >> 4, cq = tid & 15, q = 16 * J + cq;
         double x = 0.0;
         if (a < r && q < n) {
@@ -387,24 +388,6 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
     }
     double* Lo = (!FUSED && args.Lout && E.mat0 >= 0) ? args.Lout + E.mat0 : nullptr;
     __syncthreads();
-
-    // Tile coordinates of this wave's slots (tile 4 sl + wave of the
-    // column-major lower triangle; -1 past its end), wave-uniform registers:
-    // the slot tests of every step need no table reads.
-    int sI[S], sJ[S];
-    {
-      const int wv = __builtin_amdgcn_readfirstlane(wave);
-#pragma unroll
-      for (int sl = 0; sl < S; ++sl) {
-        int t = NWAVES * sl + wv, J = 0;
-        while (J < nt && t >= nt - J) {
-          t -= nt - J;
-          ++J;
-        }
-        sI[sl] = J < nt ? J + t : -1;
-        sJ[sl] = J < nt ? J : -1;
-      }
-    }
 
     // ------------------------------------------------------- factorisation
     // Step k = -1 only hands tile (0, 0) to the factor.  The RHS row is

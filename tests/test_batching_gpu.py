@@ -70,15 +70,15 @@ def test_every_size_class_in_one_batch(ctx, prec):
 
 
 @pytest.mark.parametrize("env", [{"MHM_NO_RR": "1"}, {"MHM_NO_LL": "1"}, {"MHM_NO_RR": "1", "MHM_NO_LL": "1"},
-                                 {"MHM_NO_RR": "1", "MHM_LL_OCC2": "1"}])
+                                 {"MHM_NO_RR": "1", "MHM_LL_OCC2": "1"}, {"MHM_LL_NW16": "1"}])
 def test_kernel_families_agree_with_oracle(env):
     """The families the defaults do not pick (LDS tiles for small FP64
     elements, the right-looking workspace kernel for large ones, the
-    left-looking kernel built for two workgroups per CU)."""
+    left-looking kernel built for two workgroups per CU or with 16 waves)."""
     from paper_1703_10435_amd import engine
     c = _ctx(env)
     try:
-        b = _random_batch(22, [5, 12, 16, 20, 30, 40], [2, 1, 3, 0, 2, 3], "families")
+        b = _random_batch(22, [5, 12, 16, 20, 30, 40, 48], [2, 1, 3, 0, 2, 3, 1], "families")
         for prec in (0, 1):
             say(f"[gpu] families env={env} prec={prec}")
             res, out, db = engine.solve_batch(b, prec=prec, mode="fused", ctx=c)
