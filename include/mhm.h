@@ -173,6 +173,38 @@ mhm_status mhm_local_batch_run(mhm_ctx ctx, const mhm_batch* batch, mhm_prec pre
                                double* X, double* M, double* E, double* B, double* F,
                                int32_t* info, int32_t* ir_iters, int max_iters);
 
+/* Around the path: the assembly of the skeleton system eq. (6) from the
+ * element contributions (the reduce step of reduceLocalProblems,
+ * Algorithm 1) and computeSolution, eq. (4).  The global numbering is the
+ * caller's; both calls take
+ *   gdof   [n_elem * NImax] device int32, NImax = 3 (l_max + 1): global row
+ *          of local face DoF a of element e (entries a >= N_I of the element
+ *          are not read),
+ *   erow   [n_elem] device int32: global row of the element's constant u_0,
+ *   n_rows rows of the skeleton system; an index outside [0, n_rows) is an
+ *          error of the data, handled per call below.
+ * mhm_skeleton_scatter adds, for every element whose info[e] is 0 or -1
+ * (info may be NULL), M[a][b] at (gdof[a], gdof[b]), B[a] at (erow, gdof[a])
+ * and (gdof[a], erow), E[a] to rhs[gdof[a]] and F to rhs[erow], into a CSR
+ * matrix whose pattern (row_ptr [n_rows+1], col_idx sorted within each row,
+ * both device int32) the caller built.  vals [nnz] and rhs [n_rows]
+ * accumulate: clear them first for a fresh system.  The additions are FP64
+ * atomics, so their order, and with three or more terms per entry the last
+ * bits, vary between runs.  An entry absent from the pattern or with an
+ * index out of range is skipped and counted in *missing (device int32, may
+ * be NULL; it accumulates too).
+ * mhm_reconstruct writes u[node_off[e] + p] = sol[erow[e]] +
+ * sum_a X[p][a] sol[gdof[e][a]] + X[p][N_I] (the nodal values of u_{H,h} on
+ * the element's sub-mesh, in lattice order) for every element whose info is
+ * 0 or -1; other elements' nodes are left as they are.  An out-of-range
+ * index makes the element's values NaN.  The batch needs node_off. */
+mhm_status mhm_skeleton_scatter(mhm_ctx ctx, const mhm_batch* batch, const double* M, const double* E,
+                                const double* B, const double* F, const int32_t* gdof, const int32_t* erow,
+                                const int32_t* row_ptr, const int32_t* col_idx, int32_t n_rows, double* vals,
+                                double* rhs, const int32_t* info, int32_t* missing);
+mhm_status mhm_reconstruct(mhm_ctx ctx, const mhm_batch* batch, const double* X, const int32_t* gdof,
+                           const int32_t* erow, const double* sol, int32_t n_rows, double* u, const int32_t* info);
+
 /* Factor reuse (Section 3: the local matrix is factored once and reused
  * for further load vectors, e.g. over time steps): mhm_local_batch_run with
  * each element's factor kept in a caller-owned device store.

@@ -22,7 +22,7 @@ EXPORTS = (
     "mhm_create", "mhm_destroy", "mhm_set_stream", "mhm_last_error", "mhm_sync", "mhm_workspace_bytes",
     "mhm_local_assemble", "mhm_local_factor_solve", "mhm_skeleton_contrib", "mhm_local_batch_run",
     "mhm_autotune", "mhm_tune_report", "mhm_graph_create", "mhm_graph_launch", "mhm_graph_destroy",
-    "mhm_factor_bytes", "mhm_local_batch_run_cached",
+    "mhm_factor_bytes", "mhm_local_batch_run_cached", "mhm_skeleton_scatter", "mhm_reconstruct",
 )
 
 
@@ -76,6 +76,8 @@ def load(path: str = LIB_PATH):
         "mhm_graph_destroy": (i32, [vp]),
         "mhm_factor_bytes": (ctypes.c_size_t, [i32, i32]),
         "mhm_local_batch_run_cached": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]),
+        "mhm_skeleton_scatter": (i32, [vp, bp] + [vp] * 8 + [i32] + [vp] * 4),
+        "mhm_reconstruct": (i32, [vp, bp, vp, vp, vp, vp, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -163,6 +165,16 @@ class Context:
         self._check(self.lib.mhm_local_batch_run_cached(
             self.h, ctypes.byref(batch.desc), prec, _ptr(factors), _ptr(factor_off), _ptr(factor_state), _ptr(X),
             _ptr(M), _ptr(E), _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters), max_iters))
+
+    def skeleton_scatter(self, batch, M, E, B, F, gdof, erow, row_ptr, col_idx, n_rows, vals, rhs, info=None,
+                         missing=None):
+        self._check(self.lib.mhm_skeleton_scatter(self.h, ctypes.byref(batch.desc), _ptr(M), _ptr(E), _ptr(B), _ptr(F),
+                                                  _ptr(gdof), _ptr(erow), _ptr(row_ptr), _ptr(col_idx), int(n_rows),
+                                                  _ptr(vals), _ptr(rhs), _ptr(info), _ptr(missing)))
+
+    def reconstruct(self, batch, X, gdof, erow, sol, n_rows, u, info=None):
+        self._check(self.lib.mhm_reconstruct(self.h, ctypes.byref(batch.desc), _ptr(X), _ptr(gdof), _ptr(erow),
+                                             _ptr(sol), int(n_rows), _ptr(u), _ptr(info)))
 
     def tune_report(self) -> str:
         n = int(self.lib.mhm_tune_report(self.h, None, 0))

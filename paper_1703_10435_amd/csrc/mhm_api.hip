@@ -612,6 +612,34 @@ mhm_status mhm_local_batch_run(mhm_ctx c, const mhm_batch* b, mhm_prec prec, dou
   return run_local(c, b, prec, true, fused_io(X, M, E, B, F, info, ir_iters, max_iters));
 }
 
+mhm_status mhm_reconstruct(mhm_ctx c, const mhm_batch* b, const double* X, const int32_t* gdof, const int32_t* erow,
+                           const double* sol, int32_t n_rows, double* u, const int32_t* info) {
+  mhm_status st = check_batch(c, b, false, true);
+  if (st != MHM_OK || b->n_elem == 0) return st;
+  if (!X || !gdof || !erow || !sol || !u) return fail(c, MHM_E_ARG, "X, gdof, erow, sol and u are required");
+  if (n_rows < 1) return fail(c, MHM_E_ARG, "n_rows < 1");
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = mhm::launch_reconstruct(b, X, gdof, erow, sol, n_rows, u, info, grid_for(b), c->stream);
+  return e == hipSuccess ? MHM_OK : hip_fail(c, e, "k_reconstruct launch");
+}
+
+mhm_status mhm_skeleton_scatter(mhm_ctx c, const mhm_batch* b, const double* M, const double* E, const double* B,
+                                const double* F, const int32_t* gdof, const int32_t* erow, const int32_t* row_ptr,
+                                const int32_t* col_idx, int32_t n_rows, double* vals, double* rhs,
+                                const int32_t* info, int32_t* missing) {
+  mhm_status st = check_batch(c, b, false, false);
+  if (st != MHM_OK || b->n_elem == 0) return st;
+  if (!M || !E || !B || !F || !gdof || !erow || !row_ptr || !col_idx || !vals || !rhs)
+    return fail(c, MHM_E_ARG, "M, E, B, F, gdof, erow, row_ptr, col_idx, vals and rhs are required");
+  if (n_rows < 1) return fail(c, MHM_E_ARG, "n_rows < 1");
+  hipError_t e = hipSetDevice(c->device);
+  const int grid = std::min<int64_t>(kGridCap, 4 * c->n_cu);
+  if (e == hipSuccess)
+    e = mhm::launch_skeleton_scatter(b, M, E, B, F, gdof, erow, row_ptr, col_idx, n_rows, vals, rhs, info, missing,
+                                     grid, c->stream);
+  return e == hipSuccess ? MHM_OK : hip_fail(c, e, "k_skeleton_scatter launch");
+}
+
 size_t mhm_factor_bytes(int s, mhm_prec prec) {
   if (s < 1 || s > MHM_S_LIMIT) return 0;
   const int nt = (n_of(s) + 15) / 16;

@@ -51,6 +51,14 @@ struct BinClasses {
 };
 hipError_t launch_bin(const mhm_batch* bt, const BinClasses& cls, int32_t* elist, int32_t* counts, hipStream_t st);
 
+hipError_t launch_reconstruct(const mhm_batch* bt, const double* X, const int32_t* gdof, const int32_t* erow,
+                              const double* sol, int32_t n_rows, double* u, const int32_t* info, int grid,
+                              hipStream_t st);
+hipError_t launch_skeleton_scatter(const mhm_batch* bt, const double* M, const double* E, const double* B,
+                                   const double* F, const int32_t* gdof, const int32_t* erow, const int32_t* row_ptr,
+                                   const int32_t* col_idx, int32_t n_rows, double* vals, double* rhs,
+                                   const int32_t* info, int32_t* missing, int grid, hipStream_t st);
+
 hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, double* c, double* area,
                            int32_t* info, int grid, hipStream_t st);
 hipError_t launch_contrib(const mhm_batch* bt, const double* X, double* M, double* E, double* B, double* F,

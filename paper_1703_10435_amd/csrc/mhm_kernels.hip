@@ -451,6 +451,145 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
   }
 }
 
+// ------------------------------------------------ computeSolution, scatter
+// Eq. (4): u = u_0 + sum_a lambda_a eta^a + eta^f at the sub-mesh nodes of
+// each element, with lambda_a = sol[gdof[e][a]] and u_0 = sol[erow[e]].
+// One workgroup per element, nodes across the threads (coalesced X reads).
+__global__ void __launch_bounds__(NTHREADS) k_reconstruct(BatchDev b, const double* X, const int32_t* gdof,
+                                                           const int32_t* erow, const double* sol, int32_t n_rows,
+                                                           double* u, const int32_t* info) {
+  __shared__ Elem E;
+  __shared__ int ok;
+  __shared__ double lam[16];
+  __shared__ double u0;
+  const int tid = threadIdx.x;
+  const int NImax = 3 * (b.l_max + 1);
+  for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
+    __syncthreads();
+    if (tid == 0) {
+      ok = load_elem(b, e, E) && E.rhs0 >= 0 && E.node0 >= 0 && (!info || info[e] == INFO_OK || info[e] == INFO_IR_FALLBACK);
+      if (ok) u0 = (erow[e] >= 0 && erow[e] < n_rows) ? sol[erow[e]] : __longlong_as_double(0x7ff8000000000000ll);
+    }
+    if (tid < 16) lam[tid] = 0.0;
+    __syncthreads();
+    if (!ok) continue;
+    if (tid < E.NI) {
+      const int32_t gi = gdof[(int64_t)e * NImax + tid];
+      lam[tid] = (gi >= 0 && gi < n_rows) ? sol[gi] : __longlong_as_double(0x7ff8000000000000ll);
+    }
+    __syncthreads();
+    const int n = E.n, NI = E.NI;
+    const double* Xe = X + E.rhs0;
+    for (int p = tid; p < n; p += NTHREADS) {
+      double v = u0 + Xe[(int64_t)NI * n + p];
+      for (int a = 0; a < NI; ++a) v += Xe[(int64_t)a * n + p] * lam[a];
+      u[E.node0 + p] = v;
+    }
+  }
+}
+
+// Position of column `col` in row `row` of a CSR pattern with sorted columns
+// (-1 if absent).
+__device__ __forceinline__ int64_t csr_find(const int32_t* row_ptr, const int32_t* col_idx, int row, int col) {
+  int lo = row_ptr[row], hi = row_ptr[row + 1] - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int cm = col_idx[mid];
+    if (cm == col) return mid;
+    if (cm < col) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+// The element share of eq. (6) added into the skeleton system (the assembly
+// part of reduceLocalProblems): rows and columns gdof[e][a] (multipliers) and
+// erow[e] (the element's u_0), M into the multiplier block, B and B^T into
+// the coupling, E and F into the right-hand side.  Vector FP64 atomics;
+// entries missing from the pattern are counted in *missing.
+__global__ void __launch_bounds__(NTHREADS) k_skeleton_scatter(BatchDev b, const double* M, const double* Ev,
+                                                                const double* Bv, const double* F,
+                                                                const int32_t* gdof, const int32_t* erow,
+                                                                const int32_t* row_ptr, const int32_t* col_idx,
+                                                                double* vals, double* rhs, const int32_t* info,
+                                                                int32_t n_rows, int32_t* missing) {
+  const int NImax = 3 * (b.l_max + 1);
+  const int per = NImax * NImax + 2 * NImax + NImax + 1;   // M, B, B^T, E, F
+  const int64_t total = (int64_t)b.n_elem * per;
+  for (int64_t idx = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NTHREADS) {
+    const int e = (int)(idx / per);
+    int k = (int)(idx - (int64_t)e * per);
+    if (info && info[e] != INFO_OK && info[e] != INFO_IR_FALLBACK) continue;
+    const int l = b.l[e];
+    if (l < 0 || l > MHM_L_LIMIT || l > b.l_max) continue;
+    const int NI = 3 * (l + 1);
+    const int32_t* g = gdof + (int64_t)e * NImax;
+    int row = -1, col = -1;
+    double v = 0.0;
+    bool to_rhs = false, used = true;
+    if (k < NImax * NImax) {
+      const int a = k % NImax, c = k / NImax;
+      used = a < NI && c < NI;
+      if (used) {
+        row = g[a];
+        col = g[c];
+        v = M[(int64_t)e * NImax * NImax + k];
+      }
+    } else if ((k -= NImax * NImax) < NImax) {
+      used = k < NI;
+      if (used) {
+        row = erow[e];
+        col = g[k];
+        v = Bv[(int64_t)e * NImax + k];
+      }
+    } else if ((k -= NImax) < NImax) {
+      used = k < NI;
+      if (used) {
+        row = g[k];
+        col = erow[e];
+        v = Bv[(int64_t)e * NImax + k];
+      }
+    } else if ((k -= NImax) < NImax) {
+      used = k < NI;
+      if (used) {
+        row = g[k];
+        v = Ev[(int64_t)e * NImax + k];
+        to_rhs = true;
+      }
+    } else {
+      row = erow[e];
+      v = F[e];
+      to_rhs = true;
+    }
+    if (!used) continue;
+    const bool in_range = row >= 0 && row < n_rows && (to_rhs || (col >= 0 && col < n_rows));
+    if (in_range && to_rhs) {
+      atomicAdd(rhs + row, v);
+    } else {
+      const int64_t pos = in_range ? csr_find(row_ptr, col_idx, row, col) : -1;
+      if (pos >= 0) atomicAdd(vals + pos, v);
+      else if (missing) atomicAdd(missing, 1);
+    }
+  }
+}
+
+hipError_t launch_reconstruct(const mhm_batch* bt, const double* X, const int32_t* gdof, const int32_t* erow,
+                              const double* sol, int32_t n_rows, double* u, const int32_t* info, int grid,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_reconstruct, dim3(grid), dim3(NTHREADS), 0, st, to_dev(bt), X, gdof, erow, sol, n_rows, u,
+                     info);
+  return hipGetLastError();
+}
+
+hipError_t launch_skeleton_scatter(const mhm_batch* bt, const double* M, const double* E, const double* B,
+                                   const double* F, const int32_t* gdof, const int32_t* erow, const int32_t* row_ptr,
+                                   const int32_t* col_idx, int32_t n_rows, double* vals, double* rhs,
+                                   const int32_t* info, int32_t* missing, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_skeleton_scatter, dim3(grid), dim3(NTHREADS), 0, st, to_dev(bt), M, E, B, F, gdof, erow,
+                     row_ptr, col_idx, vals, rhs, info, n_rows, missing);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------- size-class binning
 // Element e goes to the first class c with s[e] <= s_hi[c] (an s outside
 // [1, MHM_S_LIMIT] to class 0, whose kernel reports the descriptor).  Class c's

@@ -100,3 +100,36 @@ def test_validate_rejects_malformed_batches(mutate, msg):
 def test_validate_accepts_configs():
     hb.validate(configs.make("C1"))
     hb.validate(configs.make("C2", n_elem=4))
+
+
+@pytest.mark.parametrize("N,l,l_max", [(2, 1, 1), (3, 0, 2), (4, 2, 4)])
+def test_skeleton_numbering_and_pattern(N, l, l_max):
+    """The host numbering gives the oracle's global DoFs, and the CSR pattern
+    is exactly the set of positions that a dense assembly of nonzero element
+    blocks touches, with sorted columns."""
+    from mhm_inputs.mesh import coarse_mesh
+    from oracle import skeleton as oskel
+    from paper_1703_10435_amd import skeleton as sk
+    mesh = coarse_mesh(N)
+    nt = mesh["elems"].shape[0]
+    gdof, erow, n_rows = sk.numbering(mesh["elem_face"], mesh["faces"].shape[0], l, l_max=l_max)
+    NI = 3 * (l + 1)
+    assert gdof.shape == (nt, 3 * (l_max + 1)) and np.all(gdof[:, NI:] == -1)
+    for t in range(nt):
+        np.testing.assert_array_equal(gdof[t, :NI], oskel.global_dofs(mesh, t, l))
+    rng = np.random.default_rng(N)
+    res = [dict(M=rng.uniform(1, 2, (NI, NI)), B=rng.uniform(1, 2, NI), E=rng.uniform(1, 2, NI), F=1.0)
+           for _ in range(nt)]
+    K, _ = oskel.assemble_global(mesh, res, np.arange(nt), l)
+    assert K.shape == (n_rows, n_rows)
+    rp, ci = sk.csr_pattern(gdof, erow, n_rows, np.full(nt, NI))
+    mask = np.zeros((n_rows, n_rows), dtype=bool)
+    for i in range(n_rows):
+        cols = ci[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(cols) > 0)
+        mask[i, cols] = True
+    # the block pattern holds the u_0 diagonal, which eq. (6) leaves zero
+    diag = np.zeros_like(mask)
+    diag[erow, erow] = True
+    np.testing.assert_array_equal(mask & ~diag, K != 0)
+    assert rp.dtype == np.int32 and ci.dtype == np.int32

@@ -1,0 +1,205 @@
+"""GPU tests of the two steps either side of the local solves: the scatter of
+the element blocks into the skeleton system eq. (6) and the reconstruction
+of u_{H,h}, eq. (4).  Each is compared with the FP64 oracle on the same
+seeded mesh; the whole chain (local solves, scatter, a host solve of the
+assembled system, reconstruction) is checked against the manufactured
+solution's second-order convergence."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from mhm_inputs import configs
+from mhm_inputs.fields import manufactured_solution, manufactured_source
+from mhm_inputs.mesh import coarse_mesh
+from oracle import local, skeleton as oskel
+from tests.parity_util import ensure_built, say
+from tests.test_parity_gpu import TOL
+
+pytestmark = pytest.mark.gpu
+
+
+def _ones(p):
+    return np.ones(p.shape[:-1])
+
+
+def _rough_k(p):
+    return np.exp(np.sin(7.0 * p[..., 0]) * np.cos(5.0 * p[..., 1]))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ensure_built()
+    from paper_1703_10435_amd import abi
+    c = abi.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_local(ctx, mesh, s, l, kfun, prec):
+    from paper_1703_10435_amd import engine
+    E = mesh["elems"].shape[0]
+    b = configs.build_batch(mesh, np.arange(E), np.full(E, s), np.full(E, l), kfun, manufactured_source)
+    res, out, db = engine.solve_batch(b, prec=prec, mode="fused", ctx=ctx)
+    return b, res, out, db
+
+
+def _dense(rp, ci, vals, n):
+    K = np.zeros((n, n))
+    for i in range(n):
+        K[i, ci[rp[i]:rp[i + 1]]] = vals[rp[i]:rp[i + 1]]
+    return K
+
+
+def _host_solve(K, rhs):
+    """Test-side solve of the assembled system (rank deficient when l >= s)."""
+    if np.linalg.cond(K) < 1e12:
+        return np.linalg.solve(K, rhs)
+    return np.linalg.lstsq(K, rhs, rcond=1e-12)[0]
+
+
+@pytest.mark.parametrize("N,s,l,prec", [(4, 8, 1, 0), (4, 6, 2, 1), (3, 5, 4, 0), (2, 3, 0, 0)])
+def test_scatter_matches_oracle_assembly(ctx, N, s, l, prec):
+    from paper_1703_10435_amd.skeleton import SkeletonSystem
+    mesh = coarse_mesh(N)
+    say(f"[gpu] scatter N={N} s={s} l={l} prec={prec}")
+    b, res, out, db = _gpu_local(ctx, mesh, s, l, _rough_k, prec)
+    sk = SkeletonSystem(mesh, l, l_max=db.desc.l_max)
+    vals, rhs, missing = sk.scatter(ctx, db, out)
+    ctx.sync()
+    assert int(missing.item()) == 0
+    K = _dense(sk.row_ptr_h, sk.col_idx_h, vals.cpu().numpy(), sk.n_rows)
+    ora = local.solve_batch(b)
+    Ko, ro = oskel.assemble_global(mesh, ora, np.arange(b["n_elem"]), l)
+    # every entry is a sum of at most two element values, each within TOL of
+    # the oracle relative to its element's block
+    scale = max(np.abs(Ko).max(), np.abs(ro).max())
+    tol = 2 * TOL[prec] * scale
+    assert np.abs(K - Ko).max() <= tol, np.abs(K - Ko).max() / scale
+    assert np.abs(rhs.cpu().numpy() - ro).max() <= tol
+    # every nonzero of the oracle's system lies in the pattern
+    mask = np.zeros_like(Ko, dtype=bool)
+    for i in range(sk.n_rows):
+        mask[i, sk.col_idx_h[sk.row_ptr_h[i]:sk.row_ptr_h[i + 1]]] = True
+    assert not np.any(Ko[~mask])
+
+
+def test_scatter_skips_failed_elements_and_reports_missing(ctx):
+    import torch
+    from paper_1703_10435_amd.skeleton import SkeletonSystem
+    mesh = coarse_mesh(2)
+    l = 1
+    b, res, out, db = _gpu_local(ctx, mesh, 4, l, _ones, 0)
+    sk = SkeletonSystem(mesh, l, l_max=db.desc.l_max)
+    bad = 3
+    info = out["info"].clone()
+    info[bad] = 7                                     # as a failed factorisation would report
+    o2 = dict(out, info=info)
+    say("[gpu] scatter with a failed element")
+    vals, rhs, missing = sk.scatter(ctx, db, o2)
+    ctx.sync()
+    assert int(missing.item()) == 0
+    keep = [e for e in range(b["n_elem"]) if e != bad]
+    Ko, ro = oskel.assemble_global(mesh, [res[e] for e in keep], keep, l)
+    K = _dense(sk.row_ptr_h, sk.col_idx_h, vals.cpu().numpy(), sk.n_rows)
+    assert np.abs(K - Ko).max() <= 1e-14 * np.abs(Ko).max()
+    assert np.abs(rhs.cpu().numpy() - ro).max() <= 1e-14 * np.abs(ro).max()
+    # drop the first entry of element 0's u_0 row (a B coupling entry, which
+    # only element 0 adds to): exactly one addition has no place
+    rp, ci = sk.row_ptr_h.copy(), sk.col_idx_h.copy()
+    row = int(sk.erow_h[0])
+    drop = rp[row]
+    ci2 = np.delete(ci, drop)
+    rp2 = rp.copy()
+    rp2[row + 1:] -= 1
+    sk.row_ptr = torch.as_tensor(rp2, dtype=torch.int32, device="cuda")
+    sk.col_idx = torch.as_tensor(ci2, dtype=torch.int32, device="cuda")
+    sk.nnz = int(rp2[-1])
+    say("[gpu] scatter with an entry missing from the pattern")
+    vals, rhs, missing = sk.scatter(ctx, db, out)
+    ctx.sync()
+    assert int(missing.item()) == 1
+
+
+@pytest.mark.parametrize("N,s,l,prec", [(4, 8, 1, 0), (4, 6, 2, 1), (3, 5, 4, 0)])
+def test_reconstruct_matches_oracle(ctx, N, s, l, prec):
+    import torch
+    from paper_1703_10435_amd.skeleton import SkeletonSystem
+    mesh = coarse_mesh(N)
+    say(f"[gpu] reconstruct N={N} s={s} l={l} prec={prec}")
+    b, res, out, db = _gpu_local(ctx, mesh, s, l, _rough_k, prec)
+    ora = local.solve_batch(b)
+    lam, u0, _, _ = oskel.reduce_and_solve(mesh, ora, np.arange(b["n_elem"]), l)
+    sol = np.concatenate([lam, u0])
+    sk = SkeletonSystem(mesh, l, l_max=db.desc.l_max)
+    u = sk.reconstruct(ctx, db, out, torch.as_tensor(sol, device="cuda"))
+    ctx.sync()
+    u = u.cpu().numpy()
+    want = oskel.reconstruct(mesh, ora, np.arange(b["n_elem"]), l, lam, u0)
+    scale = max(np.abs(w).max() for w in want)
+    # |X err| <= TOL |X|, times the multipliers' weight in the sum
+    wsum = max(np.abs(r["X"]).max() * (1.0 + np.abs(lam[oskel.global_dofs(mesh, e, l)]).sum())
+               for e, r in enumerate(ora))
+    for e in range(b["n_elem"]):
+        got = u[db.node_off[e]:db.node_off[e + 1]]
+        assert np.abs(got - want[e]).max() <= TOL[prec] * wsum + 1e-14 * scale, e
+
+
+def test_reconstruct_skips_failed_elements(ctx):
+    import torch
+    from paper_1703_10435_amd.skeleton import SkeletonSystem
+    mesh = coarse_mesh(2)
+    b, res, out, db = _gpu_local(ctx, mesh, 4, 1, _ones, 0)
+    sk = SkeletonSystem(mesh, 1, l_max=db.desc.l_max)
+    info = out["info"].clone()
+    info[2] = 5
+    sol = torch.ones(sk.n_rows, dtype=torch.float64, device="cuda")
+    u = torch.full((db.node_total,), -7.0, dtype=torch.float64, device="cuda")
+    say("[gpu] reconstruct with a failed element")
+    sk.reconstruct(ctx, db, dict(out, info=info), sol, u)
+    ctx.sync()
+    u = u.cpu().numpy()
+    assert np.all(u[db.node_off[2]:db.node_off[3]] == -7.0)
+    assert np.all(u[db.node_off[3]:db.node_off[4]] != -7.0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_chain_converges_at_second_order(ctx, prec):
+    """Local solves, scatter, host solve of eq. (6), reconstruction: the L2
+    error against the manufactured solution falls at rate 2 (K = 1, l = 1)."""
+    import torch
+    from paper_1703_10435_amd.skeleton import SkeletonSystem
+    errs = []
+    for N in (2, 4, 8):
+        mesh = coarse_mesh(N)
+        say(f"[gpu] chain N={N} prec={prec}")
+        b, res, out, db = _gpu_local(ctx, mesh, 4, 1, _ones, prec)
+        sk = SkeletonSystem(mesh, 1, l_max=db.desc.l_max)
+        vals, rhs, missing = sk.scatter(ctx, db, out)
+        ctx.sync()
+        assert int(missing.item()) == 0
+        K = _dense(sk.row_ptr_h, sk.col_idx_h, vals.cpu().numpy(), sk.n_rows)
+        sol = _host_solve(K, rhs.cpu().numpy())
+        u = sk.reconstruct(ctx, db, out, torch.as_tensor(sol, device="cuda"))
+        ctx.sync()
+        u = u.cpu().numpy()
+        nodal = [u[db.node_off[e]:db.node_off[e + 1]] for e in range(b["n_elem"])]
+        errs.append(oskel.l2_error(b, nodal, manufactured_solution))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    say(f"  errors {errs} rates {rates}")
+    assert np.all((rates > 1.8) & (rates < 2.3)), (errs, rates)
+
+
+def test_empty_batch_is_a_no_op(ctx):
+    import torch
+    from paper_1703_10435_amd.batch import DeviceBatch
+    from tests.test_parity_gpu import _random_batch
+    db = DeviceBatch(_random_batch(15, [], [], "empty"))
+    z = torch.zeros(1, dtype=torch.float64, device="cuda")
+    zi = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.skeleton_scatter(db, z, z, z, z, zi, zi, zi, zi, 1, z, z, zi, zi)
+    ctx.reconstruct(db, z, zi, zi, z, 1, z, zi)
+    ctx.sync()
