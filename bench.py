@@ -225,6 +225,120 @@ def _serve_leg(seconds, checks, rate=20000.0):
             "latency": "scheduled arrival to contribution on the host"}
 
 
+def _transient_leg(torch, ctx, batch, db, steps, checks, n_loads=4):
+    """Factor once, then time steps that reuse the stored factors with a new
+    source each step (only the load vectors are built and solved)."""
+    from paper_1703_10435_amd import abi, engine
+    E = batch["n_elem"]
+    rng = np.random.default_rng(5)
+    loads = [batch["f"] * (1.0 + 0.25 * k) + 0.1 * rng.standard_normal(batch["f"].shape) for k in range(n_loads)]
+    views = [engine.with_source(db, torch.as_tensor(f, device="cuda")) for f in loads]
+    leg = {"n_elem": E, "loads": f"{n_loads} seeded sources used in turn"}
+    for prec, tag in ((abi.MHM_FP64, "fp64"), (abi.MHM_FP32_IR, "fp32_ir")):
+        fs = engine.FactorStore(db, prec)
+        o = db.alloc_outputs(three_call=False)
+
+        def first():
+            fs.state.zero_()
+            engine.run_cached(ctx, views[0], fs, o, update_state=False)
+        leg[f"{tag}_factor_step_ms"] = _ms(torch, first, 3)
+        engine.run_cached(ctx, views[0], fs, o)          # stores the factors, marks them valid
+        torch.cuda.synchronize()
+        leg[f"{tag}_factors_held"] = int(fs.state[:E].sum().item())
+        k = [0]
+
+        def later():
+            k[0] = (k[0] + 1) % n_loads
+            engine.run_cached(ctx, views[k[0]], fs, o, update_state=False)
+        ms = _ms(torch, later, steps)
+        leg[f"{tag}_reuse_step_ms"] = ms
+        leg[f"{tag}_reuse_solves_per_s"] = E / (ms * 1e-3)
+        leg[f"{tag}_factor_store_mb"] = fs.nbytes / 2 ** 20
+
+        # source-only steps (coefficients constant in time): the source
+        # column of X, E and F on the stored factors
+        def src():
+            k[0] = (k[0] + 1) % n_loads
+            engine.source_step(ctx, views[k[0]], fs, o)
+        ms_s = _ms(torch, src, steps)
+        last = k[0]
+        leg[f"{tag}_source_step_ms"] = ms_s
+        leg[f"{tag}_source_steps_per_s"] = 1e3 / ms_s
+        leg[f"{tag}_source_solves_per_s"] = E / (ms_s * 1e-3)
+        leg[f"{tag}_source_step_vs_factoring"] = leg[f"{tag}_factor_step_ms"] / ms_s
+        # algorithmic bytes: the factor once, f (and kappa for the FP64
+        # residual of the refinement), the source column of X, E and F
+        nbytes = (fs.nbytes + batch["f"].size * 8 * (2 if prec == abi.MHM_FP32_IR else 1)
+                  + int(np.sum(db.n)) * 8 + E * (db.NImax + 1) * 8)
+        leg[f"{tag}_source_step_GBps"] = nbytes / (ms_s * 1e-3) / 1e9
+        leg[f"{tag}_source_step_frac_hbm"] = leg[f"{tag}_source_step_GBps"] / PEAK_HBM_GBS
+        info = o["info"].cpu().numpy()[:E]
+        leg[f"{tag}_bad"] = int(np.sum((info != 0) & (info != -1)))
+        leg[f"{tag}_source_fallbacks"] = int(np.sum(info == -1))
+        if prec == abi.MHM_FP32_IR:
+            leg["fp32_ir_source_steps_mean"] = float(o["ir_iters"].cpu().numpy()[:E][info == 0].mean())
+        res = db.unpack(o)
+        bl = dict(batch, f=loads[last])
+        for e in np.random.default_rng(13).choice(E, size=4, replace=False):
+            checks.append(("T", f"{tag}_max_rel_err_sampled", bl, int(e), 0, res[int(e)]))
+        leg[f"{tag}_speedup_vs_factoring"] = leg[f"{tag}_factor_step_ms"] / ms
+        del fs, o
+    leg["sample"] = "4 elements per precision against the FP64 oracle, for the last source-only step's source"
+    leg["bytes"] = "source step: factor store once + f (+ kappa for FP32 refinement) + X source column + E, F"
+    return leg
+
+
+def _skeleton_leg(torch, ctx, batch, db, out, steps):
+    """Scatter of the C2 blocks into the CSR skeleton system (eq. (6)) and the
+    reconstruction of u (eq. (4)); HBM-bound, priced by algorithmic bytes."""
+    import scipy.sparse as sp
+    from paper_1703_10435_amd.skeleton import SkeletonSystem
+    E = batch["n_elem"]
+    l = int(batch["l"][0])
+    sk = SkeletonSystem(batch["mesh"], l, l_max=db.desc.l_max)
+    NI, NImax = 3 * (l + 1), db.NImax
+    vals = torch.zeros(sk.nnz, dtype=torch.float64, device="cuda")
+    rhs = torch.zeros(sk.n_rows, dtype=torch.float64, device="cuda")
+    ms_s = _ms(torch, lambda: sk.scatter(ctx, db, out, vals, rhs, clear=False), steps)
+    vals.zero_()
+    rhs.zero_()
+    _, _, missing = sk.scatter(ctx, db, out, vals, rhs, clear=False)
+    sol = torch.as_tensor(np.random.default_rng(3).standard_normal(sk.n_rows), device="cuda")
+    u = torch.zeros(db.node_total, dtype=torch.float64, device="cuda")
+    ms_r = _ms(torch, lambda: sk.reconstruct(ctx, db, out, sol, u), steps)
+    torch.cuda.synchronize()
+    b_scatter = (E * (NImax * NImax + 3 * NImax + 1) * 8 + E * (NImax + 2) * 4
+                 + sk.nnz * (16 + 4) + (sk.n_rows + 1) * 4 + sk.n_rows * 16)
+    b_recon = db.rhs_total * 8 + E * (NImax + 2) * 4 + sk.n_rows * 8 + db.node_total * 8
+    # consistency of both with the same blocks, on the host
+    res = db.unpack(out)
+    x = np.random.default_rng(4).standard_normal(sk.n_rows)
+    y = np.zeros(sk.n_rows)
+    for e in range(E):
+        g, t = sk.gdof_h[e, :NI], sk.erow_h[e]
+        y[g] += res[e]["M"] @ x[g] + res[e]["B"] * x[t]
+        y[t] += res[e]["B"] @ x[g]
+    K = sp.csr_matrix((vals.cpu().numpy(), sk.col_idx_h, sk.row_ptr_h), shape=(sk.n_rows, sk.n_rows))
+    err_s = float(np.abs(K @ x - y).max() / np.abs(y).max())
+    uh = u.cpu().numpy()
+    sh = sol.cpu().numpy()
+    err_r = 0.0
+    for e in range(0, E, 97):
+        want = sh[sk.erow_h[e]] + res[e]["X"][:, :NI] @ sh[sk.gdof_h[e, :NI]] + res[e]["X"][:, NI]
+        got = uh[db.node_off[e]:db.node_off[e + 1]]
+        err_r = max(err_r, float(np.abs(got - want).max() / np.abs(want).max()))
+    gbs = lambda b, ms: b / (ms * 1e-3) / 1e9  # noqa: E731
+    return {"n_rows": sk.n_rows, "nnz": sk.nnz,
+            "scatter_ms": ms_s, "scatter_GBps": gbs(b_scatter, ms_s),
+            "scatter_frac_hbm": gbs(b_scatter, ms_s) / PEAK_HBM_GBS, "scatter_bytes": b_scatter,
+            "reconstruct_ms": ms_r, "reconstruct_GBps": gbs(b_recon, ms_r),
+            "reconstruct_frac_hbm": gbs(b_recon, ms_r) / PEAK_HBM_GBS, "reconstruct_bytes": b_recon,
+            "missing": int(missing.item()), "scatter_rel_err_vs_host_sum": err_s,
+            "reconstruct_rel_err_vs_host": err_r,
+            "bytes": "scatter: blocks, indices, CSR values and rhs read+written once, pattern read once; "
+                     "reconstruct: X, indices, solution read once, u written once"}
+
+
 def extra_legs(torch, ctx, db, out, args, checks):
     from paper_1703_10435_amd import abi, engine
     E = db.n_elem
@@ -244,6 +358,10 @@ def extra_legs(torch, ctx, db, out, args, checks):
         ex["C4"] = _batched_leg(torch, ctx, "C4", 2, checks)
     if "C5" in legs:
         ex["C5"] = _serve_leg(args.serve_seconds, checks)
+    if "T" in legs:
+        ex["T"] = _transient_leg(torch, ctx, args.batch, db, args.steps, checks)
+    if "SKEL" in legs:
+        ex["SKEL"] = _skeleton_leg(torch, ctx, args.batch, db, out, args.steps)
     return ex
 
 
@@ -277,7 +395,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the C2 FP32+IR, C3, C4 (batching) and C5 (serving) legs")
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="length of the C5 open-loop stream")
-    ap.add_argument("--legs", default="C2,C3,C4,C5", help="which extra legs to run (comma list)")
+    ap.add_argument("--legs", default="C2,C3,C4,C5,T,SKEL",
+                    help="which extra legs to run (comma list): C2 C3 C4 C5, T (time steps reusing factors), "
+                         "SKEL (skeleton scatter and reconstruction)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -302,6 +422,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     batch = configs.make("C2")
+    args.batch = batch
     db = DeviceBatch(batch)
     out = db.alloc_outputs(three_call=True)
     ctx = abi.Context(0)

@@ -58,6 +58,7 @@
  *          sign/flip flags out of range, a non-positive area); nothing of
  *          the element is written
  *     -3   the element is larger than the launched kernel supports
+ *     -4   (mhm_local_source_step) no stored factor for the element
  */
 #ifndef MHM_H
 #define MHM_H
@@ -229,6 +230,34 @@ mhm_status mhm_local_batch_run_cached(mhm_ctx ctx, const mhm_batch* batch, mhm_p
                                       const int8_t* factor_state,
                                       double* X, double* M, double* E, double* B, double* F,
                                       int32_t* info, int32_t* ir_iters, int max_iters);
+
+/* Time steps on stored factors (Section 3: with coefficients that do not
+ * change in time, the local matrix is assembled and factored only in the
+ * first step of a time-marching scheme).  The multiplier load vectors do not
+ * change either, so after a first mhm_local_batch_run_cached call (state 0,
+ * which stores the factors and computes every column of X, M, E, B, F) a
+ * step with a new source f only recomputes the source column: btilde_f of
+ * eq. (8), one forward and one backward solve with the stored factor, the
+ * zero-mean projection, E = R^T eta^f and F = (1, f)_K of eq. (6).
+ *   batch     the same elements (s, l, geometry, kappa, offsets) as the call
+ *             that stored the factors and produced X, M and B; f is the new
+ *             source.
+ *   factors, factor_off, factor_state  as for mhm_local_batch_run_cached
+ *             and the same prec; only elements with factor_state[e] == 1 are
+ *             solved, the others report info -4 and are left untouched.
+ *   X         column N_I (the source) of each element is rewritten; the
+ *             multiplier columns are read by nobody and left as they are.
+ *   E, F      rewritten.  M and B are not written, except with MHM_FP32_IR
+ *             for elements whose refinement does not converge (info -1):
+ *             those are recomputed in full in FP64 (X, M, E, B, F), so with
+ *             MHM_FP32_IR M and B must be the arrays of the first call.
+ *   ir_iters  refinement steps (FP32_IR; may be NULL).
+ * info[e] as mhm_local_batch_run, plus -4: no stored factor for the element.
+ * Requires s <= 48. */
+mhm_status mhm_local_source_step(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec, const void* factors,
+                                 const int64_t* factor_off, const int8_t* factor_state, double* X, double* M,
+                                 double* E, double* B, double* F, int32_t* info, int32_t* ir_iters,
+                                 int max_iters);
 
 /* Batching: choose, per size class present in the batch, the kernel family
  * and panel width ("tile shape": register-resident tiles, LDS tiles,

@@ -23,6 +23,7 @@ EXPORTS = (
     "mhm_local_assemble", "mhm_local_factor_solve", "mhm_skeleton_contrib", "mhm_local_batch_run",
     "mhm_autotune", "mhm_tune_report", "mhm_graph_create", "mhm_graph_launch", "mhm_graph_destroy",
     "mhm_factor_bytes", "mhm_local_batch_run_cached", "mhm_skeleton_scatter", "mhm_reconstruct",
+    "mhm_local_source_step",
 )
 
 
@@ -78,6 +79,7 @@ def load(path: str = LIB_PATH):
         "mhm_local_batch_run_cached": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]),
         "mhm_skeleton_scatter": (i32, [vp, bp] + [vp] * 8 + [i32] + [vp] * 4),
         "mhm_reconstruct": (i32, [vp, bp, vp, vp, vp, vp, i32, vp, vp]),
+        "mhm_local_source_step": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -163,6 +165,12 @@ class Context:
     def local_batch_run_cached(self, batch, prec, factors, factor_off, factor_state, X, M, E, B, F, info,
                               ir_iters=None, max_iters: int = 10):
         self._check(self.lib.mhm_local_batch_run_cached(
+            self.h, ctypes.byref(batch.desc), prec, _ptr(factors), _ptr(factor_off), _ptr(factor_state), _ptr(X),
+            _ptr(M), _ptr(E), _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters), max_iters))
+
+    def local_source_step(self, batch, prec, factors, factor_off, factor_state, X, M, E, B, F, info,
+                          ir_iters=None, max_iters: int = 10):
+        self._check(self.lib.mhm_local_source_step(
             self.h, ctypes.byref(batch.desc), prec, _ptr(factors), _ptr(factor_off), _ptr(factor_state), _ptr(X),
             _ptr(M), _ptr(E), _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters), max_iters))
 

@@ -325,10 +325,13 @@ mhm::LocalArgs local_args(const Plan& p, const RunIO& io, void* ws, const int32_
 // One class: the main pass, then (FP32) the FP64 pass of the elements whose
 // refinement did not converge.
 mhm_status enqueue_class(mhm_ctx c, const ClassRun& r, const mhm_batch* b, const RunIO& io, char* ws,
-                         const int32_t* elist, const int32_t* ecount, hipStream_t st) {
-  mhm::LocalArgs a = local_args(r.main, io, ws + r.ws_off, elist, ecount);
-  hipError_t e = launch_plan(r.main, b, a, st);
-  if (e != hipSuccess) return hip_fail(c, e, "local kernel launch");
+                         const int32_t* elist, const int32_t* ecount, hipStream_t st, bool fallback_only = false) {
+  hipError_t e = hipSuccess;
+  if (!fallback_only) {
+    mhm::LocalArgs a = local_args(r.main, io, ws + r.ws_off, elist, ecount);
+    e = launch_plan(r.main, b, a, st);
+    if (e != hipSuccess) return hip_fail(c, e, "local kernel launch");
+  }
   if (r.main.fp32) {
     RunIO f = io;
     f.Ahat = nullptr;
@@ -356,7 +359,8 @@ mhm::BinClasses bin_classes() {
 // Enqueue a whole run on stream `st` (also under stream capture): binning,
 // then the classes, the largest on `st` and the others forked onto the
 // context's class streams and joined back.
-mhm_status enqueue_run(mhm_ctx c, const RunPlan& rp, const mhm_batch* b, const RunIO& io, void* ws_v, hipStream_t st) {
+mhm_status enqueue_run(mhm_ctx c, const RunPlan& rp, const mhm_batch* b, const RunIO& io, void* ws_v, hipStream_t st,
+                       bool fallback_only = false) {
   char* ws = static_cast<char*>(ws_v);
   int32_t* lists = reinterpret_cast<int32_t*>(ws);
   int32_t* counts = lists + (size_t)kNumClasses * b->n_elem;
@@ -379,7 +383,7 @@ mhm_status enqueue_run(mhm_ctx c, const RunPlan& rp, const mhm_batch* b, const R
     const ClassRun& r = rp.run[i];
     const int32_t* el = rp.listed ? lists + (size_t)r.cls * b->n_elem : nullptr;
     const int32_t* ec = rp.listed ? counts + r.cls : nullptr;
-    mhm_status s1 = enqueue_class(c, r, b, io, ws, el, ec, i == 0 ? st : c->aux[i]);
+    mhm_status s1 = enqueue_class(c, r, b, io, ws, el, ec, i == 0 ? st : c->aux[i], fallback_only);
     if (s1 != MHM_OK) return s1;
   }
   if (fork) {
@@ -661,6 +665,46 @@ mhm_status mhm_local_batch_run_cached(mhm_ctx c, const mhm_batch* b, mhm_prec pr
   io.fac_off = factor_off;
   io.fac_state = factor_state;
   return run_local(c, b, prec, true, io);
+}
+
+mhm_status mhm_local_source_step(mhm_ctx c, const mhm_batch* b, mhm_prec prec, const void* factors,
+                                 const int64_t* factor_off, const int8_t* factor_state, double* X, double* M,
+                                 double* E, double* B, double* F, int32_t* info, int32_t* ir_iters, int max_iters) {
+  mhm_status st = check_batch(c, b, false, false);
+  if (st != MHM_OK || b->n_elem == 0) return st;
+  if (prec != MHM_FP64 && prec != MHM_FP32_IR) return fail(c, MHM_E_ARG, "unknown precision");
+  const bool fp32 = prec == MHM_FP32_IR;
+  if (!factors || !factor_off || !factor_state || !X || !E || !F || !info)
+    return fail(c, MHM_E_ARG, "factors, factor_off, factor_state, X, E, F and info are required");
+  if (fp32 && (!M || !B)) return fail(c, MHM_E_ARG, "M and B are required with MHM_FP32_IR (FP64 fallback)");
+  if (b->s_max > 48) return fail(c, MHM_E_UNSUPPORTED, "stored factors need s <= 48");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  mhm::SourceArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.fac = factors;
+  a.fac_off = factor_off;
+  a.fac_state = factor_state;
+  a.X = X;
+  a.E = E;
+  a.F = F;
+  a.info = info;
+  a.ir_iters = ir_iters;
+  a.max_iters = std::max(0, max_iters);
+  a.ir_tol = kIrTol;
+  a.n_cap = n_of(b->s_max);
+  const size_t lds = mhm::source_step_lds(fp32, a.n_cap, a.wave_words);
+  const int waves = mhm::source_step_waves();
+  const int grid = (int)std::min<int64_t>(((int64_t)b->n_elem + waves - 1) / waves, kGridCap);
+  e = mhm::launch_source_step(fp32, b, a, lds, grid, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "k_source_step launch");
+  if (!fp32) return MHM_OK;
+  // elements whose refinement did not converge: full FP64 recomputation
+  RunIO io = fused_io(X, M, E, B, F, info, ir_iters, max_iters);
+  const RunPlan rp = make_run_plan(c, b, true, true, nullptr, false);
+  st = ensure_ws(c, rp.ws_total);
+  if (st != MHM_OK) return st;
+  return enqueue_run(c, rp, b, io, c->ws, c->stream, true);
 }
 
 mhm_status mhm_autotune(mhm_ctx c, const mhm_batch* b, mhm_prec prec, double* X, double* M, double* E, double* B,

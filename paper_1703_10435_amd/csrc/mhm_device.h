@@ -17,6 +17,7 @@ constexpr int INFO_OK = 0;
 constexpr int INFO_IR_FALLBACK = -1;
 constexpr int INFO_BAD_DESC = -2;
 constexpr int INFO_TOO_LARGE = -3;
+constexpr int INFO_NO_FACTOR = -4;
 
 // Batch descriptor as passed to kernels (by value).
 struct BatchDev {

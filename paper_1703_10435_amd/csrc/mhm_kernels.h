@@ -37,6 +37,22 @@ struct LocalArgs {
   const int8_t* fac_state;
 };
 
+// Time step on stored factors: the source column only.
+struct SourceArgs {
+  const void* fac;          // factor store (tiles as written by the left-looking kernel)
+  const int64_t* fac_off;   // byte offset of element e's factor
+  const int8_t* fac_state;  // 1 = a valid factor is stored
+  double* X;                // only column N_I (the source) of each element is written
+  double* E;
+  double* F;
+  int32_t* info;
+  int32_t* ir_iters;        // may be null
+  int max_iters;
+  double ir_tol;
+  int n_cap;                // largest n of the launch
+  int wave_words;           // LDS doubles per wave
+};
+
 // Element k of a launch (identity, or through the element list of a size class).
 __device__ __forceinline__ int launch_count(const LocalArgs& a, int n_elem) { return a.ecount ? *a.ecount : n_elem; }
 __device__ __forceinline__ int launch_elem(const LocalArgs& a, int k) { return a.elist ? a.elist[k] : k; }
@@ -50,6 +66,11 @@ struct BinClasses {
   int s_hi[BIN_MAX_CLASSES];
 };
 hipError_t launch_bin(const mhm_batch* bt, const BinClasses& cls, int32_t* elist, int32_t* counts, hipStream_t st);
+
+size_t source_step_lds(bool fp32, int n_cap, int& wave_words);
+int source_step_waves();
+hipError_t launch_source_step(bool fp32, const mhm_batch* bt, const SourceArgs& a, size_t lds, int grid,
+                              hipStream_t st);
 
 hipError_t launch_reconstruct(const mhm_batch* bt, const double* X, const int32_t* gdof, const int32_t* erow,
                               const double* sol, int32_t n_rows, double* u, const int32_t* info, int grid,

@@ -74,3 +74,62 @@ def solve_batch(batch: dict, prec: int = abi.MHM_FP64, mode: str = "fused", ctx:
     out = run(ctx, db, prec, max_iters=max_iters)
     ctx.sync()
     return db.unpack(out), out, db
+
+
+class FactorStore:
+    """Device store of one factor per element (mhm_local_batch_run_cached):
+    offsets 256-byte aligned, state 0 until a call has factored the element."""
+
+    def __init__(self, db: DeviceBatch, prec: int, device="cuda"):
+        import numpy as np
+        import torch
+        sizes = np.array([abi.factor_bytes(int(s), prec) for s in db.s], dtype=np.int64)
+        sizes = (sizes + 255) // 256 * 256
+        off = np.zeros(len(sizes) + 1, dtype=np.int64)
+        np.cumsum(sizes, out=off[1:])
+        self.prec = prec
+        self.nbytes = int(off[-1])
+        self.store = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+        self.off = torch.as_tensor(off[:-1], dtype=torch.int64, device=device)
+        self.state = torch.zeros(max(len(sizes), 1), dtype=torch.int8, device=device)
+
+    def mark_valid(self, info):
+        """Elements whose call reported info == 0 keep their factor."""
+        import torch
+        n = info.numel()
+        self.state[:n] = torch.where(info == 0, 1, 0).to(torch.int8)
+
+
+def with_source(db: DeviceBatch, f) -> DeviceBatch:
+    """A view of the batch with the per-sub-triangle source f replaced (a
+    new load for the same elements, e.g. the next time step)."""
+    import copy
+    import ctypes
+    v = copy.copy(db)
+    v.desc = abi.mhm_batch.from_buffer_copy(db.desc)
+    v.desc.f = ctypes.c_void_p(f.data_ptr()).value
+    v._f_ref = f
+    return v
+
+
+def run_cached(ctx: abi.Context, db: DeviceBatch, fs: FactorStore, out: dict | None = None,
+               max_iters: int = 10, update_state: bool = True) -> dict:
+    """mhm_local_batch_run_cached: factor the elements whose state is 0,
+    reuse the stored factor of the others; afterwards (update_state) every
+    element with info == 0 is marked as holding its factor."""
+    if out is None:
+        out = db.alloc_outputs(three_call=False)
+    ctx.local_batch_run_cached(db, fs.prec, fs.store, fs.off, fs.state, out["X"], out["M"], out["E"], out["B"],
+                               out["F"], out["info"], out["ir_iters"], max_iters)
+    if update_state:
+        fs.mark_valid(out["info"][:db.n_elem])
+    return out
+
+
+def source_step(ctx: abi.Context, db: DeviceBatch, fs: FactorStore, out: dict, max_iters: int = 10) -> dict:
+    """mhm_local_source_step: a time step with a new source on the stored
+    factors; rewrites the source column of X, E and F in ``out`` (the
+    outputs of the call that stored the factors)."""
+    ctx.local_source_step(db, fs.prec, fs.store, fs.off, fs.state, out["X"], out["M"], out["E"], out["B"],
+                          out["F"], out["info"], out["ir_iters"], max_iters)
+    return out
