@@ -78,22 +78,26 @@ __device__ __forceinline__ void sweep1(const T* __restrict__ Lb, T* y, int nt, i
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = BACK ? p[(4 * k4 + k) * TST + u] : p[u * TST + 4 * k4 + k];
   };
+  // Fetch cursor: runs D tiles ahead and stops on the last tile (the ring
+  // then re-reads it from cache), so that every step issues its loads
+  // unconditionally and the memory counters wait exactly D - 1 tiles back.
   T buf[D][4];
-  int fi = BACK ? nt - 1 : 0, fj = BACK ? nt - 1 : 0;   // fetch cursor
-#pragma unroll
-  for (int q = 0; q < D; ++q) {
-    if (q < ntile) {
-      load(buf[q], fi, fj);
+  int fi = BACK ? nt - 1 : 0, fj = BACK ? nt - 1 : 0, fleft = ntile - 1;
+  auto fetch = [&](T (&v)[4]) {
+    load(v, fi, fj);
+    if (fleft > 0) {
       advance(fi, fj);
+      --fleft;
     }
-  }
+  };
+#pragma unroll
+  for (int q = 0; q < D; ++q) fetch(buf[q]);
   int I = BACK ? nt - 1 : 0, J = BACK ? nt - 1 : 0;   // arithmetic cursor
   T acc = T(0);
   for (int t0 = 0; t0 < ntile; t0 += D) {
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-      const int t = t0 + q;
-      if (t < ntile) {
+      if (t0 + q < ntile) {
         if (I != J) {
           // forward: sum_c L_IJ[u][c] y_J[c];  backward: sum_r L_JI[r][u] y_J[r]
           const T* yj = y + 16 * J + 4 * k4;
@@ -112,17 +116,14 @@ __device__ __forceinline__ void sweep1(const T* __restrict__ Lb, T* y, int nt, i
           acc = T(0);
         }
         advance(I, J);
-        if (t + D < ntile) {
-          load(buf[q], fi, fj);
-          advance(fi, fj);
-        }
       }
+      fetch(buf[q]);
     }
   }
 }
 
 template <typename T>
-__device__ __noinline__ void sweep_pair(const T* Lb, T* y, int nt, int lane) {
+__device__ __forceinline__ void sweep_pair(const T* Lb, T* y, int nt, int lane) {
   constexpr int D = sizeof(T) == 8 ? 8 : 12;
   sweep1<T, false, D>(Lb, y, nt, lane);
   wave_sync();
