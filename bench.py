@@ -299,13 +299,20 @@ def _skeleton_leg(torch, ctx, batch, db, out, steps):
     NI, NImax = 3 * (l + 1), db.NImax
     vals = torch.zeros(sk.nnz, dtype=torch.float64, device="cuda")
     rhs = torch.zeros(sk.n_rows, dtype=torch.float64, device="cuda")
-    ms_s = _ms(torch, lambda: sk.scatter(ctx, db, out, vals, rhs, clear=False), steps)
+    missing = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def scatter():   # the library call alone (buffers allocated beforehand)
+        ctx.skeleton_scatter(db, out["M"], out["E"], out["B"], out["F"], sk.gdof, sk.erow, sk.row_ptr,
+                             sk.col_idx, sk.n_rows, vals, rhs, out["info"], missing)
+    ms_s = _ms(torch, scatter, steps)
     vals.zero_()
     rhs.zero_()
-    _, _, missing = sk.scatter(ctx, db, out, vals, rhs, clear=False)
+    missing.zero_()
+    scatter()
     sol = torch.as_tensor(np.random.default_rng(3).standard_normal(sk.n_rows), device="cuda")
     u = torch.zeros(db.node_total, dtype=torch.float64, device="cuda")
-    ms_r = _ms(torch, lambda: sk.reconstruct(ctx, db, out, sol, u), steps)
+    ms_r = _ms(torch, lambda: ctx.reconstruct(db, out["X"], sk.gdof, sk.erow, sol, sk.n_rows, u, out["info"]),
+               steps)
     torch.cuda.synchronize()
     b_scatter = (E * (NImax * NImax + 3 * NImax + 1) * 8 + E * (NImax + 2) * 4
                  + sk.nnz * (16 + 4) + (sk.n_rows + 1) * 4 + sk.n_rows * 16)
