@@ -128,45 +128,69 @@ def face_length(vert6, e):
     return float(np.hypot(*(b - a)))
 
 
-def _legendre_in_tau(q: int, flip: int) -> Polynomial:
-    """P_q(t) as a polynomial in the local face parameter tau in [0, 1];
-    t = -1 at the lower global vertex id (t = 2 tau - 1, or 1 - 2 tau when
-    the local direction runs high -> low)."""
+def _legendre_in_tau(q: int, flip: int, m: int = 1, seg: int = 0) -> Polynomial:
+    """P_q(t) of segment `seg` of an m-partition of the face, as a polynomial
+    in the local face parameter tau in [0, 1].  Segments and t run along the
+    global orientation (from the lower global vertex id): with the global
+    parameter g = tau (or 1 - tau when the local direction runs high ->
+    low), segment seg is g in [seg/m, (seg+1)/m] and t = 2 (m g - seg) - 1."""
     pq = Polynomial(npleg.leg2poly([0] * q + [1]))
-    t_of_tau = Polynomial([1.0, -2.0]) if flip else Polynomial([-1.0, 2.0])
-    return pq(t_of_tau)
+    g_of_tau = Polynomial([1.0, -1.0]) if flip else Polynomial([0.0, 1.0])
+    return pq(2.0 * (m * g_of_tau - seg) - 1.0)
 
 
-def face_loads(vert6, s, l, sigma, flip):
-    """R[:, e(l+1)+q] = -sigma_e * integral over F_e of psi_q phi_j ds (eq. (9)
-    right-hand side), integrated exactly on each of the s segments."""
+def _segment_tau(flip: int, m: int, seg: int):
+    """The tau interval of global segment `seg`."""
+    g0, g1 = seg / m, (seg + 1) / m
+    return (1.0 - g1, 1.0 - g0) if flip else (g0, g1)
+
+
+def face_dof(e: int, seg: int, q: int, l: int, m: int = 1) -> int:
+    """Local index of face DoF (segment seg in the global orientation,
+    degree q) of local face e: e m(l+1) + seg (l+1) + q."""
+    return (e * m + seg) * (l + 1) + q
+
+
+def face_loads(vert6, s, l, sigma, flip, m: int = 1):
+    """R[:, face_dof(e, seg, q)] = -sigma_e * integral over F_e of psi phi_j ds
+    (eq. (9) right-hand side) for the discontinuous face space of Section 2
+    with m segments per face (m must divide s, so that every sub-edge lies
+    in one segment), integrated exactly on each of the s sub-edges."""
+    if s % m:
+        raise ValueError("m must divide s")
     n = (s + 1) * (s + 2) // 2
-    NI = 3 * (l + 1)
+    NI = 3 * m * (l + 1)
     R = np.zeros((n, NI))
     for e in range(3):
         L = face_length(vert6, e)
         nodes = face_nodes(e, s)
-        for q in range(l + 1):
-            P = _legendre_in_tau(q, int(flip[e]))
-            for k in range(s):
-                t0, t1 = k / s, (k + 1) / s
-                left = Polynomial([t1, -1.0]) * s      # hat of node k on [t0, t1]
-                right = Polynomial([-t0, 1.0]) * s     # hat of node k+1
-                for node, hat in ((nodes[k], left), (nodes[k + 1], right)):
-                    anti = (P * hat).integ()
-                    R[node, e * (l + 1) + q] += -float(sigma[e]) * L * (anti(t1) - anti(t0))
+        for seg in range(m):
+            lo, hi = _segment_tau(int(flip[e]), m, seg)
+            for q in range(l + 1):
+                P = _legendre_in_tau(q, int(flip[e]), m, seg)
+                for k in range(s):
+                    t0, t1 = k / s, (k + 1) / s
+                    if t0 < lo - 1e-12 or t1 > hi + 1e-12:
+                        continue                       # sub-edge outside the segment
+                    left = Polynomial([t1, -1.0]) * s      # hat of node k on [t0, t1]
+                    right = Polynomial([-t0, 1.0]) * s     # hat of node k+1
+                    for node, hat in ((nodes[k], left), (nodes[k + 1], right)):
+                        anti = (P * hat).integ()
+                        R[node, face_dof(e, seg, q, l, m)] += -float(sigma[e]) * L * (anti(t1) - anti(t0))
     return R
 
 
-def face_moments(vert6, l, sigma, flip):
+def face_moments(vert6, l, sigma, flip, m: int = 1):
     """B_j = (sigma psi_j, 1)_{dK}: integral of the signed face polynomial."""
-    NI = 3 * (l + 1)
+    NI = 3 * m * (l + 1)
     Bv = np.zeros(NI)
     for e in range(3):
         L = face_length(vert6, e)
-        for q in range(l + 1):
-            anti = _legendre_in_tau(q, int(flip[e])).integ()
-            Bv[e * (l + 1) + q] = float(sigma[e]) * L * (anti(1.0) - anti(0.0))
+        for seg in range(m):
+            lo, hi = _segment_tau(int(flip[e]), m, seg)
+            for q in range(l + 1):
+                anti = _legendre_in_tau(q, int(flip[e]), m, seg).integ()
+                Bv[face_dof(e, seg, q, l, m)] = float(sigma[e]) * L * (anti(hi) - anti(lo))
     return Bv
 
 
@@ -185,20 +209,21 @@ def solve_zero_mean(A, c, B):
     return sol[:n], sol[n]
 
 
-def local_problem(vert6, s, l, sigma, flip, kappa, f):
+def local_problem(vert6, s, l, sigma, flip, kappa, f, m: int = 1):
     """solveLocalProblem for one element plus its share of the skeleton
-    system.  Returns a dict with A, c, R, b, X (n x (N_I+1), source last),
-    M, E, B, F and the element area."""
+    system (face space: m segments per face, degree l on each).  Returns a
+    dict with A, c, R, b, X (n x (N_I+1), source last), M, E, B, F and the
+    element area."""
     vert6 = np.asarray(vert6, dtype=np.float64)
     A = stiffness(vert6, s, kappa)
     c = mean_vector(vert6, s)
-    R = face_loads(vert6, s, l, sigma, flip)
+    R = face_loads(vert6, s, l, sigma, flip, m)
     b = source_load(vert6, s, f)
     X, mu = solve_zero_mean(A, c, np.column_stack([R, b]))
     NI = R.shape[1]
     M = -R.T @ X[:, :NI]
     E = R.T @ X[:, NI]
-    Bv = face_moments(vert6, l, sigma, flip)
+    Bv = face_moments(vert6, l, sigma, flip, m)
     F = float(np.sum(np.asarray(f) * _p1_gradients(*submesh(vert6, s))[1]))
     area = 0.5 * abs((vert6[2] - vert6[0]) * (vert6[5] - vert6[1]) - (vert6[4] - vert6[0]) * (vert6[3] - vert6[1]))
     return dict(A=A, c=c, R=R, b=b, X=X, mu=mu, M=M, E=E, B=Bv, F=F, area=area)
@@ -206,8 +231,9 @@ def local_problem(vert6, s, l, sigma, flip, kappa, f):
 
 def element_inputs(batch: dict, e: int):
     o0, o1 = batch["tri_off"][e], batch["tri_off"][e + 1]
+    m = int(batch["m"][e]) if batch.get("m") is not None else 1
     return (batch["vert"][e], int(batch["s"][e]), int(batch["l"][e]), batch["sigma"][e],
-            batch["flip"][e], batch["kappa"][o0:o1], batch["f"][o0:o1])
+            batch["flip"][e], batch["kappa"][o0:o1], batch["f"][o0:o1], m)
 
 
 def solve_element(batch: dict, e: int) -> dict:

@@ -18,19 +18,22 @@ import numpy as np
 from .local import _p1_gradients, submesh
 
 
-def global_dofs(mesh: dict, t: int, l: int):
-    """Global multiplier index of each local face DoF a = e(l+1)+q of element t."""
-    return np.array([mesh["elem_face"][t, e] * (l + 1) + q for e in range(3) for q in range(l + 1)])
+def global_dofs(mesh: dict, t: int, l: int, m: int = 1):
+    """Global multiplier index of each local face DoF a = (e m + seg)(l+1) + q
+    of element t: face g's DoF (seg, q) is (g m + seg)(l+1) + q (segments in
+    the face's global orientation, as in the local numbering)."""
+    return np.array([(mesh["elem_face"][t, e] * m + seg) * (l + 1) + q
+                     for e in range(3) for seg in range(m) for q in range(l + 1)])
 
 
-def assemble_global(mesh: dict, results: list, elem_ids, l: int):
+def assemble_global(mesh: dict, results: list, elem_ids, l: int, m: int = 1):
     ne = mesh["faces"].shape[0]
     nt = mesh["elems"].shape[0]
-    nl = ne * (l + 1)
+    nl = ne * m * (l + 1)
     K = np.zeros((nl + nt, nl + nt))
     rhs = np.zeros(nl + nt)
     for t, r in zip(elem_ids, results):
-        g = global_dofs(mesh, int(t), l)
+        g = global_dofs(mesh, int(t), l, m)
         K[np.ix_(g, g)] += r["M"]
         K[nl + t, g] += r["B"]
         K[g, nl + t] += r["B"]
@@ -39,9 +42,9 @@ def assemble_global(mesh: dict, results: list, elem_ids, l: int):
     return K, rhs
 
 
-def reduce_and_solve(mesh: dict, results: list, elem_ids, l: int):
-    K, rhs = assemble_global(mesh, results, elem_ids, l)
-    nl = mesh["faces"].shape[0] * (l + 1)
+def reduce_and_solve(mesh: dict, results: list, elem_ids, l: int, m: int = 1):
+    K, rhs = assemble_global(mesh, results, elem_ids, l, m)
+    nl = mesh["faces"].shape[0] * m * (l + 1)
     try:
         cond = np.linalg.cond(K)
     except np.linalg.LinAlgError:
@@ -53,12 +56,12 @@ def reduce_and_solve(mesh: dict, results: list, elem_ids, l: int):
     return sol[:nl], sol[nl:], K, rhs
 
 
-def reconstruct(mesh: dict, results: list, elem_ids, l: int, lam, u0):
+def reconstruct(mesh: dict, results: list, elem_ids, l: int, lam, u0, m: int = 1):
     """Nodal values of u_{H,h} on each element's sub-mesh (list of arrays)."""
     out = []
-    NI = 3 * (l + 1)
+    NI = 3 * m * (l + 1)
     for t, r in zip(elem_ids, results):
-        g = global_dofs(mesh, int(t), l)
+        g = global_dofs(mesh, int(t), l, m)
         X = r["X"]
         out.append(u0[t] + X[:, :NI] @ lam[g] + X[:, NI])
     return out

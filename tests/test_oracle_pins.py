@@ -172,6 +172,73 @@ def test_face_loads_against_gauss_quadrature_moments(s, l):
                 assert got == pytest.approx(want, abs=1e-13)
 
 
+@pytest.mark.parametrize("s,l,m", [(4, 0, 2), (6, 1, 2), (8, 0, 4), (6, 1, 3), (5, 0, 5)])
+def test_segmented_face_loads_against_gauss_quadrature(s, l, m):
+    """m segments per face: sum_j R[j,a] g(x_j) = -sigma int_{segment} P_q(t) g ds
+    for every linear g, t running over [-1, 1] on the segment in the global
+    face orientation; 10-point Gauss rule per segment, points placed from
+    the coordinates (this pins segment placement, order, orientation and
+    sign independently of the oracle's polynomial algebra)."""
+    rng = np.random.default_rng(40 + s + m)
+    v, s, l, sg, fl, kap, f = _rand_element(rng, s, l)
+    R = local.face_loads(v, s, l, sg, fl, m)
+    Bv = local.face_moments(v, l, sg, fl, m)
+    assert R.shape[1] == 3 * m * (l + 1)
+    nodes, _ = local.submesh(v, s)
+    gx, gw = np.polynomial.legendre.leggauss(10)
+    for a_vec in ([1.0, 0.0], [0.0, 1.0], [0.3, -0.7]):
+        g = nodes @ np.array(a_vec) + 0.25
+        for e in range(3):
+            p_start = v[2 * ((e + 1) % 3): 2 * ((e + 1) % 3) + 2]
+            p_end = v[2 * ((e + 2) % 3): 2 * ((e + 2) % 3) + 2]
+            L = np.hypot(*(p_end - p_start))
+            lo, hi = (p_end, p_start) if fl[e] else (p_start, p_end)   # global orientation
+            for seg in range(m):
+                a0 = lo + (hi - lo) * seg / m
+                a1 = lo + (hi - lo) * (seg + 1) / m
+                pts = a0[None, :] + 0.5 * (gx[:, None] + 1.0) * (a1 - a0)[None, :]
+                gval = pts @ np.array(a_vec) + 0.25
+                for q in range(l + 1):
+                    Pq = np.polynomial.legendre.legval(gx, [0] * q + [1])
+                    a = (e * m + seg) * (l + 1) + q
+                    want = -sg[e] * 0.5 * (L / m) * np.sum(gw * Pq * gval)
+                    assert R[:, a] @ g == pytest.approx(want, abs=1e-13)
+                    wantB = sg[e] * 0.5 * (L / m) * np.sum(gw * Pq)
+                    assert Bv[a] == pytest.approx(wantB, abs=1e-13)
+
+
+@pytest.mark.parametrize("s,l,m", [(4, 1, 2), (6, 0, 3), (8, 1, 2)])
+def test_whole_face_space_is_inside_the_segmented_one(s, l, m):
+    """Lambda^{1,l} lies inside Lambda^{m,l}: P_q on the whole face is a
+    polynomial of degree q on each segment, so R^(1) = R^(m) T with T given
+    by Legendre re-expansion (computed here from the polynomials alone, not
+    by fitting), and then X^(1)_I = X^(m)_I T and M^(1) = T^T M^(m) T."""
+    from numpy.polynomial import legendre as L_
+    rng = np.random.default_rng(50 + s)
+    v, s, l, sg, fl, kap, f = _rand_element(rng, s, l)
+    r1 = local.local_problem(v, s, l, sg, fl, kap, f, 1)
+    rm = local.local_problem(v, s, l, sg, fl, kap, f, m)
+    N1, Nm = 3 * (l + 1), 3 * m * (l + 1)
+    T = np.zeros((Nm, N1))
+    for e in range(3):
+        for q in range(l + 1):
+            for seg in range(m):
+                # P_q(T) with T = (2 seg + 1 + t) / m - 1 on segment seg, in Legendre P_k(t)
+                poly = L_.leg2poly([0] * q + [1])                  # power coefficients in T
+                comp = np.polynomial.Polynomial(poly)(np.polynomial.Polynomial([(2 * seg + 1) / m - 1.0, 1.0 / m]))
+                coef = L_.poly2leg(comp.coef)
+                for k, ck in enumerate(coef):
+                    if abs(ck) > 0:
+                        T[(e * m + seg) * (l + 1) + k, e * (l + 1) + q] = ck
+    np.testing.assert_allclose(r1["R"], rm["R"] @ T, atol=1e-14, rtol=0)
+    scale = np.abs(r1["X"]).max()
+    np.testing.assert_allclose(r1["X"][:, :N1], rm["X"][:, :Nm] @ T, atol=1e-12 * scale, rtol=0)
+    np.testing.assert_allclose(r1["X"][:, N1], rm["X"][:, Nm], atol=1e-12 * scale, rtol=0)
+    np.testing.assert_allclose(r1["M"], T.T @ rm["M"] @ T, atol=1e-12 * np.abs(r1["M"]).max(), rtol=0)
+    np.testing.assert_allclose(r1["B"], T.T @ rm["B"], atol=1e-14, rtol=0)
+    np.testing.assert_allclose(r1["E"], T.T @ rm["E"], atol=1e-12 * max(np.abs(r1["E"]).max(), 1e-300), rtol=0)
+
+
 def test_sigma_flip_match_geometric_definition():
     """The generator's sign n.n^K_F and orientation flags, re-derived from the
     coordinates: +1 where the element's outward normal agrees with the face's
@@ -316,6 +383,51 @@ def test_l_equals_s_reduces_to_conforming_galerkin(N, s):
         for p, val in zip(nodes_l[e], uh[e]):
             k = (int(round(p[0] * N * s)), int(round(p[1] * N * s)))
             assert abs(val - ref[k]) < 1e-11 * scale
+
+
+@pytest.mark.parametrize("N,s,m", [(2, 2, 2), (2, 4, 4), (3, 3, 3)])
+def test_m_equals_s_linear_reduces_to_conforming_galerkin(N, s, m):
+    """m = s segments of degree 1 (one linear function pair per sub-edge)
+    force continuity across every face, so MHM equals textbook P1 Galerkin
+    on the composite fine mesh node by node, as for l = s with m = 1."""
+    mesh = coarse_mesh(N)
+    E = mesh["elems"].shape[0]
+    b = configs.build_batch(mesh, np.arange(E), np.full(E, s), np.full(E, 1), _smooth_k, manufactured_source)
+    b["m"] = np.full(E, m, dtype=np.int32)
+    res = local.solve_batch(b)
+    lam, u0, K, rhs = skeleton.reduce_and_solve(mesh, res, np.arange(E), 1, m)
+    uh = skeleton.reconstruct(mesh, res, np.arange(E), 1, lam, u0, m)
+    nodes_l, tris_l, kap_l, f_l = [], [], [], []
+    for e in range(E):
+        nodes, tris = local.submesh(b["vert"][e], s)
+        o0, o1 = b["tri_off"][e], b["tri_off"][e + 1]
+        nodes_l.append(nodes)
+        tris_l.append(tris)
+        kap_l.append(b["kappa"][o0:o1])
+        f_l.append(b["f"][o0:o1])
+    ref = galerkin_ref.fine_mesh_solve(nodes_l, tris_l, kap_l, f_l, N * s)
+    scale = max(abs(x) for x in ref.values())
+    for e in range(E):
+        for p, val in zip(nodes_l[e], uh[e]):
+            k = (int(round(p[0] * N * s)), int(round(p[1] * N * s)))
+            assert abs(val - ref[k]) < 1e-11 * scale
+
+
+def test_segmented_multipliers_converge_at_second_order():
+    """m = 2, l = 0 (piecewise constant multipliers on two segments): L2
+    error falls at rate 2 under coarse-mesh refinement."""
+    errs = []
+    for N in (2, 4, 8):
+        mesh = coarse_mesh(N)
+        E = mesh["elems"].shape[0]
+        b = configs.build_batch(mesh, np.arange(E), np.full(E, 4), np.full(E, 0), _ones, manufactured_source)
+        b["m"] = np.full(E, 2, dtype=np.int32)
+        res = local.solve_batch(b)
+        lam, u0, K, rhs = skeleton.reduce_and_solve(mesh, res, np.arange(E), 0, 2)
+        uh = skeleton.reconstruct(mesh, res, np.arange(E), 0, lam, u0, 2)
+        errs.append(skeleton.l2_error(b, uh, manufactured_solution))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((rates > 1.8) & (rates < 2.3)), (errs, rates)
 
 
 def test_manufactured_solution_converges_at_second_order():
