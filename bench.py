@@ -295,7 +295,7 @@ def _skeleton_leg(torch, ctx, batch, db, out, steps):
     from paper_1703_10435_amd.skeleton import SkeletonSystem
     E = batch["n_elem"]
     l = int(batch["l"][0])
-    sk = SkeletonSystem(batch["mesh"], l, l_max=db.desc.l_max)
+    sk = SkeletonSystem(batch["mesh"], l, p_max=db.p_max)
     NI, NImax = 3 * (l + 1), db.NImax
     vals = torch.zeros(sk.nnz, dtype=torch.float64, device="cuda")
     rhs = torch.zeros(sk.n_rows, dtype=torch.float64, device="cuda")

@@ -72,6 +72,7 @@ extern "C" {
 
 #define MHM_S_LIMIT 64   /* largest s per element          */
 #define MHM_L_LIMIT 4    /* largest l per element (r <= 16) */
+#define MHM_P_LIMIT 5    /* largest m (l + 1), face DoFs per face (r <= 16) */
 
 typedef struct mhm_ctx_s* mhm_ctx;
 typedef struct mhm_graph_s* mhm_graph;
@@ -93,8 +94,7 @@ typedef enum {
 typedef struct {
   int32_t n_elem;          /* host: number of elements (0 is allowed)          */
   int32_t s_max;           /* host: upper bound on s over the batch            */
-  int32_t l_max;           /* host: bound on l; contribution blocks are padded
-                              to NImax = 3(l_max+1)                             */
+  int32_t l_max;           /* host: bound on l                                 */
   int32_t s_min;           /* host: lower bound on s over the batch (0: unknown,
                               taken as 1).  When [s_min, s_max] spans several
                               size classes the batch is binned on the device
@@ -114,6 +114,16 @@ typedef struct {
   int64_t mat_total;       /* host: doubles in the Ahat buffer                 */
   int64_t rhs_total;       /* host: doubles in the Btilde and X buffers        */
   int64_t node_total;      /* host: doubles in the c buffer                    */
+  const int32_t* m;        /* [n_elem] segments per face (the m-partition of
+                              each face in Section 2: a polynomial of degree l
+                              on each of m equal segments, segments and the
+                              Legendre variable in the global face orientation),
+                              or NULL for m = 1 everywhere.  m must divide s,
+                              and m(l+1) <= MHM_P_LIMIT.  N_I = 3 m (l+1)      */
+  int32_t p_max;           /* host: bound on m(l+1) over the batch, 0 for
+                              l_max + 1; contribution blocks (M, E, B) are
+                              padded to NImax = 3 p_max                        */
+  int32_t reserved;        /* set to 0                                         */
 } mhm_batch;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`

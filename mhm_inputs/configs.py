@@ -44,7 +44,7 @@ def _centroids_grouped(vert: np.ndarray, s_arr: np.ndarray):
         yield idx, pts
 
 
-def build_batch(mesh: dict, elem_ids, s_arr, l_arr, kappa_fn, f_fn, name: str = "") -> dict:
+def build_batch(mesh: dict, elem_ids, s_arr, l_arr, kappa_fn, f_fn, name: str = "", m_arr=None) -> dict:
     elem_ids = np.asarray(elem_ids, dtype=np.int64)
     E = elem_ids.size
     s_arr = np.asarray(s_arr, dtype=np.int32).reshape(E)
@@ -76,6 +76,7 @@ def build_batch(mesh: dict, elem_ids, s_arr, l_arr, kappa_fn, f_fn, name: str = 
         tri_off=tri_off,
         elem_id=elem_ids,
         mesh=mesh,
+        m=None if m_arr is None else np.asarray(m_arr, dtype=np.int32).reshape(E),
     )
 
 
@@ -139,7 +140,8 @@ def sub_batch(batch: dict, idx) -> dict:
     return dict(name=batch["name"], n_elem=int(idx.size), s=s.copy(), l=batch["l"][idx].copy(),
                 vert=batch["vert"][idx].copy(), sigma=batch["sigma"][idx].copy(),
                 flip=batch["flip"][idx].copy(), kappa=kap, f=ff, tri_off=tri_off,
-                elem_id=batch["elem_id"][idx].copy(), mesh=batch["mesh"])
+                elem_id=batch["elem_id"][idx].copy(), mesh=batch["mesh"],
+                m=None if batch.get("m") is None else np.asarray(batch["m"])[idx].copy())
 
 
 def make(name: str, n_elem: int | None = None) -> dict:

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libmhm.so")
 
 MHM_OK, MHM_E_ARG, MHM_E_NOMEM, MHM_E_DEVICE, MHM_E_UNSUPPORTED = 0, 1, 2, 3, 4
 MHM_FP64, MHM_FP32_IR = 0, 1
-MHM_S_LIMIT, MHM_L_LIMIT = 64, 4
+MHM_S_LIMIT, MHM_L_LIMIT, MHM_P_LIMIT = 64, 4, 5
 
 INFO_OK, INFO_IR_FALLBACK, INFO_BAD_DESC, INFO_TOO_LARGE = 0, -1, -2, -3
 
@@ -37,6 +37,7 @@ class mhm_batch(ctypes.Structure):
         ("rhs_off", ctypes.c_void_p), ("node_off", ctypes.c_void_p),
         ("tri_total", ctypes.c_int64), ("mat_total", ctypes.c_int64), ("rhs_total", ctypes.c_int64),
         ("node_total", ctypes.c_int64),
+        ("m", ctypes.c_void_p), ("p_max", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -1,7 +1,8 @@
 """Host-side batch layout: offsets, validation and upload of a ragged batch.
 
-A batch (see ``mhm_inputs.configs``) lists per element s, l, the vertices,
-face signs and orientation flags, and kappa, f per sub-triangle.  Here the
+A batch (see ``mhm_inputs.configs``) lists per element s, l, optionally m
+(segments per face, default 1), the vertices, face signs and orientation
+flags, and kappa, f per sub-triangle.  Here the
 prefix offsets of every per-element block are computed, the descriptor is
 checked on the host (sizes, ranges, finite values) and the arrays are copied
 to device memory owned by torch tensors.
@@ -18,8 +19,14 @@ def n_nodes(s):
     return (s + 1) * (s + 2) // 2
 
 
-def n_rhs(l):
-    return 3 * (np.asarray(l, dtype=np.int64) + 1) + 1
+def n_rhs(l, m=1):
+    return 3 * np.asarray(m, dtype=np.int64) * (np.asarray(l, dtype=np.int64) + 1) + 1
+
+
+def segments(b: dict) -> np.ndarray:
+    """Per-element m (segments per face) of a batch dict, 1 when absent."""
+    m = b.get("m")
+    return np.ones(int(b["n_elem"]), dtype=np.int32) if m is None else np.asarray(m, dtype=np.int32)
 
 
 def _prefix(x):
@@ -28,10 +35,10 @@ def _prefix(x):
     return out
 
 
-def layout(s, l) -> dict:
+def layout(s, l, m=1) -> dict:
     """Offsets of the per-element blocks (Ahat n^2, Btilde/X n*r, c n, kappa s^2)."""
     n = n_nodes(s)
-    r = n_rhs(l)
+    r = n_rhs(l, m)
     s64 = np.asarray(s, dtype=np.int64)
     return dict(n=n, r=r, tri_off=_prefix(s64 * s64), mat_off=_prefix(n * n), rhs_off=_prefix(n * r),
                 node_off=_prefix(n))
@@ -48,6 +55,13 @@ def validate(b: dict) -> None:
         raise ValueError(f"s must lie in [1, {abi.MHM_S_LIMIT}]")
     if E and (l.min() < 0 or l.max() > abi.MHM_L_LIMIT):
         raise ValueError(f"l must lie in [0, {abi.MHM_L_LIMIT}]")
+    m = segments(b)
+    if m.shape != (E,):
+        raise ValueError("m must have one entry per element")
+    if E and (m.min() < 1 or np.any(s % m != 0)):
+        raise ValueError("m must be >= 1 and divide s")
+    if E and np.max(m * (l + 1)) > abi.MHM_P_LIMIT:
+        raise ValueError(f"m (l + 1) must be at most {abi.MHM_P_LIMIT}")
     if np.asarray(b["vert"]).shape != (E, 6):
         raise ValueError("vert must be (n_elem, 6)")
     for k in ("sigma", "flip"):
@@ -83,16 +97,20 @@ class DeviceBatch:
         E = int(b["n_elem"])
         s = np.asarray(b["s"], dtype=np.int32)
         l = np.asarray(b["l"], dtype=np.int32)
-        lay = layout(s, l)
+        m = segments(b)
+        lay = layout(s, l, m)
         self.n_elem = E
         self.s = s
         self.l = l
+        self.m = m
         self.n = lay["n"]
         self.r = lay["r"]
         self.s_max = int(s.max()) if E else 1
         self.s_min = int(s.min()) if E else 1
         self.l_max = int(l.max()) if E else 0
-        self.NImax = 3 * (self.l_max + 1)
+        self.p_max = int(np.max(m * (l + 1))) if E else 1
+        self.NImax = 3 * self.p_max
+        self.has_m = b.get("m") is not None
         self.mat_off = lay["mat_off"]
         self.rhs_off = lay["rhs_off"]
         self.node_off = lay["node_off"]
@@ -118,6 +136,10 @@ class DeviceBatch:
         d.mat_total = int(lay["mat_off"][-1])
         d.rhs_total = int(lay["rhs_off"][-1])
         d.node_total = int(lay["node_off"][-1])
+        if self.has_m:
+            self.t["m"] = up(m, np.int32)
+            d.m = self.t["m"].data_ptr() if E else None
+        d.p_max = self.p_max
         self.desc = d
         self.mat_total = d.mat_total
         self.rhs_total = d.rhs_total

@@ -94,6 +94,8 @@ mhm_status hip_fail(mhm_ctx c, hipError_t e, const char* where) {
 }
 
 int n_of(int s) { return (s + 1) * (s + 2) / 2; }
+// Bound on the face DoFs per face, m (l + 1); the contribution blocks are 3x that wide.
+int p_bound(const mhm_batch* b) { return b->p_max > 0 ? b->p_max : b->l_max + 1; }
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 mhm_status check_batch(mhm_ctx c, const mhm_batch* b, bool need_mat, bool need_node) {
@@ -104,6 +106,8 @@ mhm_status check_batch(mhm_ctx c, const mhm_batch* b, bool need_mat, bool need_n
   if (b->s_max < 1 || b->s_max > MHM_S_LIMIT) return fail(c, MHM_E_UNSUPPORTED, "s_max outside [1, MHM_S_LIMIT]");
   if (b->s_min < 0 || b->s_min > b->s_max) return fail(c, MHM_E_ARG, "s_min outside [0, s_max]");
   if (b->l_max < 0 || b->l_max > MHM_L_LIMIT) return fail(c, MHM_E_UNSUPPORTED, "l_max outside [0, MHM_L_LIMIT]");
+  if (b->p_max < 0 || p_bound(b) > MHM_P_LIMIT)
+    return fail(c, MHM_E_UNSUPPORTED, "p_max (bound on m(l+1)) outside [0, MHM_P_LIMIT]");
   if (!b->s || !b->l || !b->vert || !b->sigma || !b->flip || !b->kappa || !b->f || !b->tri_off || !b->rhs_off)
     return fail(c, MHM_E_ARG, "a required batch array is NULL");
   if (need_mat && !b->mat_off) return fail(c, MHM_E_ARG, "mat_off is NULL");
@@ -131,7 +135,7 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
   p.fused = fused;
   p.ch = ch;
   p.n_cap = n_of(s_cap);
-  p.f_cap = 3 * (b->l_max + 1) * (s_cap + 1);
+  p.f_cap = 3 * p_bound(b) * (s_cap + 1);
   p.nt = (p.n_cap + 15) / 16;
   p.tile_cap = p.nt * (p.nt + 1) / 2 + p.nt;
   const size_t tsz = fp32 ? sizeof(float) : sizeof(double);

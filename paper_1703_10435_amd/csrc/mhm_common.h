@@ -103,11 +103,10 @@ __device__ __forceinline__ double node_tri_sum(int i, int j, int s, FN fn) {
 // ft[a*(s+1) + k] = R[face node k of face e(a)][a]   (face load table)
 // colsum[a] = 1^T B[:, a]  (face columns from ft, source column from bf)
 __device__ __forceinline__ void face_table(const Elem& E, double* ft) {
-  const int sp1 = E.s + 1, lp1 = E.l + 1;
+  const int sp1 = E.s + 1;
   for (int idx = threadIdx.x; idx < E.NI * sp1; idx += blockDim.x) {
     const int a = idx / sp1, k = idx - a * sp1;
-    const int e = a / lp1, q = a - e * lp1;
-    ft[idx] = face_load(E, e, q, k);
+    ft[idx] = face_load(E, a, k);
   }
 }
 __device__ __forceinline__ void face_colsums(const Elem& E, const double* ft, double* colsum) {
@@ -124,7 +123,7 @@ __device__ __forceinline__ double btilde_tab(const Elem& E, const double* ft, co
                                              const double* colsum, int a, int p, int i, int j) {
   double v = 0.0;
   if (a < E.NI) {
-    const int e = a / (E.l + 1);
+    const int e = a / E.P;
     const int k = face_pos(e, i, j, E.s);
     if (k >= 0) v = ft[a * (E.s + 1) + k];
   } else {
@@ -140,7 +139,7 @@ __device__ __forceinline__ double btilde_tab(const Elem& E, const double* ft, co
 __device__ __forceinline__ void contrib_element(const Elem& E, const double* X, const double* ft, double Fval, int NImax,
                                 double* M, double* Ev, double* Bv, double* F, int e) {
   const int tid = threadIdx.x;
-  const int NI = E.NI, n = E.n, lp1 = E.l + 1, s = E.s, sp1 = s + 1;
+  const int NI = E.NI, n = E.n, s = E.s, sp1 = s + 1;
   double* Me = M + (int64_t)e * NImax * NImax;
   for (int idx = tid; idx < NImax * NImax; idx += blockDim.x) {
     const int a = idx % NImax, bb = idx / NImax;
@@ -148,7 +147,7 @@ __device__ __forceinline__ void contrib_element(const Elem& E, const double* X, 
   }
   if (tid < NI * E.r) {
     const int a = tid % NI, bb = tid / NI;
-    const int ef = a / lp1;
+    const int ef = a / E.P;
     const double* fa = ft + a * sp1;
     const double* xb = X + (int64_t)bb * n;
     double v = 0.0;

@@ -34,7 +34,12 @@ struct BatchDev {
   const int64_t* rhs_off;
   const int64_t* node_off;
   int64_t tri_total, mat_total, rhs_total, node_total;
+  const int32_t* m;   // segments per face, null = 1
+  int p_max;          // bound on m (l + 1): contribution blocks are 3 p_max wide
 };
+
+// Padded width of the contribution blocks M, E, B.
+__host__ __device__ inline int nimax(const BatchDev& b) { return 3 * b.p_max; }
 
 inline BatchDev to_dev(const mhm_batch* p) {
   BatchDev d;
@@ -56,12 +61,15 @@ inline BatchDev to_dev(const mhm_batch* p) {
   d.mat_total = p->mat_total;
   d.rhs_total = p->rhs_total;
   d.node_total = p->node_total;
+  d.m = p->m;
+  d.p_max = p->p_max > 0 ? p->p_max : p->l_max + 1;
   return d;
 }
 
 // One element's geometry and offsets, decoded once per workgroup.
 struct Elem {
   int s, l, n, NI, r, nt;   // nt = ceil(n / 16) tiles per matrix edge
+  int m, P;                 // segments per face, face DoFs per face m (l + 1); NI = 3 P
   double area;              // |K|
   double G[3][3];           // D_a . D_b / (4 |K|): P1 stiffness of any sub-triangle / kappa
   double flen[3];           // |F_e|
@@ -92,11 +100,15 @@ __device__ __forceinline__ void node_ij(int p, int s, int& i, int& j) {
 __device__ __forceinline__ bool load_elem(const BatchDev& b, int e, Elem& E) {
   const int s = b.s[e];
   const int l = b.l[e];
+  const int m = b.m ? b.m[e] : 1;
   if (s < 1 || s > MHM_S_LIMIT || s > b.s_max || l < 0 || l > MHM_L_LIMIT || l > b.l_max) return false;
+  if (m < 1 || s % m != 0 || m * (l + 1) > b.p_max || m * (l + 1) > MHM_P_LIMIT) return false;
   E.s = s;
   E.l = l;
+  E.m = m;
+  E.P = m * (l + 1);
   E.n = (s + 1) * (s + 2) / 2;
-  E.NI = 3 * (l + 1);
+  E.NI = 3 * E.P;
   E.r = E.NI + 1;
   E.nt = (E.n + 15) / 16;
   const int64_t t0 = b.tri_off[e], t1 = b.tri_off[e + 1];
@@ -216,18 +228,32 @@ __device__ __forceinline__ double legendre(int q, double t) {
 
 // R[node at position k of face e][column e(l+1)+q] = -sigma_e (P_q, phi)_{F_e}:
 // exact for q <= 4 with the 3-point Gauss rule on each of the s face segments.
-__device__ __forceinline__ double face_load(const Elem& E, int e, int q, int k) {
+// Face load of face DoF a at lattice position k (0..s) of its face:
+// -sigma_e times the integral of psi_a phi_k over the face (eq. (9)).  DoF
+// a = (e m + seg)(l + 1) + q is P_q(t) on segment seg of the m-partition of
+// face e; segments and t in [-1, 1] run along the global orientation (from
+// the lower global vertex id), so with the global face parameter g = tau
+// (or 1 - tau when flip[e]), t = 2 (m g - seg) - 1.  Each sub-edge lies in one
+// segment (m divides s); 3-point Gauss on each sub-edge is exact (degree
+// q + 1 <= 5).
+__device__ __forceinline__ double face_load(const Elem& E, int a, int k) {
   const double r15 = 0.38729833462074168852;  // sqrt(15)/10
   const double xg[3] = {0.5 - r15, 0.5, 0.5 + r15};
   const double wg[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
-  const int s = E.s;
+  const int s = E.s, lp1 = E.l + 1;
+  const int e = a / E.P, rem = a - e * E.P;
+  const int segf = rem / lp1, q = rem - segf * lp1;
+  const int per = s / E.m;                    // sub-edges per segment
+  const bool fl = E.flip[e] != 0;
   double acc = 0.0;
   for (int side = 0; side < 2; ++side) {
-    const int seg = side == 0 ? k - 1 : k;   // node k is the right end of seg k-1, left end of seg k
+    const int seg = side == 0 ? k - 1 : k;   // node k is the right end of sub-edge k-1, left end of k
     if (seg < 0 || seg >= s) continue;
+    if ((fl ? s - 1 - seg : seg) / per != segf) continue;
     for (int g = 0; g < 3; ++g) {
       const double tau = (seg + xg[g]) * E.inv_s;
-      const double t = E.flip[e] ? 1.0 - 2.0 * tau : 2.0 * tau - 1.0;
+      const double gp = fl ? 1.0 - tau : tau;
+      const double t = 2.0 * (E.m * gp - segf) - 1.0;
       const double hat = side == 0 ? xg[g] : 1.0 - xg[g];
       acc += wg[g] * legendre(q, t) * hat;
     }

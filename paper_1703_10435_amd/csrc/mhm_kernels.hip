@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(NTHREADS) k_contrib(BatchDev b, const double* 
   __shared__ double red[48];
   __shared__ double fsum;
   extern __shared__ double ft[];   // NI(s+1)
-  const int NImax = 3 * (b.l_max + 1);
+  const int NImax = nimax(b);
   for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
     __syncthreads();
     if (threadIdx.x == 0) ok = (info == nullptr || info[e] == 0 || info[e] == INFO_IR_FALLBACK) &&
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
   __shared__ double rmax[16], xmax[16], bmax[16];
   extern __shared__ double dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int NImax = 3 * (b.l_max + 1);
+  const int NImax = nimax(b);
   const bool fp32 = sizeof(T) == 4;
 
   const int n_launch = launch_count(args, b.n_elem);
@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(NTHREADS) k_reconstruct(BatchDev b, const doub
   __shared__ double lam[16];
   __shared__ double u0;
   const int tid = threadIdx.x;
-  const int NImax = 3 * (b.l_max + 1);
+  const int NImax = nimax(b);
   for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
     __syncthreads();
     if (tid == 0) {
@@ -513,7 +513,7 @@ __global__ void __launch_bounds__(NTHREADS) k_skeleton_scatter(BatchDev b, const
                                                                 const int32_t* row_ptr, const int32_t* col_idx,
                                                                 double* vals, double* rhs, const int32_t* info,
                                                                 int32_t n_rows, int32_t* missing) {
-  const int NImax = 3 * (b.l_max + 1);
+  const int NImax = nimax(b);
   const int per = NImax * NImax + 2 * NImax + NImax + 1;   // M, B, B^T, E, F
   const int64_t total = (int64_t)b.n_elem * per;
   for (int64_t idx = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NTHREADS) {
@@ -521,8 +521,9 @@ __global__ void __launch_bounds__(NTHREADS) k_skeleton_scatter(BatchDev b, const
     int k = (int)(idx - (int64_t)e * per);
     if (info && info[e] != INFO_OK && info[e] != INFO_IR_FALLBACK) continue;
     const int l = b.l[e];
-    if (l < 0 || l > MHM_L_LIMIT || l > b.l_max) continue;
-    const int NI = 3 * (l + 1);
+    const int m = b.m ? b.m[e] : 1;
+    if (l < 0 || l > MHM_L_LIMIT || l > b.l_max || m < 1 || m * (l + 1) > b.p_max) continue;
+    const int NI = 3 * m * (l + 1);
     const int32_t* g = gdof + (int64_t)e * NImax;
     int row = -1, col = -1;
     double v = 0.0;
@@ -642,7 +643,7 @@ hipError_t launch_bin(const mhm_batch* bt, const BinClasses& cls, int32_t* elist
 }
 
 // ------------------------------------------------------------- host launchers
-int local_face_cap(const mhm_batch* bt) { return 3 * (bt->l_max + 1) * (bt->s_max + 1); }
+int local_face_cap(const mhm_batch* bt) { return nimax(to_dev(bt)) * (bt->s_max + 1); }
 
 hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, double* c, double* area, int32_t* info,
                            int grid, hipStream_t st) {

@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
   __shared__ double rmax[16], xmax[16], bmax[16];
   extern __shared__ double dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int NImax = 3 * (b.l_max + 1);
+  const int NImax = nimax(b);
   const bool fp32 = sizeof(T) == 4;
 
   const int n_launch = launch_count(args, b.n_elem);

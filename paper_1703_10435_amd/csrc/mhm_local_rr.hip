@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
   __shared__ double gam;
   extern __shared__ double dyn[];      // c | bf | ft | kap | stencil[8 n] | P[NT] | W[NT] | R[NT]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int NImax = 3 * (b.l_max + 1);
+  const int NImax = nimax(b);
 
   double* c = dyn;
   double* bf = c + args.n_cap;
@@ -262,11 +262,10 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
     // ------------------------------------------------------------- set-up
     if (FUSED) {
       for (int t = tid; t < T2; t += NTHREADS) kapl[t] = kapg[t];
-      const int sp1 = s + 1, lp1 = E.l + 1;
+      const int sp1 = s + 1;
       for (int idx = tid; idx < E.NI * sp1; idx += NTHREADS) {
         const int a = idx / sp1, k = idx - a * sp1;
-        const int ef = a / lp1, q = a - ef * lp1;
-        ft[idx] = face_load(E, ef, q, k);
+        ft[idx] = face_load(E, a, k);
       }
     }
     __syncthreads();
@@ -372,7 +371,7 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
             node_ij(q, s, qi, qj);
             double base = 0.0;
             if (a < E.NI) {
-              const int ef = a / (E.l + 1);
+              const int ef = a / E.P;
               const int kk = face_pos(ef, qi, qj, s);
               if (kk >= 0) base = ft[a * (s + 1) + kk];
             } else {
@@ -538,7 +537,7 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
     __syncthreads();
     if (FUSED && args.M) {
       // contribution blocks of eq. (6): M = -R^T X_I, E = R^T x_f, B, F
-      const int NI = E.NI, lp1 = E.l + 1, sp1 = s + 1;
+      const int NI = E.NI, sp1 = s + 1;
       double* Me = args.M + (int64_t)e * NImax * NImax;
       for (int idx = tid; idx < NImax * NImax; idx += NTHREADS) {
         const int a = idx % NImax, bb = idx / NImax;
@@ -546,7 +545,7 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
       }
       if (tid < NI * r) {
         const int a = tid % NI, bb = tid / NI;
-        const int ef = a / lp1;
+        const int ef = a / E.P;
         const double* fa = ft + a * sp1;
         const double* xb = X + (int64_t)bb * n;
         double v = 0.0;

@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(64 * SS_WAVES) k_source_step(BatchDev b, Sourc
   Elem& E = Es[wave];
   double* bt = dyn + (int64_t)wave * a.wave_words;                    // btilde (FP64), n_cap
   T* y = reinterpret_cast<T*>(bt + a.n_cap);                          // solve vector, 16 nt_cap
-  const int NImax = 3 * (b.l_max + 1);
+  const int NImax = nimax(b);
   constexpr bool fp32 = sizeof(T) == 4;
 
   for (int e = blockIdx.x * SS_WAVES + wave; e < b.n_elem; e += gridDim.x * SS_WAVES) {
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(64 * SS_WAVES) k_source_step(BatchDev b, Sourc
     wave_sync();
     if (!ok_s[wave]) continue;
 
-    const int s = E.s, n = E.n, nt = E.nt, NI = E.NI, lp1 = E.l + 1;
+    const int s = E.s, n = E.n, nt = E.nt, NI = E.NI;
     const double* fp = b.f + E.tri0;
     const double* kapg = b.kappa + E.tri0;
     auto kap = [&](int t) -> double { return kapg[t]; };
@@ -295,8 +295,8 @@ __global__ void __launch_bounds__(64 * SS_WAVES) k_source_step(BatchDev b, Sourc
     if (lane < NImax) {
       double v = 0.0;
       if (lane < NI) {
-        const int ef = lane / lp1, q = lane - ef * lp1;
-        for (int k = 0; k <= s; ++k) v += face_load(E, ef, q, k) * xg[face_node(ef, k, s)];
+        const int ef = lane / E.P;
+        for (int k = 0; k <= s; ++k) v += face_load(E, lane, k) * xg[face_node(ef, k, s)];
       }
       a.E[(int64_t)e * NImax + lane] = v;
     }

@@ -16,21 +16,25 @@ from __future__ import annotations
 import numpy as np
 
 
-def numbering(elem_face: np.ndarray, n_faces: int, l: int, elem_ids=None, l_max: int | None = None):
-    """gdof [n_elem, 3*(l_max+1)] (entries past N_I = 3(l+1) are -1), erow
+def numbering(elem_face: np.ndarray, n_faces: int, l: int, elem_ids=None, p_max: int | None = None, m: int = 1):
+    """gdof [n_elem, 3 p_max] (entries past N_I = 3 m (l+1) are -1), erow
     [n_elem] and the number of rows, for the elements ``elem_ids`` (default
-    all) of a mesh with uniform face degree l."""
+    all) of a mesh with a uniform face space (m segments of degree l per
+    face).  Face g's DoF (seg, q) is row (g m + seg)(l + 1) + q; the
+    element's local DoF (e m + seg)(l + 1) + q refers to the same function
+    (segments in the face's global orientation)."""
     elem_face = np.asarray(elem_face, dtype=np.int64)
     nt = elem_face.shape[0]
     ids = np.arange(nt) if elem_ids is None else np.asarray(elem_ids, dtype=np.int64)
-    l_max = l if l_max is None else l_max
-    if l_max < l:
-        raise ValueError("l_max < l")
-    NI, NImax = 3 * (l + 1), 3 * (l_max + 1)
-    nl = n_faces * (l + 1)
+    P = m * (l + 1)
+    p_max = P if p_max is None else p_max
+    if p_max < P:
+        raise ValueError("p_max < m (l + 1)")
+    NI, NImax = 3 * P, 3 * p_max
+    nl = n_faces * P
     gdof = np.full((len(ids), NImax), -1, dtype=np.int64)
-    q = np.arange(l + 1)
-    gdof[:, :NI] = (elem_face[ids][:, :, None] * (l + 1) + q[None, None, :]).reshape(len(ids), NI)
+    k = np.arange(P)
+    gdof[:, :NI] = (elem_face[ids][:, :, None] * P + k[None, None, :]).reshape(len(ids), NI)
     erow = nl + ids
     return gdof.astype(np.int32), erow.astype(np.int32), nl + nt
 
@@ -65,11 +69,11 @@ class SkeletonSystem:
     calls around the local solves: scatter the element blocks into the CSR
     system, reconstruct u from a skeleton solution."""
 
-    def __init__(self, mesh: dict, l: int, elem_ids=None, l_max: int | None = None, device="cuda"):
+    def __init__(self, mesh: dict, l: int, elem_ids=None, p_max: int | None = None, device="cuda", m: int = 1):
         import torch
         self.gdof_h, self.erow_h, self.n_rows = numbering(mesh["elem_face"], mesh["faces"].shape[0], l, elem_ids,
-                                                          l_max)
-        ni = np.full(len(self.erow_h), 3 * (l + 1))
+                                                          p_max, m)
+        ni = np.full(len(self.erow_h), 3 * m * (l + 1))
         self.row_ptr_h, self.col_idx_h = csr_pattern(self.gdof_h, self.erow_h, self.n_rows, ni)
         i32 = dict(dtype=torch.int32, device=device)
         self.gdof = torch.as_tensor(self.gdof_h.ravel(), **i32)

@@ -87,6 +87,8 @@ def test_layout_offsets():
     (lambda b: b["l"].__setitem__(0, 9), "l must"),
     (lambda b: b["sigma"].__setitem__((0, 0), 2), "sigma"),
     (lambda b: b["vert"].__setitem__(0, b["vert"][0][[0, 1, 4, 5, 2, 3]]), "counter-clockwise"),
+    (lambda b: b.__setitem__("m", np.full(b["n_elem"], 3, dtype=np.int32)), "divide s"),
+    (lambda b: b.__setitem__("m", np.full(b["n_elem"], 4, dtype=np.int32)), "at most"),
 ])
 def test_validate_rejects_malformed_batches(mutate, msg):
     b = configs.make("C1")
@@ -102,8 +104,8 @@ def test_validate_accepts_configs():
     hb.validate(configs.make("C2", n_elem=4))
 
 
-@pytest.mark.parametrize("N,l,l_max", [(2, 1, 1), (3, 0, 2), (4, 2, 4)])
-def test_skeleton_numbering_and_pattern(N, l, l_max):
+@pytest.mark.parametrize("N,l,l_max,m", [(2, 1, 1, 1), (3, 0, 2, 1), (4, 2, 4, 1), (2, 1, 1, 2), (3, 0, 4, 3)])
+def test_skeleton_numbering_and_pattern(N, l, l_max, m):
     """The host numbering gives the oracle's global DoFs, and the CSR pattern
     is exactly the set of positions that a dense assembly of nonzero element
     blocks touches, with sorted columns."""
@@ -112,15 +114,16 @@ def test_skeleton_numbering_and_pattern(N, l, l_max):
     from paper_1703_10435_amd import skeleton as sk
     mesh = coarse_mesh(N)
     nt = mesh["elems"].shape[0]
-    gdof, erow, n_rows = sk.numbering(mesh["elem_face"], mesh["faces"].shape[0], l, l_max=l_max)
-    NI = 3 * (l + 1)
-    assert gdof.shape == (nt, 3 * (l_max + 1)) and np.all(gdof[:, NI:] == -1)
+    p_max = max(l_max + 1, m * (l + 1))
+    gdof, erow, n_rows = sk.numbering(mesh["elem_face"], mesh["faces"].shape[0], l, p_max=p_max, m=m)
+    NI = 3 * m * (l + 1)
+    assert gdof.shape == (nt, 3 * p_max) and np.all(gdof[:, NI:] == -1)
     for t in range(nt):
-        np.testing.assert_array_equal(gdof[t, :NI], oskel.global_dofs(mesh, t, l))
+        np.testing.assert_array_equal(gdof[t, :NI], oskel.global_dofs(mesh, t, l, m))
     rng = np.random.default_rng(N)
     res = [dict(M=rng.uniform(1, 2, (NI, NI)), B=rng.uniform(1, 2, NI), E=rng.uniform(1, 2, NI), F=1.0)
            for _ in range(nt)]
-    K, _ = oskel.assemble_global(mesh, res, np.arange(nt), l)
+    K, _ = oskel.assemble_global(mesh, res, np.arange(nt), l, m)
     assert K.shape == (n_rows, n_rows)
     rp, ci = sk.csr_pattern(gdof, erow, n_rows, np.full(nt, NI))
     mask = np.zeros((n_rows, n_rows), dtype=bool)

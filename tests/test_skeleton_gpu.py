@@ -67,7 +67,7 @@ def test_scatter_matches_oracle_assembly(ctx, N, s, l, prec):
     mesh = coarse_mesh(N)
     say(f"[gpu] scatter N={N} s={s} l={l} prec={prec}")
     b, res, out, db = _gpu_local(ctx, mesh, s, l, _rough_k, prec)
-    sk = SkeletonSystem(mesh, l, l_max=db.desc.l_max)
+    sk = SkeletonSystem(mesh, l, p_max=db.p_max)
     vals, rhs, missing = sk.scatter(ctx, db, out)
     ctx.sync()
     assert int(missing.item()) == 0
@@ -93,7 +93,7 @@ def test_scatter_skips_failed_elements_and_reports_missing(ctx):
     mesh = coarse_mesh(2)
     l = 1
     b, res, out, db = _gpu_local(ctx, mesh, 4, l, _ones, 0)
-    sk = SkeletonSystem(mesh, l, l_max=db.desc.l_max)
+    sk = SkeletonSystem(mesh, l, p_max=db.p_max)
     bad = 3
     info = out["info"].clone()
     info[bad] = 7                                     # as a failed factorisation would report
@@ -134,7 +134,7 @@ def test_reconstruct_matches_oracle(ctx, N, s, l, prec):
     ora = local.solve_batch(b)
     lam, u0, _, _ = oskel.reduce_and_solve(mesh, ora, np.arange(b["n_elem"]), l)
     sol = np.concatenate([lam, u0])
-    sk = SkeletonSystem(mesh, l, l_max=db.desc.l_max)
+    sk = SkeletonSystem(mesh, l, p_max=db.p_max)
     u = sk.reconstruct(ctx, db, out, torch.as_tensor(sol, device="cuda"))
     ctx.sync()
     u = u.cpu().numpy()
@@ -153,7 +153,7 @@ def test_reconstruct_skips_failed_elements(ctx):
     from paper_1703_10435_amd.skeleton import SkeletonSystem
     mesh = coarse_mesh(2)
     b, res, out, db = _gpu_local(ctx, mesh, 4, 1, _ones, 0)
-    sk = SkeletonSystem(mesh, 1, l_max=db.desc.l_max)
+    sk = SkeletonSystem(mesh, 1, p_max=db.p_max)
     info = out["info"].clone()
     info[2] = 5
     sol = torch.ones(sk.n_rows, dtype=torch.float64, device="cuda")
@@ -177,7 +177,7 @@ def test_chain_converges_at_second_order(ctx, prec):
         mesh = coarse_mesh(N)
         say(f"[gpu] chain N={N} prec={prec}")
         b, res, out, db = _gpu_local(ctx, mesh, 4, 1, _ones, prec)
-        sk = SkeletonSystem(mesh, 1, l_max=db.desc.l_max)
+        sk = SkeletonSystem(mesh, 1, p_max=db.p_max)
         vals, rhs, missing = sk.scatter(ctx, db, out)
         ctx.sync()
         assert int(missing.item()) == 0
