@@ -334,8 +334,23 @@ def _skeleton_leg(torch, ctx, batch, db, out, steps):
         want = sh[sk.erow_h[e]] + res[e]["X"][:, :NI] @ sh[sk.gdof_h[e, :NI]] + res[e]["X"][:, NI]
         got = uh[db.node_off[e]:db.node_off[e + 1]]
         err_r = max(err_r, float(np.abs(got - want).max() / np.abs(want).max()))
+    # the skeleton solve (MINRES on the device; it synchronises, so it is
+    # timed by the host clock around the call)
+    import time
+    import scipy.sparse.linalg as spla
+    xs = torch.empty(sk.n_rows, dtype=torch.float64, device="cuda")
+    sk.solve(ctx, vals, rhs, xs, tol=1e-10)             # warm-up
+    t0 = time.perf_counter()
+    _, it_s, rr_s = sk.solve(ctx, vals, rhs, xs, tol=1e-10)
+    ms_solve = (time.perf_counter() - t0) * 1e3
+    xd = spla.spsolve(K.tocsc(), rhs.cpu().numpy())     # host sparse direct solve of the same system
+    nl = sk.n_lambda
+    err_solve = float(np.abs(xs.cpu().numpy()[nl:] - xd[nl:]).max() / np.abs(xd[nl:]).max())
     gbs = lambda b, ms: b / (ms * 1e-3) / 1e9  # noqa: E731
     return {"n_rows": sk.n_rows, "nnz": sk.nnz,
+            "solve_ms": ms_solve, "solve_minres_steps": it_s, "solve_relres": rr_s,
+            "solve_ms_per_step": ms_solve / max(it_s, 1),
+            "solve_u0_rel_diff_vs_host_direct": err_solve,
             "scatter_ms": ms_s, "scatter_GBps": gbs(b_scatter, ms_s),
             "scatter_frac_hbm": gbs(b_scatter, ms_s) / PEAK_HBM_GBS, "scatter_bytes": b_scatter,
             "reconstruct_ms": ms_r, "reconstruct_GBps": gbs(b_recon, ms_r),

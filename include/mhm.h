@@ -216,6 +216,36 @@ mhm_status mhm_skeleton_scatter(mhm_ctx ctx, const mhm_batch* batch, const doubl
 mhm_status mhm_reconstruct(mhm_ctx ctx, const mhm_batch* batch, const double* X, const int32_t* gdof,
                            const int32_t* erow, const double* sol, int32_t n_rows, double* u, const int32_t* info);
 
+/* The skeleton solve (the solve of reduceLocalProblems, Algorithm 1):
+ * eq. (6) is symmetric and indefinite, [[M, B^T], [B, 0]] [lambda; u_0] =
+ * [E; F] with M negative (semi-)definite.  Preconditioned MINRES (the
+ * minimal-residual method for symmetric indefinite systems) with the block
+ * diagonal preconditioner diag(|diag M|, diag(B |diag M|^-1 B^T)); the paper
+ * uses sparse direct solvers and names hybrid direct-iterative ones as
+ * future work (Section 6).
+ *   n_rows, n_lambda  rows of the system; rows < n_lambda are multiplier
+ *             rows (M, B^T), the others u_0 rows (B, 0), as numbered for
+ *             mhm_skeleton_scatter.
+ *   row_ptr [n_rows+1], col_idx, vals (device): the CSR matrix, e.g. as
+ *             accumulated by mhm_skeleton_scatter (both triangles).  The
+ *             structure is checked on the device first (row pointers from 0,
+ *             non-decreasing; columns in [0, n_rows)); a violation returns
+ *             MHM_E_ARG before any product.  vals must hold row_ptr[n_rows]
+ *             entries.
+ *   rhs [n_rows] (device), sol [n_rows] (device, written; x_0 = 0).
+ *   tol       stop when the preconditioned residual norm has fallen by tol.
+ *   max_iters bound on the MINRES steps.
+ *   iters, relres (host, may be NULL): steps taken and the final true
+ *             relative residual ||rhs - K sol||_2 / ||rhs||_2.
+ * A singular but consistent system (multiplier block rank deficient, l >= s)
+ * is fine: u_0, and u of mhm_reconstruct, are unique.  Uses the context's
+ * workspace (9 n_rows doubles plus a few KB); synchronises the stream (the
+ * host reads the residual estimate every 16 steps); deterministic for a
+ * given launch configuration. */
+mhm_status mhm_skeleton_solve(mhm_ctx ctx, int32_t n_rows, int32_t n_lambda, const int32_t* row_ptr,
+                              const int32_t* col_idx, const double* vals, const double* rhs, double* sol,
+                              double tol, int32_t max_iters, int32_t* iters, double* relres);
+
 /* Factor reuse (Section 3: the local matrix is factored once and reused
  * for further load vectors, e.g. over time steps): mhm_local_batch_run with
  * each element's factor kept in a caller-owned device store.

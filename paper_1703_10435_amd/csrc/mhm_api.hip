@@ -648,6 +648,36 @@ mhm_status mhm_skeleton_scatter(mhm_ctx c, const mhm_batch* b, const double* M, 
   return e == hipSuccess ? MHM_OK : hip_fail(c, e, "k_skeleton_scatter launch");
 }
 
+mhm_status mhm_skeleton_solve(mhm_ctx c, int32_t n_rows, int32_t n_lambda, const int32_t* row_ptr,
+                              const int32_t* col_idx, const double* vals, const double* rhs, double* sol, double tol,
+                              int32_t max_iters, int32_t* iters, double* relres) {
+  if (!c) return MHM_E_ARG;
+  if (n_rows < 0 || n_lambda < 0 || n_lambda > n_rows) return fail(c, MHM_E_ARG, "need 0 <= n_lambda <= n_rows");
+  if (!(tol > 0.0) || max_iters < 0) return fail(c, MHM_E_ARG, "need tol > 0 and max_iters >= 0");
+  if (iters) *iters = 0;
+  if (relres) *relres = 0.0;
+  if (n_rows == 0) return MHM_OK;
+  if (!row_ptr || !col_idx || !vals || !rhs || !sol)
+    return fail(c, MHM_E_ARG, "row_ptr, col_idx, vals, rhs and sol are required");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  mhm_status st = ensure_ws(c, mhm::skeleton_solve_bytes(n_rows));
+  if (st != MHM_OK) return st;
+  int bad = 0;
+  e = mhm::skeleton_csr_check(n_rows, row_ptr, col_idx, c->ws, &bad, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "CSR check");
+  if (bad) return fail(c, MHM_E_ARG, std::to_string(bad) + " row pointers or column indices out of range");
+  std::vector<double> host_sc(64, 0.0);
+  int it = 0;
+  double rr = 0.0;
+  e = mhm::skeleton_solve(n_rows, n_lambda, row_ptr, col_idx, vals, rhs, sol, tol, max_iters, c->ws,
+                          host_sc.data(), &it, &rr, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "skeleton solve");
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  return MHM_OK;
+}
+
 size_t mhm_factor_bytes(int s, mhm_prec prec) {
   if (s < 1 || s > MHM_S_LIMIT) return 0;
   const int nt = (n_of(s) + 15) / 16;

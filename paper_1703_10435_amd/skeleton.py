@@ -81,6 +81,7 @@ class SkeletonSystem:
         self.row_ptr = torch.as_tensor(self.row_ptr_h, **i32)
         self.col_idx = torch.as_tensor(self.col_idx_h, **i32)
         self.nnz = int(self.row_ptr_h[-1])
+        self.n_lambda = self.n_rows - mesh["elems"].shape[0]   # multiplier rows come first
         self.device = device
 
     def scatter(self, ctx, db, out, vals=None, rhs=None, clear: bool = True):
@@ -115,3 +116,13 @@ class SkeletonSystem:
             raise ValueError("sol shorter than the skeleton system")
         ctx.reconstruct(db, out["X"], self.gdof, self.erow, sol, self.n_rows, u, out["info"])
         return u
+
+    def solve(self, ctx, vals, rhs, sol=None, tol: float = 1e-12, max_iters: int = 20000):
+        """mhm_skeleton_solve on the scattered system; returns (sol, iterations,
+        relative residual)."""
+        import torch
+        if sol is None:
+            sol = torch.empty(self.n_rows, dtype=torch.float64, device=self.device)
+        it, rr = ctx.skeleton_solve(self.n_rows, self.n_lambda, self.row_ptr, self.col_idx, vals, rhs, sol, tol,
+                                    max_iters)
+        return sol, it, rr

@@ -203,3 +203,95 @@ def test_empty_batch_is_a_no_op(ctx):
     ctx.skeleton_scatter(db, z, z, z, z, zi, zi, zi, zi, 1, z, z, zi, zi)
     ctx.reconstruct(db, z, zi, zi, z, 1, z, zi)
     ctx.sync()
+
+
+# ------------------------------------------------------------ skeleton solve
+def _gpu_system(ctx, N, s, l, m, kfun, prec=0):
+    from paper_1703_10435_amd import engine
+    from paper_1703_10435_amd.skeleton import SkeletonSystem
+    mesh = coarse_mesh(N)
+    E = mesh["elems"].shape[0]
+    b = configs.build_batch(mesh, np.arange(E), np.full(E, s), np.full(E, l), kfun, manufactured_source,
+                            m_arr=np.full(E, m))
+    res, out, db = engine.solve_batch(b, prec=prec, mode="fused", ctx=ctx)
+    sk = SkeletonSystem(mesh, l, p_max=db.p_max, m=m)
+    vals, rhs, missing = sk.scatter(ctx, db, out)
+    return mesh, b, out, db, sk, vals, rhs
+
+
+@pytest.mark.parametrize("N,s,l,m", [(4, 8, 1, 1), (4, 6, 2, 1), (3, 6, 0, 3), (4, 8, 1, 2), (8, 4, 1, 1)])
+def test_skeleton_solve_matches_oracle(ctx, N, s, l, m):
+    """MINRES on the device-assembled system against the oracle's dense
+    solve of its own assembly: u_0 and lambda within 10 cond(K) times the
+    assembly and solve tolerances, the true residual below 1e-10."""
+    mesh, b, out, db, sk, vals, rhs = _gpu_system(ctx, N, s, l, m, _rough_k)
+    say(f"[gpu] skeleton solve N={N} s={s} l={l} m={m} rows={sk.n_rows}")
+    sol, it, rr = sk.solve(ctx, vals, rhs, tol=1e-13)
+    ctx.sync()
+    say(f"  {it} MINRES steps, relative residual {rr:.2e}")
+    assert rr < 1e-10
+    ora = local.solve_batch(b)
+    lam, u0, K, rhs_o = oskel.reduce_and_solve(mesh, ora, np.arange(b["n_elem"]), l, m)
+    kappa = np.linalg.cond(K)
+    x = sol.cpu().numpy()
+    want = np.concatenate([lam, u0])
+    bound = 10.0 * kappa * (2 * TOL[0] + 1e-13)
+    err = np.abs(x - want).max() / np.abs(want).max()
+    say(f"  cond {kappa:.2e}, max rel err {err:.2e} (bound {bound:.2e})")
+    assert err <= bound
+
+
+def test_skeleton_solve_singular_multiplier_block(ctx):
+    """l = s: the multiplier block is rank deficient; u (through the
+    reconstruction) is still unique and matches the oracle."""
+    N, s, l = 2, 2, 2
+    mesh, b, out, db, sk, vals, rhs = _gpu_system(ctx, N, s, l, 1, _rough_k)
+    say("[gpu] skeleton solve, singular multiplier block")
+    sol, it, rr = sk.solve(ctx, vals, rhs, tol=1e-13)
+    u = sk.reconstruct(ctx, db, out, sol)
+    ctx.sync()
+    assert rr < 1e-9, rr
+    ora = local.solve_batch(b)
+    lam, u0, K, _ = oskel.reduce_and_solve(mesh, ora, np.arange(b["n_elem"]), l)
+    want = oskel.reconstruct(mesh, ora, np.arange(b["n_elem"]), l, lam, u0)
+    u = u.cpu().numpy()
+    scale = max(np.abs(w).max() for w in want)
+    for e in range(b["n_elem"]):
+        assert np.abs(u[db.node_off[e]:db.node_off[e + 1]] - want[e]).max() <= 1e-8 * scale, e
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_device_chain_converges_at_second_order(ctx, prec):
+    """Every step on the device: local solves, scatter, MINRES, reconstruction."""
+    errs, its = [], []
+    for N in (2, 4, 8, 16):
+        mesh, b, out, db, sk, vals, rhs = _gpu_system(ctx, N, 4, 1, 1, _ones, prec)
+        say(f"[gpu] device chain N={N} prec={prec}")
+        sol, it, rr = sk.solve(ctx, vals, rhs, tol=1e-12)
+        u = sk.reconstruct(ctx, db, out, sol)
+        ctx.sync()
+        assert rr < 1e-9
+        its.append(it)
+        u = u.cpu().numpy()
+        errs.append(oskel.l2_error(b, [u[db.node_off[e]:db.node_off[e + 1]] for e in range(b["n_elem"])],
+                                   manufactured_solution))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    say(f"  errors {errs} rates {rates} MINRES steps {its}")
+    assert np.all((rates > 1.8) & (rates < 2.3)), (errs, rates)
+
+
+def test_skeleton_solve_edge_cases(ctx):
+    import torch
+    from paper_1703_10435_amd import abi
+    mesh, b, out, db, sk, vals, rhs = _gpu_system(ctx, 2, 3, 1, 1, _ones)
+    say("[gpu] skeleton solve edge cases")
+    sol, it, rr = sk.solve(ctx, vals, torch.zeros_like(rhs))
+    ctx.sync()
+    assert it == 0 and rr == 0.0 and not torch.any(sol != 0).item()
+    bad = sk.col_idx.clone()
+    bad[5] = sk.n_rows + 3
+    sol = torch.empty(sk.n_rows, dtype=torch.float64, device="cuda")
+    with pytest.raises(abi.MhmError, match="out of range"):
+        ctx.skeleton_solve(sk.n_rows, sk.n_lambda, sk.row_ptr, bad, vals, rhs, sol)
+    it, rr = ctx.skeleton_solve(0, 0, None, None, None, None, None)
+    assert it == 0
