@@ -228,22 +228,22 @@ __device__ __forceinline__ int potrf_tile(T* t, T* Lo, int n, int k, int lane) {
 // Broadcast lane `src` of each 16-lane row to the whole row (DPP row_newbcast).
 __device__ __forceinline__ int row_bcast_i(int x, int src) {
   switch (src) {
-    case 0: return __builtin_amdgcn_update_dpp(0, x, 0x150, 0xF, 0xF, false);
-    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x151, 0xF, 0xF, false);
-    case 2: return __builtin_amdgcn_update_dpp(0, x, 0x152, 0xF, 0xF, false);
-    case 3: return __builtin_amdgcn_update_dpp(0, x, 0x153, 0xF, 0xF, false);
-    case 4: return __builtin_amdgcn_update_dpp(0, x, 0x154, 0xF, 0xF, false);
-    case 5: return __builtin_amdgcn_update_dpp(0, x, 0x155, 0xF, 0xF, false);
-    case 6: return __builtin_amdgcn_update_dpp(0, x, 0x156, 0xF, 0xF, false);
-    case 7: return __builtin_amdgcn_update_dpp(0, x, 0x157, 0xF, 0xF, false);
-    case 8: return __builtin_amdgcn_update_dpp(0, x, 0x158, 0xF, 0xF, false);
-    case 9: return __builtin_amdgcn_update_dpp(0, x, 0x159, 0xF, 0xF, false);
-    case 10: return __builtin_amdgcn_update_dpp(0, x, 0x15A, 0xF, 0xF, false);
-    case 11: return __builtin_amdgcn_update_dpp(0, x, 0x15B, 0xF, 0xF, false);
-    case 12: return __builtin_amdgcn_update_dpp(0, x, 0x15C, 0xF, 0xF, false);
-    case 13: return __builtin_amdgcn_update_dpp(0, x, 0x15D, 0xF, 0xF, false);
-    case 14: return __builtin_amdgcn_update_dpp(0, x, 0x15E, 0xF, 0xF, false);
-    default: return __builtin_amdgcn_update_dpp(0, x, 0x15F, 0xF, 0xF, false);
+    case 0: return __builtin_amdgcn_mov_dpp(x, 0x150, 0xF, 0xF, true);
+    case 1: return __builtin_amdgcn_mov_dpp(x, 0x151, 0xF, 0xF, true);
+    case 2: return __builtin_amdgcn_mov_dpp(x, 0x152, 0xF, 0xF, true);
+    case 3: return __builtin_amdgcn_mov_dpp(x, 0x153, 0xF, 0xF, true);
+    case 4: return __builtin_amdgcn_mov_dpp(x, 0x154, 0xF, 0xF, true);
+    case 5: return __builtin_amdgcn_mov_dpp(x, 0x155, 0xF, 0xF, true);
+    case 6: return __builtin_amdgcn_mov_dpp(x, 0x156, 0xF, 0xF, true);
+    case 7: return __builtin_amdgcn_mov_dpp(x, 0x157, 0xF, 0xF, true);
+    case 8: return __builtin_amdgcn_mov_dpp(x, 0x158, 0xF, 0xF, true);
+    case 9: return __builtin_amdgcn_mov_dpp(x, 0x159, 0xF, 0xF, true);
+    case 10: return __builtin_amdgcn_mov_dpp(x, 0x15A, 0xF, 0xF, true);
+    case 11: return __builtin_amdgcn_mov_dpp(x, 0x15B, 0xF, 0xF, true);
+    case 12: return __builtin_amdgcn_mov_dpp(x, 0x15C, 0xF, 0xF, true);
+    case 13: return __builtin_amdgcn_mov_dpp(x, 0x15D, 0xF, 0xF, true);
+    case 14: return __builtin_amdgcn_mov_dpp(x, 0x15E, 0xF, 0xF, true);
+    default: return __builtin_amdgcn_mov_dpp(x, 0x15F, 0xF, 0xF, true);
   }
 }
 __device__ __forceinline__ double row_bcast(double x, int src) {
@@ -281,6 +281,7 @@ __device__ __forceinline__ int potrf_c(T* t, T* Lo, int n, int k, int lane, T* L
   for (int j = 0; j < 16; ++j) {
     const int gj = j & 3, vj = j >> 2;          // lane group / item holding row j
     const T ajc = __shfl(a[vj], c + 16 * gj, 64);    // a[j][c]
+    const T wv = __shfl(w[vj], c + 16 * gj, 64);     // V[j][c]
     T ajj = readlane(a[vj], j + 16 * gj);           // a[j][j]
     if (!(ajj > T(0))) {
       if (bad < 0) bad = j;
@@ -288,18 +289,20 @@ __device__ __forceinline__ int potrf_c(T* t, T* Lo, int n, int k, int lane, T* L
     }
     const T rs = rsqrt_t(ajj);
     if (c == j) myrs = rs;
-    const T inv = rs * rs;
-    const T wjc = __shfl(w[vj], c + 16 * gj, 64) * rs;   // W[j][c]
+    const T wjc = wv * rs;                           // W[j][c]
+    const T f = ajc * (rs * rs);
+    const bool cgt = c > j;
+    // items whose four rows are all above row j are final (static test);
+    // the rest are updated by selects
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
+      if (4 * v + 3 < j) continue;
       const int r = g + 4 * v;
       const T arj = row_bcast(a[v], j);      // a[r][j]
-      if (r > j) {
-        w[v] -= arj * rs * wjc;
-        if (c > j) a[v] -= arj * ajc * inv;
-      } else if (r == j) {
-        w[v] = wjc;
-      }
+      const T wu = w[v] - arj * rs * wjc;
+      const T au = a[v] - arj * f;
+      w[v] = r > j ? wu : (r == j ? wjc : w[v]);
+      a[v] = (r > j && cgt) ? au : a[v];
     }
   }
 #pragma unroll

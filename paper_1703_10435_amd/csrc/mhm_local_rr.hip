@@ -64,22 +64,22 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 // must fold to a constant).
 __device__ __forceinline__ int row_bcast_i(int x, int src) {
   switch (src) {
-    case 0: return __builtin_amdgcn_update_dpp(0, x, 0x150, 0xF, 0xF, false);
-    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x151, 0xF, 0xF, false);
-    case 2: return __builtin_amdgcn_update_dpp(0, x, 0x152, 0xF, 0xF, false);
-    case 3: return __builtin_amdgcn_update_dpp(0, x, 0x153, 0xF, 0xF, false);
-    case 4: return __builtin_amdgcn_update_dpp(0, x, 0x154, 0xF, 0xF, false);
-    case 5: return __builtin_amdgcn_update_dpp(0, x, 0x155, 0xF, 0xF, false);
-    case 6: return __builtin_amdgcn_update_dpp(0, x, 0x156, 0xF, 0xF, false);
-    case 7: return __builtin_amdgcn_update_dpp(0, x, 0x157, 0xF, 0xF, false);
-    case 8: return __builtin_amdgcn_update_dpp(0, x, 0x158, 0xF, 0xF, false);
-    case 9: return __builtin_amdgcn_update_dpp(0, x, 0x159, 0xF, 0xF, false);
-    case 10: return __builtin_amdgcn_update_dpp(0, x, 0x15A, 0xF, 0xF, false);
-    case 11: return __builtin_amdgcn_update_dpp(0, x, 0x15B, 0xF, 0xF, false);
-    case 12: return __builtin_amdgcn_update_dpp(0, x, 0x15C, 0xF, 0xF, false);
-    case 13: return __builtin_amdgcn_update_dpp(0, x, 0x15D, 0xF, 0xF, false);
-    case 14: return __builtin_amdgcn_update_dpp(0, x, 0x15E, 0xF, 0xF, false);
-    default: return __builtin_amdgcn_update_dpp(0, x, 0x15F, 0xF, 0xF, false);
+    case 0: return __builtin_amdgcn_mov_dpp(x, 0x150, 0xF, 0xF, true);
+    case 1: return __builtin_amdgcn_mov_dpp(x, 0x151, 0xF, 0xF, true);
+    case 2: return __builtin_amdgcn_mov_dpp(x, 0x152, 0xF, 0xF, true);
+    case 3: return __builtin_amdgcn_mov_dpp(x, 0x153, 0xF, 0xF, true);
+    case 4: return __builtin_amdgcn_mov_dpp(x, 0x154, 0xF, 0xF, true);
+    case 5: return __builtin_amdgcn_mov_dpp(x, 0x155, 0xF, 0xF, true);
+    case 6: return __builtin_amdgcn_mov_dpp(x, 0x156, 0xF, 0xF, true);
+    case 7: return __builtin_amdgcn_mov_dpp(x, 0x157, 0xF, 0xF, true);
+    case 8: return __builtin_amdgcn_mov_dpp(x, 0x158, 0xF, 0xF, true);
+    case 9: return __builtin_amdgcn_mov_dpp(x, 0x159, 0xF, 0xF, true);
+    case 10: return __builtin_amdgcn_mov_dpp(x, 0x15A, 0xF, 0xF, true);
+    case 11: return __builtin_amdgcn_mov_dpp(x, 0x15B, 0xF, 0xF, true);
+    case 12: return __builtin_amdgcn_mov_dpp(x, 0x15C, 0xF, 0xF, true);
+    case 13: return __builtin_amdgcn_mov_dpp(x, 0x15D, 0xF, 0xF, true);
+    case 14: return __builtin_amdgcn_mov_dpp(x, 0x15E, 0xF, 0xF, true);
+    default: return __builtin_amdgcn_mov_dpp(x, 0x15F, 0xF, 0xF, true);
   }
 }
 __device__ __forceinline__ double bcast16(double x, int src) {
@@ -136,6 +136,8 @@ __device__ __forceinline__ int potrf_inv(double* t, double* Lo, int n, int k, in
     const int gj = j & 3, vj = j >> 2;          // lane group / item holding row j
     // row j of the current matrix, seen from column c: a[j][c] (lane (c, gj), item vj)
     const double ajc = __shfl(a[vj], c + 16 * gj, 64);
+    // V row j (before scaling): lane (c, gj), item vj
+    const double wv = __shfl(w[vj], c + 16 * gj, 64);
     double ajj = readlane_d(a[vj], j + 16 * gj);   // pivot a[j][j]
     if (!(ajj > 0.0)) {
       if (bad < 0) bad = j;
@@ -143,19 +145,20 @@ __device__ __forceinline__ int potrf_inv(double* t, double* Lo, int n, int k, in
     }
     const double rs = rsqrt_nr(ajj);
     if (c == j) myrs = rs;
-    const double inv = rs * rs;
-    // W row j: W[j][c] = V[j][c] / sqrt(ajj) (lane (c, gj), item vj)
-    const double wjc = __shfl(w[vj], c + 16 * gj, 64) * rs;
+    const double wjc = wv * rs;                    // W[j][c]
+    const double f = ajc * (rs * rs);
+    const bool cgt = c > j;
+    // items whose four rows are all above row j are final: skipped (a
+    // static test, so the step shrinks as j grows); the rest by selects
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
+      if (4 * v + 3 < j) continue;
       const int r = g + 4 * v;
       const double arj = bcast16(a[v], j);      // a[r][j]
-      if (r > j) {
-        w[v] -= arj * rs * wjc;
-        if (c > j) a[v] -= arj * ajc * inv;
-      } else if (r == j) {
-        w[v] = wjc;
-      }
+      const double wu = w[v] - arj * rs * wjc;
+      const double au = a[v] - arj * f;
+      w[v] = r > j ? wu : (r == j ? wjc : w[v]);
+      a[v] = (r > j && cgt) ? au : a[v];
     }
   }
   // column c of L is a[.][c] * myrs for rows >= c (entries above stay as read)
