@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
   __shared__ double colsum[16];
   __shared__ double cx[16];
   __shared__ double gam;
-  extern __shared__ double dyn[];      // c | bf | ft | kap | stencil[8 n] | P[NT] | W[NT] | R[NT]
+  extern __shared__ double dyn[];      // c | bf | ft | kap | stencil[8][n] | P[NT] | W[NT] | R[NT]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int NImax = nimax(b);
 
@@ -210,7 +210,8 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
   double* bf = c + args.n_cap;
   double* ft = bf + args.n_cap;
   double* kapl = ft + args.f_cap;
-  double* stt = kapl + args.k_cap;     // per node: d e w n s nw se, row j (fused)
+  double* stt = kapl + args.k_cap;     // node tables, entry k of node p at k n_cap + p (fused): the
+                                       // stencil d e w n s nw se, then 256 j + i
   double* P = stt + 8 * args.n_cap;    // panel column L_ik
   double* Wb = P + NT * TILE;          // inverses of the diagonal tiles
   double* Rb = Wb + NT * TILE;         // right-hand-side row: tile J holds Z_J^T
@@ -283,9 +284,10 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
         cc2 += cp * cp;
         if (FUSED) {
           const Stencil st = stencil(i, j, s, E.G, kap);
-          double* sp = stt + 8 * p;
-          sp[0] = st.d; sp[1] = st.e; sp[2] = st.w; sp[3] = st.n;
-          sp[4] = st.so; sp[5] = st.nw; sp[6] = st.se; sp[7] = (double)j;
+          const int NC = args.n_cap;
+          double* sp = stt + p;
+          sp[0] = st.d; sp[NC] = st.e; sp[2 * NC] = st.w; sp[3 * NC] = st.n;
+          sp[4 * NC] = st.so; sp[5 * NC] = st.nw; sp[6 * NC] = st.se; sp[7 * NC] = (double)(256 * j + i);
           tr += st.d;
           const double bp = E.cunit * node_tri_sum(i, j, s, [&](int t) { return fp[t]; });
           bf[p] = bp;
@@ -324,9 +326,11 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
             double sd = 0, se_ = 0, sw = 0, sn = 0, ss = 0, snw = 0, sse = 0;
             int qj = 0;
             if (band && q < n) {
-              const double* sp = stt + 8 * q;
-              sd = sp[0]; se_ = sp[1]; sw = sp[2]; sn = sp[3]; ss = sp[4]; snw = sp[5]; sse = sp[6];
-              qj = (int)sp[7];
+              const int NC = args.n_cap;
+              const double* sp = stt + q;
+              sd = sp[0]; se_ = sp[NC]; sw = sp[2 * NC]; sn = sp[3 * NC]; ss = sp[4 * NC]; snw = sp[5 * NC];
+              sse = sp[6 * NC];
+              qj = (int)sp[7 * NC] >> 8;
             }
             const int pE = q + 1, pW = q - 1, pN = q + (s + 1 - qj), pS = q - (s + 2 - qj), pNW = q + (s - qj),
                       pSE = q - (s + 1 - qj);
@@ -370,8 +374,8 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
         double x = 0.0;
         if (a < r && q < n) {
           if (FUSED) {
-            int qi, qj;
-            node_ij(q, s, qi, qj);
+            const int code = (int)stt[7 * args.n_cap + q];
+            const int qi = code & 255, qj = code >> 8;
             double base = 0.0;
             if (a < E.NI) {
               const int ef = a / E.P;
@@ -444,9 +448,14 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
         }
       }
       if (mine) {
+        // the diagonal factorisation is the critical path of the step: the
+        // wave runs it at raised issue priority over the other workgroup's
+        // waves on its SIMD
+        __builtin_amdgcn_s_setprio(3);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const int bj = rr::potrf_inv(Wt(k + 1), Lo, n, k + 1, lane);
         if (lane == 0 && bj >= 0 && bad < 0) bad = 16 * (k + 1) + bj;
+        __builtin_amdgcn_s_setprio(0);
       }
       if (k >= 0) {
 #pragma unroll
