@@ -394,6 +394,16 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
             if (idx < pw * TILE) st[idx] = sv[q];
           }
           __syncthreads();
+          // B operands (the staged tiles L_jm): in FP32 read once and used by
+          // every row (registers to spare); in FP64 read per row
+          constexpr bool HOIST = sizeof(T) == 4;
+          T bo[PW][4];
+          if constexpr (HOIST) {
+#pragma unroll
+            for (int jj = 0; jj < PW; ++jj)
+#pragma unroll
+              for (int cch = 0; cch < 4; ++cch) bo[jj][cch] = ld_rowcol(st + jj * TILE, cch, lane);
+          }
 #pragma unroll
           for (int ri = 0; ri < RPW; ++ri) {
             const int i = j0 + wave + NW * ri;
@@ -404,7 +414,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
                   V4 x = acc[ri][jj];
 #pragma unroll
                   for (int cch = 0; cch < 4; ++cch)
-                    x = Mfma<T>::op(-a[ri][cch], ld_rowcol(st + jj * TILE, cch, lane), x);
+                    x = Mfma<T>::op(-a[ri][cch], HOIST ? bo[jj][cch] : ld_rowcol(st + jj * TILE, cch, lane), x);
                   acc[ri][jj] = x;
                 }
               }
