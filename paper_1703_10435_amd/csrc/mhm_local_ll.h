@@ -26,6 +26,23 @@ namespace mhm {
 
 namespace ll {
 
+// Operand chunks of a stored tile for the earlier-column updates, with the
+// contraction index of chunk c in lane group g taken as k = 4 g + c (the
+// same for both operands, so the product is unchanged): the four values of
+// a lane are adjacent in memory and come in one vector load (4-byte
+// aligned; the tile rows are 17 wide).
+template <typename T> struct Vec4U;
+template <> struct Vec4U<float> { typedef float t __attribute__((ext_vector_type(4), aligned(4))); };
+template <> struct Vec4U<double> { typedef double t __attribute__((ext_vector_type(4), aligned(8))); };
+template <typename T>
+__device__ __forceinline__ void ld_row4(const T* t, int lane, T (&o)[4]) {
+  const typename Vec4U<T>::t v = *reinterpret_cast<const typename Vec4U<T>::t*>(t + (lane & 15) * TST + 4 * (lane >> 4));
+  o[0] = v[0];
+  o[1] = v[1];
+  o[2] = v[2];
+  o[3] = v[3];
+}
+
 // One block triangular sweep over the right-hand-side tile row of the factor
 // (tiles tl(nt, i) hold Z_i^T, 16 right-hand sides by 16 nodes; the diagonal
 // tiles tl(j, j) hold W_j = L_jj^{-1}):
@@ -374,11 +391,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
 #pragma unroll
           for (int ri = 0; ri < RPW; ++ri) {
             const int i = j0 + wave + NW * ri;
-            if (i <= nt) {
-              const T* L = tl(i, m);
-#pragma unroll
-              for (int cch = 0; cch < 4; ++cch) a[ri][cch] = ld_rowcol(L, cch, lane);
-            }
+            if (i <= nt) ll::ld_row4(tl(i, m), lane, a[ri]);
           }
 #pragma unroll
           for (int q = 0; q < SPT; ++q) {
@@ -400,9 +413,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
           T bo[PW][4];
           if constexpr (HOIST) {
 #pragma unroll
-            for (int jj = 0; jj < PW; ++jj)
-#pragma unroll
-              for (int cch = 0; cch < 4; ++cch) bo[jj][cch] = ld_rowcol(st + jj * TILE, cch, lane);
+            for (int jj = 0; jj < PW; ++jj) ll::ld_row4(st + jj * TILE, lane, bo[jj]);
           }
 #pragma unroll
           for (int ri = 0; ri < RPW; ++ri) {
@@ -414,7 +425,8 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
                   V4 x = acc[ri][jj];
 #pragma unroll
                   for (int cch = 0; cch < 4; ++cch)
-                    x = Mfma<T>::op(-a[ri][cch], HOIST ? bo[jj][cch] : ld_rowcol(st + jj * TILE, cch, lane), x);
+                    x = Mfma<T>::op(-a[ri][cch],
+                                    HOIST ? bo[jj][cch] : st[jj * TILE + (lane & 15) * TST + 4 * (lane >> 4) + cch], x);
                   acc[ri][jj] = x;
                 }
               }
