@@ -88,9 +88,16 @@ __device__ __forceinline__ void sweep_body(T* Lb, T* rhs_row, int nt, T* xb, T* 
     for (int ri = 0; ri < RPW; ++ri) {
       const int i = wave + NW * ri;
       if (upd(i, j)) {
-        const T* L = BACK ? tl(j, i) : tl(i, j);
+        // forward: rows of L_ij, one vector load per lane (contraction index
+        // 4 (l / 16) + c, matched in the A operand below); backward: columns
+        // of L_ji, element loads
+        if (BACK) {
+          const T* L = tl(j, i);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) b[ri][c] = BACK ? ld_colrow(L, c, lane) : ld_rowcol(L, c, lane);
+          for (int c = 0; c < 4; ++c) b[ri][c] = ld_colrow(L, c, lane);
+        } else {
+          ld_row4(tl(i, j), lane, b[ri]);
+        }
       }
     }
     if (st + 1 < nt && wave == colj(st + 1) % NW) ld_w(colj(st + 1), w);
@@ -126,7 +133,8 @@ __device__ __forceinline__ void sweep_body(T* Lb, T* rhs_row, int nt, T* xb, T* 
     T* xn = xb + ((st + 1) & 1) * TILE;
     T a[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a[c] = -ld_rowcol(xj, c, lane);
+    for (int c = 0; c < 4; ++c)
+      a[c] = BACK ? -ld_rowcol(xj, c, lane) : -xj[(lane & 15) * TST + 4 * (lane >> 4) + c];
 #pragma unroll
     for (int ri = 0; ri < RPW; ++ri) {
       const int i = wave + NW * ri;
