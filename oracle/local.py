@@ -128,21 +128,18 @@ def face_length(vert6, e):
     return float(np.hypot(*(b - a)))
 
 
-def _legendre_in_tau(q: int, flip: int, m: int = 1, seg: int = 0) -> Polynomial:
-    """P_q(t) of segment `seg` of an m-partition of the face, as a polynomial
-    in the local face parameter tau in [0, 1].  Segments and t run along the
-    global orientation (from the lower global vertex id): with the global
-    parameter g = tau (or 1 - tau when the local direction runs high ->
-    low), segment seg is g in [seg/m, (seg+1)/m] and t = 2 (m g - seg) - 1."""
-    pq = Polynomial(npleg.leg2poly([0] * q + [1]))
-    g_of_tau = Polynomial([1.0, -1.0]) if flip else Polynomial([0.0, 1.0])
-    return pq(2.0 * (m * g_of_tau - seg) - 1.0)
+def _t_at(k: int, s: int, flip: int, m: int, seg: int) -> float:
+    """The segment variable t in [-1, 1] of segment `seg` (global
+    orientation) at the face node at local position k of s: with the global
+    parameter g = k/s (or 1 - k/s when the local direction runs high -> low),
+    t = 2 (m g - seg) - 1, formed from integers and rounded once."""
+    kk = s - k if flip else k
+    return 2.0 * (m * kk - seg * s) / s - 1.0
 
 
-def _segment_tau(flip: int, m: int, seg: int):
-    """The tau interval of global segment `seg`."""
-    g0, g1 = seg / m, (seg + 1) / m
-    return (1.0 - g1, 1.0 - g0) if flip else (g0, g1)
+def _segment_of(k: int, s: int, flip: int, m: int) -> int:
+    """Global segment holding local sub-edge k (between face nodes k and k+1)."""
+    return (s - 1 - k if flip else k) // (s // m)
 
 
 def face_dof(e: int, seg: int, q: int, l: int, m: int = 1) -> int:
@@ -155,42 +152,44 @@ def face_loads(vert6, s, l, sigma, flip, m: int = 1):
     """R[:, face_dof(e, seg, q)] = -sigma_e * integral over F_e of psi phi_j ds
     (eq. (9) right-hand side) for the discontinuous face space of Section 2
     with m segments per face (m must divide s, so that every sub-edge lies
-    in one segment), integrated exactly on each of the s sub-edges."""
+    in one segment), integrated exactly on each of the s sub-edges.  On a
+    sub-edge the integrand is written in the sub-edge variable u in [0, 1]
+    (hats 1 - u and u, P_q(t) with t linear in u), so every polynomial that
+    is integrated has coefficients of order one."""
     if s % m:
         raise ValueError("m must divide s")
     n = (s + 1) * (s + 2) // 2
     NI = 3 * m * (l + 1)
     R = np.zeros((n, NI))
+    u = Polynomial([0.0, 1.0])
     for e in range(3):
         L = face_length(vert6, e)
         nodes = face_nodes(e, s)
-        for seg in range(m):
-            lo, hi = _segment_tau(int(flip[e]), m, seg)
+        fl = int(flip[e])
+        for k in range(s):
+            seg = _segment_of(k, s, fl, m)
+            ta, tb = _t_at(k, s, fl, m, seg), _t_at(k + 1, s, fl, m, seg)
+            t_of_u = Polynomial([ta, tb - ta])
             for q in range(l + 1):
-                P = _legendre_in_tau(q, int(flip[e]), m, seg)
-                for k in range(s):
-                    t0, t1 = k / s, (k + 1) / s
-                    if t0 < lo - 1e-12 or t1 > hi + 1e-12:
-                        continue                       # sub-edge outside the segment
-                    left = Polynomial([t1, -1.0]) * s      # hat of node k on [t0, t1]
-                    right = Polynomial([-t0, 1.0]) * s     # hat of node k+1
-                    for node, hat in ((nodes[k], left), (nodes[k + 1], right)):
-                        anti = (P * hat).integ()
-                        R[node, face_dof(e, seg, q, l, m)] += -float(sigma[e]) * L * (anti(t1) - anti(t0))
+                P = Polynomial(npleg.leg2poly([0] * q + [1]))(t_of_u)
+                for node, hat in ((nodes[k], 1.0 - u), (nodes[k + 1], u)):
+                    anti = (P * hat).integ()
+                    # d(arc length) = (L / s) du
+                    R[node, face_dof(e, seg, q, l, m)] += -float(sigma[e]) * (L / s) * (anti(1.0) - anti(0.0))
     return R
 
 
 def face_moments(vert6, l, sigma, flip, m: int = 1):
-    """B_j = (sigma psi_j, 1)_{dK}: integral of the signed face polynomial."""
+    """B_j = (sigma psi_j, 1)_{dK}: integral of the signed face polynomial
+    over its segment (length |F_e| / m; ds = |F_e| / (2 m) dt)."""
     NI = 3 * m * (l + 1)
     Bv = np.zeros(NI)
     for e in range(3):
         L = face_length(vert6, e)
         for seg in range(m):
-            lo, hi = _segment_tau(int(flip[e]), m, seg)
             for q in range(l + 1):
-                anti = _legendre_in_tau(q, int(flip[e]), m, seg).integ()
-                Bv[face_dof(e, seg, q, l, m)] = float(sigma[e]) * L * (anti(hi) - anti(lo))
+                anti = Polynomial(npleg.leg2poly([0] * q + [1])).integ()
+                Bv[face_dof(e, seg, q, l, m)] = float(sigma[e]) * L / (2.0 * m) * (anti(1.0) - anti(-1.0))
     return Bv
 
 

@@ -207,6 +207,80 @@ def test_segmented_face_loads_against_gauss_quadrature(s, l, m):
                     assert Bv[a] == pytest.approx(wantB, abs=1e-13)
 
 
+def _exact_segment_integrals(s, l, m, flip):
+    """Exact rational values of int_{sub-edge k} P_q(t) phi ds / (ds/dtau)
+    for both end nodes of every sub-edge, written directly in the face
+    parameter tau in [0, 1] (power basis in tau, the form that loses
+    digits in floating point for the far segments of a fine face), with
+    P_q from the three-term recurrence in exact arithmetic.
+    Returns {(k_node, seg, q): value} for one face of orientation `flip`."""
+    from fractions import Fraction as Fr
+
+    def mul(a, b):
+        out = [Fr(0)] * (len(a) + len(b) - 1)
+        for i, x in enumerate(a):
+            for j, y in enumerate(b):
+                out[i + j] += x * y
+        return out
+
+    def add(a, b):
+        n = max(len(a), len(b))
+        return [(a[i] if i < len(a) else 0) + (b[i] if i < len(b) else 0) for i in range(n)]
+
+    def integ(a, lo, hi):
+        return sum(c * (hi ** (j + 1) - lo ** (j + 1)) / (j + 1) for j, c in enumerate(a))
+
+    per = s // m
+    out = {}
+    for seg in range(m):
+        # t(tau) = 2 (m g - seg) - 1 with g = tau or 1 - tau
+        t_lin = [Fr(2 * m - 2 * seg - 1), Fr(-2 * m)] if flip else [Fr(-2 * seg - 1), Fr(2 * m)]
+        P = [[Fr(1)], t_lin]
+        for k in range(1, l):
+            P.append([c / (k + 1) for c in add([Fr(2 * k + 1) * x for x in mul(t_lin, P[k])],
+                                                [Fr(-k) * x for x in P[k - 1]])])
+        for k in range(s):
+            if (s - 1 - k if flip else k) // per != seg:
+                continue
+            t0, t1 = Fr(k, s), Fr(k + 1, s)
+            left = [t1 * s, Fr(-s)]       # hat of node k on [t0, t1]
+            right = [-t0 * s, Fr(s)]      # hat of node k + 1
+            for q in range(l + 1):
+                for node, hat in ((k, left), (k + 1, right)):
+                    out[(node, seg, q)] = out.get((node, seg, q), Fr(0)) + integ(mul(P[q], hat), t0, t1)
+    return out
+
+
+@pytest.mark.parametrize("s,l,m", [(48, 4, 4), (48, 3, 8), (36, 4, 6), (64, 2, 16)])
+def test_segmented_face_loads_match_exact_rational_integrals(s, l, m):
+    """Fine faces with many segments and high degree: every entry of R and
+    B against the exact rational integrals (times -sigma |F_e| and sigma
+    |F_e|), to a few units of the last place of the column scale.  An
+    evaluation that cancels (a power basis in the face parameter on the far
+    segments) is off by orders of magnitude more here."""
+    from fractions import Fraction as Fr
+    rng = np.random.default_rng(70 + s + m)
+    v, s, l, sg, fl, kap, f = _rand_element(rng, s, l)
+    fl = np.array([0, 1, 0], dtype=np.int8)      # both orientations
+    R = local.face_loads(v, s, l, sg, fl, m)
+    Bv = local.face_moments(v, l, sg, fl, m)
+    for e in range(3):
+        L = local.face_length(v, e)
+        nodes = local.face_nodes(e, s)
+        ex = _exact_segment_integrals(s, l, m, int(fl[e]))
+        want = np.zeros((R.shape[0], m * (l + 1)))
+        for (k, seg, q), val in ex.items():
+            want[nodes[k], seg * (l + 1) + q] = -float(sg[e]) * L * float(val)
+        got = R[:, e * m * (l + 1):(e + 1) * m * (l + 1)]
+        scale = np.abs(want).max(axis=0)
+        assert np.all(np.abs(got - want) <= 4e-16 * 8 * scale), np.abs(got - want).max(axis=0) / scale
+        for seg in range(m):
+            for q in range(l + 1):
+                exact_b = Fr(1, m) if q == 0 else Fr(0)      # int over the segment of P_q d tau
+                assert Bv[(e * m + seg) * (l + 1) + q] == pytest.approx(float(sg[e]) * L * float(exact_b),
+                                                                        abs=4e-16 * L)
+
+
 @pytest.mark.parametrize("s,l,m", [(4, 1, 2), (6, 0, 3), (8, 1, 2)])
 def test_whole_face_space_is_inside_the_segmented_one(s, l, m):
     """Lambda^{1,l} lies inside Lambda^{m,l}: P_q on the whole face is a
