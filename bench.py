@@ -35,7 +35,7 @@ WORKLOAD = ("C2: plain FP64 batched, 32x32x2=2048 coarse triangles, s=16 (153 P1
 
 def _flops_per_element(n, r):
     """Algorithmic flops of the dense method: Cholesky n^3/3 + forward and
-    backward solves 2 n^2 r (the SURVEY's per-element count)."""
+    backward solves 2 n^2 r per element."""
     n = np.asarray(n, dtype=np.float64)
     r = np.asarray(r, dtype=np.float64)
     return n ** 3 / 3.0 + 2.0 * n * n * r
@@ -182,6 +182,45 @@ def _batched_leg(torch, ctx, name, sample_per_size, checks, reps=3):
     leg["fp32_ir_batched_vs_plain_fp64"] = ms3 / leg["fp32_ir_graph_ms"]
     leg["sample"] = f"{len(idx)} elements ({sample_per_size} per s) against the FP64 oracle"
     del outs, subs, db
+    torch.cuda.empty_cache()
+    return leg
+
+
+def _wide_leg(torch, ctx, checks, m=4, reps=3):
+    """The C3 workload (s = 32, l = 3) with a richer multiplier space: m
+    segments of degree l per face, N_I = 3 m (l + 1) face right-hand sides
+    per factor (49 in all for m = 4, in four 16-column chunks) instead of
+    C3's 13.  The factorisation is the same; the solves grow with r."""
+    from mhm_inputs import configs
+    from paper_1703_10435_amd import abi, engine
+    from paper_1703_10435_amd.batch import DeviceBatch
+    b = configs.make("C3")
+    E = b["n_elem"]
+    b["m"] = np.full(E, m, dtype=np.int32)
+    db = DeviceBatch(b)
+    s = int(b["s"][0])
+    n, r = (s + 1) * (s + 2) // 2, int(db.r[0])
+    idx = np.random.default_rng(10).choice(E, size=3, replace=False)
+    leg = {"n_elem": E, "s": s, "l": int(b["l"][0]), "m": m, "n": n, "r": r}
+    for prec, tag in ((abi.MHM_FP32_IR, "fp32_ir"), (abi.MHM_FP64, "fp64")):
+        o = db.alloc_outputs(three_call=False)
+        engine.autotune(ctx, db, prec, o)
+        g, go = engine.capture_fused(ctx, db, prec)
+        ms = _ms(torch, g.launch, reps)
+        g.close()
+        info = go["info"].cpu().numpy()[:E]
+        leg[f"{tag}_graph_ms"] = ms
+        leg[f"{tag}_graph_problems_per_s"] = E / (ms * 1e-3)
+        leg[f"{tag}_rhs_columns_per_s"] = E * r / (ms * 1e-3)
+        leg[f"{tag}_algorithmic_tflops"] = E * float(_flops_per_element(n, r)) / (ms * 1e-3) / 1e12
+        leg[f"{tag}_fallbacks"] = int(np.sum(info == -1))
+        leg[f"{tag}_bad"] = int(np.sum((info != 0) & (info != -1)))
+        res = db.unpack(go)
+        checks += [("W", f"{tag}_max_rel_err_sampled", b, int(e), 0, res[int(e)]) for e in idx]
+        leg[f"{tag}_tuning"] = ctx.tune_report()
+    leg["flops_per_element"] = "n^3/3 + 2 n^2 r"
+    leg["sample"] = f"{len(idx)} elements against the FP64 oracle"
+    del db
     torch.cuda.empty_cache()
     return leg
 
@@ -384,6 +423,8 @@ def extra_legs(torch, ctx, db, out, args, checks):
         ex["T"] = _transient_leg(torch, ctx, args.batch, db, args.steps, checks)
     if "SKEL" in legs:
         ex["SKEL"] = _skeleton_leg(torch, ctx, args.batch, db, out, args.steps)
+    if "W" in legs:
+        ex["W"] = _wide_leg(torch, ctx, checks)
     return ex
 
 
@@ -417,15 +458,16 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the C2 FP32+IR, C3, C4 (batching) and C5 (serving) legs")
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="length of the C5 open-loop stream")
-    ap.add_argument("--legs", default="C2,C3,C4,C5,T,SKEL",
+    ap.add_argument("--legs", default="C2,C3,C4,C5,T,SKEL,W",
                     help="which extra legs to run (comma list): C2 C3 C4 C5, T (time steps reusing factors), "
-                         "SKEL (skeleton scatter and reconstruction)")
+                         "SKEL (skeleton scatter and reconstruction), W (C3 with m = 4 segments per face, "
+                         "49 right-hand sides per factor)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 (the local problems shard "
-                                   "by element across GPUs, see DESIGN.md)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the local problems are "
+                                   "independent and shard by element across GPUs)"}))
         sys.exit(2)
 
     import torch

@@ -71,8 +71,12 @@ extern "C" {
 #endif
 
 #define MHM_S_LIMIT 64   /* largest s per element          */
-#define MHM_L_LIMIT 4    /* largest l per element (r <= 16) */
-#define MHM_P_LIMIT 5    /* largest m (l + 1), face DoFs per face (r <= 16) */
+#define MHM_L_LIMIT 4    /* largest l per element                          */
+#define MHM_P_LIMIT 16   /* largest m (l + 1), face DoFs per face (r <= 49):
+                            a batch with p_max (or l_max + 1) above 5, that is
+                            r above 16, runs on the left-looking kernel only,
+                            which takes s <= 48; an element it cannot take
+                            reports info -3                                 */
 
 typedef struct mhm_ctx_s* mhm_ctx;
 typedef struct mhm_graph_s* mhm_graph;

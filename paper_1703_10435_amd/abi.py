@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libmhm.so")
 
 MHM_OK, MHM_E_ARG, MHM_E_NOMEM, MHM_E_DEVICE, MHM_E_UNSUPPORTED = 0, 1, 2, 3, 4
 MHM_FP64, MHM_FP32_IR = 0, 1
-MHM_S_LIMIT, MHM_L_LIMIT, MHM_P_LIMIT = 64, 4, 5
+MHM_S_LIMIT, MHM_L_LIMIT, MHM_P_LIMIT = 64, 4, 16
 
 INFO_OK, INFO_IR_FALLBACK, INFO_BAD_DESC, INFO_TOO_LARGE = 0, -1, -2, -3
 

@@ -122,6 +122,7 @@ int grid_for(const mhm_batch* b) { return std::min(b->n_elem, kGridCap); }
 // Launch plan of one local-problem kernel for elements with s <= s_cap.
 struct Plan {
   bool ok = false, fp32 = false, fused = false;
+  bool mc = false;   // more than RHS_CHUNK right-hand sides (left-looking kernel only)
   Choice ch;
   int nt = 0, tile_cap = 0, n_cap = 0, f_cap = 0, k_cap = 0, grid = 0;
   size_t lds = 0, ws_need = 0;
@@ -138,6 +139,10 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
   p.f_cap = 3 * p_bound(b) * (s_cap + 1);
   p.nt = (p.n_cap + 15) / 16;
   p.tile_cap = p.nt * (p.nt + 1) / 2 + p.nt;
+  // every right-hand side in one 16-wide chunk: the families other than the
+  // left-looking one take only that
+  const bool one_chunk = 3 * p_bound(b) + 1 <= mhm::RHS_CHUNK;
+  p.mc = !one_chunk;
   const size_t tsz = fp32 ? sizeof(float) : sizeof(double);
   const int k_lds = fused ? s_cap * s_cap : 0;
   // one workgroup per element, or a persistent grid over a class list
@@ -145,7 +150,7 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
   const int slots = std::min(b->n_elem, 2 * c->n_cu);
   switch (ch.fam) {
     case FAM_RR:
-      p.ok = !fp32 && p.nt <= mhm::local_rr_max_nt();
+      p.ok = !fp32 && p.nt <= mhm::local_rr_max_nt() && one_chunk;
       p.k_cap = k_lds;
       p.lds = mhm::local_rr_lds_bytes(p.n_cap, p.f_cap, k_lds);
       p.grid = one_each;
@@ -153,11 +158,11 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
     case FAM_LDS:
       p.k_cap = k_lds;
       p.lds = mhm::local_lds_bytes(fp32, true, p.n_cap, p.f_cap, k_lds, p.tile_cap);
-      p.ok = p.lds + kStaticLds <= c->lds_limit;
+      p.ok = p.lds + kStaticLds <= c->lds_limit && one_chunk;
       p.grid = one_each;
       break;
     case FAM_LL:
-      p.ok = mhm::local_ll_has(fp32, ch.pw, p.nt, ch.occ, ch.nw);
+      p.ok = mhm::local_ll_has(fp32, ch.pw, p.nt, ch.occ, ch.nw, p.mc);
       p.lds = mhm::local_ll_lds_bytes(fp32, ch.pw, p.n_cap, p.f_cap, ch.nw);
       p.grid = slots;
       p.tile_cap += p.nt;   // the diagonal factor tiles kept for the factor output
@@ -166,7 +171,7 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
       break;
     default:
       p.lds = mhm::local_lds_bytes(fp32, false, p.n_cap, p.f_cap, 0, p.tile_cap);
-      p.ok = p.lds + kStaticLds <= c->lds_limit;
+      p.ok = p.lds + kStaticLds <= c->lds_limit && one_chunk;
       p.grid = slots;
       p.ws_slot = (int64_t)p.tile_cap * mhm::TILE_WORDS;
       break;
@@ -180,7 +185,7 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
 Choice default_choice(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_cap, bool listed) {
   const Choice ll = c->ll_occ2 ? Choice{FAM_LL, 2, 2} : Choice{FAM_LL, mhm::local_ll_default_panel(fp32), 1};
   const Choice ll16{FAM_LL, 2, 1, 16};
-  const Choice cands[] = {{FAM_RR, 0}, {FAM_LDS, 0}, c->ll_nw16 ? ll16 : ll, ll, {FAM_WS, 0}};
+  const Choice cands[] = {{FAM_RR, 0}, {FAM_LDS, 0}, c->ll_nw16 ? ll16 : ll, ll, {FAM_LL, 2, 1}, {FAM_WS, 0}};
   for (const Choice& ch : cands) {
     if (ch.fam == FAM_RR && c->no_rr) continue;
     if (ch.fam == FAM_LL && c->no_ll) continue;
@@ -228,8 +233,10 @@ RunPlan make_run_plan(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused
     r.s_cap = rp.listed ? std::min(kClassHi[k], b->s_max) : b->s_max;
     Choice ch = over ? *over : c->tuned[k][fp32][fused];
     if (cached) {
-      // stored factors: the left-looking kernel (tuned panel width if any)
+      // stored factors: the left-looking kernel (tuned panel width if any;
+      // the chunked instance for more than RHS_CHUNK right-hand sides)
       if (ch.fam != FAM_LL) ch = Choice{FAM_LL, mhm::local_ll_default_panel(fp32)};
+      if (3 * p_bound(b) + 1 > mhm::RHS_CHUNK) ch = Choice{FAM_LL, 2};
     } else if (ch.fam < 0 || !plan_for(c, b, fp32, fused, r.s_cap, ch, rp.listed).ok) {
       ch = default_choice(c, b, fp32, fused, r.s_cap, rp.listed);
     }
@@ -292,7 +299,7 @@ hipError_t launch_plan(const Plan& p, const mhm_batch* b, const mhm::LocalArgs& 
     case FAM_RR: return mhm::launch_local_rr(p.fused, b, a, p.lds, p.grid, st);
     case FAM_LDS: return mhm::launch_local(p.fp32, true, p.fused, b, a, p.lds, p.grid, st);
     case FAM_LL:
-      return mhm::launch_local_ll(p.fp32, p.fused, p.ch.pw, p.ch.occ, p.ch.nw, p.nt, b, a, p.lds, p.grid, st);
+      return mhm::launch_local_ll(p.fp32, p.fused, p.ch.pw, p.ch.occ, p.ch.nw, p.mc, p.nt, b, a, p.lds, p.grid, st);
     default: return mhm::launch_local(p.fp32, false, p.fused, b, a, p.lds, p.grid, st);
   }
 }

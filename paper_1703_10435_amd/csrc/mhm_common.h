@@ -145,8 +145,8 @@ __device__ __forceinline__ void contrib_element(const Elem& E, const double* X, 
     const int a = idx % NImax, bb = idx / NImax;
     if (a >= NI || bb >= NI) Me[idx] = 0.0;
   }
-  if (tid < NI * E.r) {
-    const int a = tid % NI, bb = tid / NI;
+  for (int idx = tid; idx < NI * E.r; idx += blockDim.x) {
+    const int a = idx % NI, bb = idx / NI;
     const int ef = a / E.P;
     const double* fa = ft + a * sp1;
     const double* xb = X + (int64_t)bb * n;
@@ -154,8 +154,8 @@ __device__ __forceinline__ void contrib_element(const Elem& E, const double* X, 
     for (int k = 0; k < sp1; ++k) v += fa[k] * xb[face_node(ef, k, s)];
     if (bb < NI) Me[(int64_t)bb * NImax + a] = -v;
     else Ev[(int64_t)e * NImax + a] = v;
-  } else if (tid >= 240 && tid < 240 + NImax) {
-    const int a = tid - 240;
+  }
+  for (int a = tid; a < NImax; a += blockDim.x) {
     double v = 0.0;
     if (a < NI) {
       for (int k = 0; k < sp1; ++k) v -= ft[a * sp1 + k];
@@ -164,7 +164,7 @@ __device__ __forceinline__ void contrib_element(const Elem& E, const double* X, 
     }
     Bv[(int64_t)e * NImax + a] = v;
   }
-  if (tid == 255) F[e] = Fval;
+  if (tid == 0) F[e] = Fval;
 }
 
 // ================================================================== k_local
@@ -372,7 +372,7 @@ __device__ __forceinline__ double ir_residual_body(const Elem& E, const double* 
                                                    T* rhs_row, double* red) {
   auto kap = [=](int t) -> double { return kapp[t]; };
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int s = E.s, n = E.n, r = E.r, nt = E.nt;
+  const int s = E.s, n = E.n, r = E.rc, c0 = E.c0, nt = E.nt;   // the columns of the current chunk
   for (int p = tid; p < 16 * nt; p += nthr) {   // padding rows and columns of the tiles
     T* rt = rhs_row + (int64_t)(p >> 4) * TILE + (p & 15);
     for (int a = (p >= n ? 0 : r); a < 16; ++a) rt[a * TST] = T(0);
@@ -392,12 +392,12 @@ __device__ __forceinline__ double ir_residual_body(const Elem& E, const double* 
     T* rt = rhs_row + (int64_t)(p >> 4) * TILE + (p & 15);
 #pragma unroll 4
     for (int a = 0; a < r; ++a) {
-      const double* xa = X + (int64_t)a * n;
+      const double* xa = X + (int64_t)(c0 + a) * n;
       double ax = st.d * xa[p] + cp * (g * cx[a]);
       if (hasE) ax += st.e * xa[pE] + st.n * xa[pN];
       if (hasW) ax += st.w * xa[pW] + st.nw * xa[pNW];
       if (hasS) ax += st.so * xa[pS] + st.se * xa[pSE];
-      const double b = FUSED ? btilde_tab(E, ft, bf, c, colsum, a, p, i, j) : Btg[(int64_t)a * n + p];
+      const double b = FUSED ? btilde_tab(E, ft, bf, c, colsum, c0 + a, p, i, j) : Btg[(int64_t)(c0 + a) * n + p];
       rt[a * TST] = (T)(b - ax);
     }
   }
@@ -413,7 +413,7 @@ __device__ __forceinline__ void ir_colmax_body(const Elem& E, const T* rhs_row, 
   const int tid = threadIdx.x, grp = tid >> 4, cl = tid & 15;
   const int gpc = blockDim.x >> 8;
   const int a = grp & 15, k = grp >> 4;
-  const int n = E.n, r = E.r, s = E.s;
+  const int n = E.n, r = E.rc, c0 = E.c0, s = E.s;
   double v = 0.0;
   if (a < r) {
     const int step = 16 * gpc;
@@ -422,7 +422,7 @@ __device__ __forceinline__ void ir_colmax_body(const Elem& E, const T* rhs_row, 
       if (of_b) {
         int i, j;
         node_ij(p, s, i, j);
-        x = FUSED ? btilde_tab(E, ft, bf, c, colsum, a, p, i, j) : Btg[(int64_t)a * n + p];
+        x = FUSED ? btilde_tab(E, ft, bf, c, colsum, c0 + a, p, i, j) : Btg[(int64_t)(c0 + a) * n + p];
       } else {
         x = (double)rhs_row[(int64_t)(p >> 4) * TILE + a * TST + (p & 15)];
       }

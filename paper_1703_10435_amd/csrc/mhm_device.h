@@ -18,6 +18,11 @@ constexpr int INFO_IR_FALLBACK = -1;
 constexpr int INFO_BAD_DESC = -2;
 constexpr int INFO_TOO_LARGE = -3;
 constexpr int INFO_NO_FACTOR = -4;
+// Right-hand sides per element: at most R_MAX = 3 MHM_P_LIMIT + 1; the
+// kernels solve them in chunks of R_CHUNK (one 16-wide tile row).  The
+// register-resident and right-looking kernels take one chunk only.
+constexpr int R_CHUNK = 16;
+constexpr int R_MAX = 3 * MHM_P_LIMIT + 1;
 
 // Batch descriptor as passed to kernels (by value).
 struct BatchDev {
@@ -70,6 +75,7 @@ inline BatchDev to_dev(const mhm_batch* p) {
 struct Elem {
   int s, l, n, NI, r, nt;   // nt = ceil(n / 16) tiles per matrix edge
   int m, P;                 // segments per face, face DoFs per face m (l + 1); NI = 3 P
+  int c0, rc;               // right-hand-side chunk in work: columns c0 .. c0 + rc - 1 (rc <= 16)
   double area;              // |K|
   double G[3][3];           // D_a . D_b / (4 |K|): P1 stiffness of any sub-triangle / kappa
   double flen[3];           // |F_e|
@@ -109,7 +115,9 @@ __device__ __forceinline__ bool load_elem(const BatchDev& b, int e, Elem& E) {
   E.P = m * (l + 1);
   E.n = (s + 1) * (s + 2) / 2;
   E.NI = 3 * E.P;
+  E.c0 = 0;
   E.r = E.NI + 1;
+  E.rc = E.r < R_CHUNK ? E.r : R_CHUNK;
   E.nt = (E.n + 15) / 16;
   const int64_t t0 = b.tri_off[e], t1 = b.tri_off[e + 1];
   if (t0 < 0 || t1 - t0 != (int64_t)s * s || t1 > b.tri_total) return false;

@@ -58,6 +58,7 @@ __device__ __forceinline__ int launch_count(const LocalArgs& a, int n_elem) { re
 __device__ __forceinline__ int launch_elem(const LocalArgs& a, int k) { return a.elist ? a.elist[k] : k; }
 
 constexpr int TILE_WORDS = 16 * 17;   // stored tile: 16 rows, padded stride 17
+constexpr int RHS_CHUNK = 16;         // right-hand sides per tile row (the one-chunk kernels' limit)
 
 // Size classes for ragged batches (upper s bound of each class, ascending).
 constexpr int BIN_MAX_CLASSES = 8;
@@ -98,12 +99,13 @@ size_t local_rr_lds_bytes(int n_cap, int f_cap, int k_cap);
 int local_rr_max_nt();
 hipError_t launch_local_rr(bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid, hipStream_t st);
 // Left-looking kernel for large elements (tiles in a workspace slot), panel
-// width pw (block columns of pw tiles).
+// width pw (block columns of pw tiles); mc: the instance that takes more than
+// RHS_CHUNK right-hand sides (in chunks).
 int local_ll_rows_per_wave(int nt, int nw);
 int local_ll_default_panel(bool fp32);
-bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw);
+bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw, bool mc);
 size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap, int nw);
-hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, int nt_max, const mhm_batch* bt,
+hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, bool mc, int nt_max, const mhm_batch* bt,
                            LocalArgs a, size_t lds, int grid, hipStream_t st);
 hipError_t launch_local(bool fp32, bool in_lds, bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
                         hipStream_t st);

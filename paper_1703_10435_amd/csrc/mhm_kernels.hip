@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
   __shared__ Elem E;
   __shared__ int ok;
   __shared__ double red[48];
-  __shared__ double colsum[16];
+  __shared__ double colsum[R_MAX];
   __shared__ double gam;
   extern __shared__ double dyn[];   // kappa[s^2] | c[n] | bf[n] | ft[NI(s+1)]
   const int tid = threadIdx.x;
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
   __shared__ int ok, bad, conv;
   __shared__ double be_prev;
   __shared__ double red[48];
-  __shared__ double colsum[16];
+  __shared__ double colsum[R_CHUNK];   // one chunk only (r <= 16)
   __shared__ double cx[16];          // (c^T X) per column
   __shared__ double gam;
   __shared__ double part_s[32 * (NTHREADS / 256)];
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
       } else {
         const bool good = load_elem(b, e, E) && E.rhs0 >= 0 && (FUSED || E.mat0 >= 0);
         if (!good) st = INFO_BAD_DESC;
-        else if ((E.nt * (E.nt + 1)) / 2 + E.nt > args.tile_cap || E.n > args.n_cap ||
+        else if ((E.nt * (E.nt + 1)) / 2 + E.nt > args.tile_cap || E.n > args.n_cap || E.r > R_CHUNK ||
                  (FUSED && E.NI * (E.s + 1) > args.f_cap) || (FUSED && IN_LDS && E.s * E.s > args.k_cap))
           st = INFO_TOO_LARGE;
         ok = st == INFO_OK;
@@ -460,7 +460,7 @@ __global__ void __launch_bounds__(NTHREADS) k_reconstruct(BatchDev b, const doub
                                                            double* u, const int32_t* info) {
   __shared__ Elem E;
   __shared__ int ok;
-  __shared__ double lam[16];
+  __shared__ double lam[R_MAX];
   __shared__ double u0;
   const int tid = threadIdx.x;
   const int NImax = nimax(b);
@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(NTHREADS) k_reconstruct(BatchDev b, const doub
       ok = load_elem(b, e, E) && E.rhs0 >= 0 && E.node0 >= 0 && (!info || info[e] == INFO_OK || info[e] == INFO_IR_FALLBACK);
       if (ok) u0 = (erow[e] >= 0 && erow[e] < n_rows) ? sol[erow[e]] : __longlong_as_double(0x7ff8000000000000ll);
     }
-    if (tid < 16) lam[tid] = 0.0;
+    if (tid < R_MAX) lam[tid] = 0.0;
     __syncthreads();
     if (!ok) continue;
     if (tid < E.NI) {

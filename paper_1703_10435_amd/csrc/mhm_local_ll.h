@@ -183,8 +183,10 @@ __device__ __forceinline__ void sweep(T* Lb, T* rhs_row, int nt, T* xb, T* scr, 
 // per SIMD, at most 128 registers per lane; two elements interleave their
 // latencies), with one operand buffer.  NWV = 16: 16 waves per element
 // (half the rows per wave, at most 128 registers per lane, twice the waves
-// in flight).
-template <typename T, bool FUSED, int PW, int RPW, int OCC, int NWV>
+// in flight).  MC: more than 16 right-hand sides, in chunks of 16 (built
+// only where a batch has them, so the one-chunk instances keep their
+// registers).
+template <typename T, bool FUSED, int PW, int RPW, int OCC, int NWV, bool MC>
 __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev b, LocalArgs args) {
   typedef typename Mfma<T>::v4 V4;
   constexpr int NW = NWV;
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
   __shared__ int ok, bad, conv;
   __shared__ double be_prev;
   __shared__ double red[48];
-  __shared__ double colsum[16];
+  __shared__ double colsum[R_MAX];
   __shared__ double cx[16];
   __shared__ double gam;
   __shared__ double part_s[32 * (NTHREADS / 256)];
@@ -215,6 +217,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
         const bool good = load_elem(b, e, E) && E.rhs0 >= 0 && (FUSED || E.mat0 >= 0);
         if (!good) st = INFO_BAD_DESC;
         else if ((args.fac ? E.nt : (E.nt * (E.nt + 1)) / 2 + 2 * E.nt) > args.tile_cap || E.n > args.n_cap ||
+                 (!MC && E.r > R_CHUNK) ||
                  E.nt + 1 > NW * RPW || (args.fac && args.fac_off[e] < 0) ||
                  (FUSED && E.NI * (E.s + 1) > args.f_cap))
           st = INFO_TOO_LARGE;
@@ -296,8 +299,8 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
         for (int v = 0; v < 4; ++v) {
           const int a = Mfma<T>::row(grp, v);
           double x = 0.0;
-          if (a < r && q < n) x = FUSED ? btilde_tab(E, ft, bf, c, colsum, a, q, qi, qj)
-                                        : args.Btil[E.rhs0 + (int64_t)a * n + q];
+          if (a < E.rc && q < n) x = FUSED ? btilde_tab(E, ft, bf, c, colsum, E.c0 + a, q, qi, qj)
+                                           : args.Btil[E.rhs0 + (int64_t)(E.c0 + a) * n + q];
           v4[v] = (T)x;
         }
         return v4;
@@ -553,79 +556,104 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     }
 
     // ------------------------------------------------ solves on the RHS row
+    // The right-hand sides go through the row in chunks of 16 columns: the
+    // first chunk's forward solve ran with the factorisation (or the stored
+    // factor's forward sweep above); later chunks (more than 15 face DoFs)
+    // load their columns and run both sweeps on the finished factor, as
+    // calls (the kernel's registers stay those of the first chunk).
     backward();
     const bool failed = bad >= 0;
     double* X = args.X + E.rhs0;
     const int ca = tid >> 4, cl16 = tid & 15;   // 32 groups of 16 lanes; groups 0..15 do column sums
-
-    if (fp32 && !failed) {
-      // --------------------------------------- FP64 refinement (FP32 path)
-      double* part = part_s;
-      ir_accumulate<T>(X, tl(nt, 0), c, n, r, true, cx, xmax, part);
-      const double* Btg = FUSED ? nullptr : args.Btil + E.rhs0;
-      int it = 0;
-      for (;; ++it) {
-        const double anorm = ir_residual<T, FUSED>(E, kapg, X, c, cx, g, ft, bf, colsum, Btg, tl(nt, 0), red);
-        if (it == 0) ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, true, bmax, part);
-        ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, false, rmax, part);
-        if (tid == 0) {
-          const double be = ir_backward_error(rmax, xmax, bmax, r, anorm);
-          conv = ir_decide(be, be_prev, it, args.max_iters, args.ir_tol);
-          be_prev = be;
-        }
-        __syncthreads();
-        if (conv != 0) break;
-        forward();
-        backward();
-        ir_accumulate<T>(X, tl(nt, 0), c, n, r, false, cx, xmax, part);
+    if (failed) {
+      if (fp32) {
+        if (tid == 0) args.info[e] = INFO_IR_FALLBACK;
+        continue;
       }
-      const bool cvd = conv > 0;
-      if (tid == 0) {
-        if (args.ir_iters) args.ir_iters[e] = it;
-        if (!cvd) args.info[e] = INFO_IR_FALLBACK;
-      }
-      if (!cvd) continue;
-      // zero-mean projection: cx still holds c^T X of the converged iterate
-      for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] -= cx[idx / n] * E.inv_area;
-      __syncthreads();
-    } else if (fp32) {
-      if (tid == 0) args.info[e] = INFO_IR_FALLBACK;
-      continue;
-    } else if (failed) {
       for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] = __builtin_nan("");
       if (tid == 0) args.info[e] = bad + 1;
       if (FUSED && args.M) {
         for (int idx = tid; idx < NImax * NImax; idx += NTHREADS)
           args.M[(int64_t)e * NImax * NImax + idx] = __builtin_nan("");
-        if (tid < NImax) {
-          args.E[(int64_t)e * NImax + tid] = __builtin_nan("");
-          args.B[(int64_t)e * NImax + tid] = __builtin_nan("");
+        for (int a = tid; a < NImax; a += NTHREADS) {
+          args.E[(int64_t)e * NImax + a] = __builtin_nan("");
+          args.B[(int64_t)e * NImax + a] = __builtin_nan("");
         }
         if (tid == 0) args.F[e] = __builtin_nan("");
       }
       continue;
-    } else {
-      {
-        double v = 0.0;
-        if (ca < r)
-          for (int p = cl16; p < n; p += 16) v += c[p] * (double)tl(nt, p >> 4)[ca * TST + (p & 15)];
-        v = group16_sum(v);
-        if (cl16 == 0 && ca < 16) cx[ca] = v * E.inv_area;
-      }
-      __syncthreads();
-      for (int idx = tid; idx < n * r; idx += NTHREADS) {
-        const int a = idx / n, p = idx - a * n;
-        X[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)] - cx[a];
-      }
-      __syncthreads();
     }
+    int it_max = 0;
+    for (int c0 = 0; c0 < (MC ? r : 1); c0 += R_CHUNK) {
+      if (MC && c0 > 0) {
+        __syncthreads();
+        if (tid == 0) {
+          E.c0 = c0;
+          E.rc = r - c0 < R_CHUNK ? r - c0 : R_CHUNK;
+        }
+        __syncthreads();
+        for (int J = wave; J < nt; J += NW) st_acc<T>(tl(nt, J), init_tile(nt, J), lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __syncthreads();
+        ll::sweep_call<T, RPW, false, OCC, NW>(Lb, rhs_row, nt, xb, scr, wave, lane);
+        ll::sweep_call<T, RPW, true, OCC, NW>(Lb, rhs_row, nt, xb, scr, wave, lane);
+      }
+      const int rc = E.rc;
+      double* Xc = X + (int64_t)c0 * n;
+      if (fp32) {
+        // ------------------------------------- FP64 refinement (FP32 path)
+        double* part = part_s;
+        ir_accumulate<T>(Xc, tl(nt, 0), c, n, rc, true, cx, xmax, part);
+        const double* Btg = FUSED ? nullptr : args.Btil + E.rhs0;
+        int it = 0;
+        for (;; ++it) {
+          const double anorm = ir_residual<T, FUSED>(E, kapg, X, c, cx, g, ft, bf, colsum, Btg, tl(nt, 0), red);
+          if (it == 0) ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, true, bmax, part);
+          ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, false, rmax, part);
+          if (tid == 0) {
+            const double be = ir_backward_error(rmax, xmax, bmax, rc, anorm);
+            conv = ir_decide(be, be_prev, it, args.max_iters, args.ir_tol);
+            be_prev = be;
+          }
+          __syncthreads();
+          if (conv != 0) break;
+          forward();
+          backward();
+          ir_accumulate<T>(Xc, tl(nt, 0), c, n, rc, false, cx, xmax, part);
+        }
+        it_max = it > it_max ? it : it_max;
+        if (conv < 0) break;
+        // zero-mean projection: cx still holds c^T X of the converged iterate
+        for (int idx = tid; idx < n * rc; idx += NTHREADS) Xc[idx] -= cx[idx / n] * E.inv_area;
+        __syncthreads();
+      } else {
+        {
+          double v = 0.0;
+          if (ca < rc)
+            for (int p = cl16; p < n; p += 16) v += c[p] * (double)tl(nt, p >> 4)[ca * TST + (p & 15)];
+          v = group16_sum(v);
+          if (cl16 == 0 && ca < 16) cx[ca] = v * E.inv_area;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < n * rc; idx += NTHREADS) {
+          const int a = idx / n, p = idx - a * n;
+          Xc[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)] - cx[a];
+        }
+        __syncthreads();
+      }
+    }
+    if (fp32 && tid == 0) {
+      if (args.ir_iters) args.ir_iters[e] = it_max;
+      if (conv < 0) args.info[e] = INFO_IR_FALLBACK;
+    }
+    if (fp32 && conv < 0) continue;
     if (FUSED && args.M) contrib_element(E, X, ft, colsum[E.NI], NImax, args.M, args.E, args.B, args.F, e);
   }
 }
 
-template <typename T, bool FUSED, int PW, int RPW, int OCC, int NWV = 8>
+template <typename T, bool FUSED, int PW, int RPW, int OCC, int NWV = 8, bool MC = false>
 static hipError_t launch_ll_t(const BatchDev& d, LocalArgs a, size_t lds, int grid, hipStream_t st) {
-  auto kern = k_local_ll<T, FUSED, PW, RPW, OCC, NWV>;
+  auto kern = k_local_ll<T, FUSED, PW, RPW, OCC, NWV, MC>;
   hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NWV), lds, st, d, a);

@@ -5,10 +5,10 @@
 
 namespace mhm {
 
-hipError_t launch_local_ll_f32(bool fused, int pw, int occ, int nw, int rpw, const BatchDev& d, LocalArgs a,
-                               size_t lds, int grid, hipStream_t st);
-hipError_t launch_local_ll_f64(bool fused, int pw, int occ, int nw, int rpw, const BatchDev& d, LocalArgs a,
-                               size_t lds, int grid, hipStream_t st);
+hipError_t launch_local_ll_f32(bool fused, int pw, int occ, int nw, int rpw, bool mc, const BatchDev& d,
+                               LocalArgs a, size_t lds, int grid, hipStream_t st);
+hipError_t launch_local_ll_f64(bool fused, int pw, int occ, int nw, int rpw, bool mc, const BatchDev& d,
+                               LocalArgs a, size_t lds, int grid, hipStream_t st);
 
 int local_ll_rows_per_wave(int nt, int nw) {
   const int rows = nt + 1;
@@ -21,7 +21,9 @@ int local_ll_rows_per_wave(int nt, int nw) {
 
 int local_ll_default_panel(bool fp32) { return fp32 ? 4 : 2; }
 
-bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw) {
+bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw, bool mc) {
+  if (mc)   // chunked right-hand sides: panel width 2, 8 waves, one workgroup per CU
+    return pw == 2 && occ == 1 && nw == 8 && local_ll_rows_per_wave(nt, 8) > 0;
   if (nw == 16)   // built for the largest elements only (49 to 80 tile rows)
     return occ == 1 && nt + 1 > 48 && local_ll_rows_per_wave(nt, 16) == 5 && (pw == 2 || (fp32 && pw == 4));
   if (nw != 8) return false;
@@ -38,13 +40,13 @@ size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap, int nw) {
          (size_t)(2 * pw + 1 + pw + nw) * TILE * (fp32 ? sizeof(float) : sizeof(double));
 }
 
-hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, int nt_max, const mhm_batch* bt,
+hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, bool mc, int nt_max, const mhm_batch* bt,
                            LocalArgs a, size_t lds, int grid, hipStream_t st) {
-  if (!local_ll_has(fp32, pw, nt_max, occ, nw)) return hipErrorInvalidValue;
+  if (!local_ll_has(fp32, pw, nt_max, occ, nw, mc)) return hipErrorInvalidValue;
   const int rpw = local_ll_rows_per_wave(nt_max, nw);
   const BatchDev d = to_dev(bt);
-  return fp32 ? launch_local_ll_f32(fused, pw, occ, nw, rpw, d, a, lds, grid, st)
-              : launch_local_ll_f64(fused, pw, occ, nw, rpw, d, a, lds, grid, st);
+  return fp32 ? launch_local_ll_f32(fused, pw, occ, nw, rpw, mc, d, a, lds, grid, st)
+              : launch_local_ll_f64(fused, pw, occ, nw, rpw, mc, d, a, lds, grid, st);
 }
 
 }  // namespace mhm

@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
   __shared__ Elem E;
   __shared__ int ok, bad;
   __shared__ double red[3 * NWAVES];
-  __shared__ double colsum[16];
+  __shared__ double colsum[R_CHUNK];   // one chunk only (r <= 16): two workgroups per CU need every byte
   __shared__ double cx[16];
   __shared__ double gam;
   extern __shared__ double dyn[];      // c | bf | ft | kap | stencil[8][n] | P[NT] | W[NT] | R[NT]
@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
       int st = INFO_OK;
       const bool good = load_elem(b, e, E) && E.rhs0 >= 0 && (FUSED || E.mat0 >= 0);
       if (!good) st = INFO_BAD_DESC;
-      else if (E.nt > NT || E.n > args.n_cap || (FUSED && (E.NI * (E.s + 1) > args.f_cap || E.s * E.s > args.k_cap)))
+      else if (E.nt > NT || E.n > args.n_cap || E.r > R_CHUNK || (FUSED && (E.NI * (E.s + 1) > args.f_cap || E.s * E.s > args.k_cap)))
         st = INFO_TOO_LARGE;
       ok = st == INFO_OK;
       args.info[e] = st;

@@ -88,7 +88,7 @@ def test_layout_offsets():
     (lambda b: b["sigma"].__setitem__((0, 0), 2), "sigma"),
     (lambda b: b["vert"].__setitem__(0, b["vert"][0][[0, 1, 4, 5, 2, 3]]), "counter-clockwise"),
     (lambda b: b.__setitem__("m", np.full(b["n_elem"], 3, dtype=np.int32)), "divide s"),
-    (lambda b: b.__setitem__("m", np.full(b["n_elem"], 4, dtype=np.int32)), "at most"),
+    (lambda b: (b.__setitem__("m", np.full(b["n_elem"], 4, dtype=np.int32)), b["l"].fill(4)), "at most"),
 ])
 def test_validate_rejects_malformed_batches(mutate, msg):
     b = configs.make("C1")
