@@ -299,8 +299,9 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
         for (int v = 0; v < 4; ++v) {
           const int a = Mfma<T>::row(grp, v);
           double x = 0.0;
-          if (a < E.rc && q < n) x = FUSED ? btilde_tab(E, ft, bf, c, colsum, E.c0 + a, q, qi, qj)
-                                           : args.Btil[E.rhs0 + (int64_t)(E.c0 + a) * n + q];
+          const int col = MC ? E.c0 + a : a;   // the current chunk's column
+          if (a < (MC ? E.rc : r) && q < n) x = FUSED ? btilde_tab(E, ft, bf, c, colsum, col, q, qi, qj)
+                                                      : args.Btil[E.rhs0 + (int64_t)col * n + q];
           v4[v] = (T)x;
         }
         return v4;
@@ -565,6 +566,39 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     const bool failed = bad >= 0;
     double* X = args.X + E.rhs0;
     const int ca = tid >> 4, cl16 = tid & 15;   // 32 groups of 16 lanes; groups 0..15 do column sums
+    if constexpr (!MC && sizeof(T) == 8) {
+      // FP64, one chunk: the straight-line form (the chunked loop below costs
+      // this kernel registers)
+      if (failed) {
+        for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] = __builtin_nan("");
+        if (tid == 0) args.info[e] = bad + 1;
+        if (FUSED && args.M) {
+          for (int idx = tid; idx < NImax * NImax; idx += NTHREADS)
+            args.M[(int64_t)e * NImax * NImax + idx] = __builtin_nan("");
+          if (tid < NImax) {
+            args.E[(int64_t)e * NImax + tid] = __builtin_nan("");
+            args.B[(int64_t)e * NImax + tid] = __builtin_nan("");
+          }
+          if (tid == 0) args.F[e] = __builtin_nan("");
+        }
+        continue;
+      }
+      {
+        double v = 0.0;
+        if (ca < r)
+          for (int p = cl16; p < n; p += 16) v += c[p] * (double)tl(nt, p >> 4)[ca * TST + (p & 15)];
+        v = group16_sum(v);
+        if (cl16 == 0 && ca < 16) cx[ca] = v * E.inv_area;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < n * r; idx += NTHREADS) {
+        const int a = idx / n, p = idx - a * n;
+        X[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)] - cx[a];
+      }
+      __syncthreads();
+      if (FUSED && args.M) contrib_element(E, X, ft, colsum[E.NI], NImax, args.M, args.E, args.B, args.F, e);
+      continue;
+    }
     if (failed) {
       if (fp32) {
         if (tid == 0) args.info[e] = INFO_IR_FALLBACK;
