@@ -165,8 +165,14 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
       p.ok = mhm::local_ll_has(fp32, ch.pw, p.nt, ch.occ, ch.nw, p.mc);
       p.lds = mhm::local_ll_lds_bytes(fp32, ch.pw, p.n_cap, p.f_cap, ch.nw);
       p.grid = slots;
-      p.tile_cap += p.nt;   // the diagonal factor tiles kept for the factor output
-      if (cached) p.tile_cap = p.nt;   // factor in the caller's store: the RHS row only
+      {
+        // right-hand-side tile rows (one per 16 columns), then the diagonal
+        // factor tiles kept for the factor output; with the factor in the
+        // caller's store, the right-hand-side rows only
+        const int nch = p.mc ? (3 * p_bound(b) + 1 + mhm::RHS_CHUNK - 1) / mhm::RHS_CHUNK : 1;
+        p.tile_cap += nch * p.nt;
+        if (cached) p.tile_cap = nch * p.nt;
+      }
       p.ws_slot = (int64_t)p.tile_cap * mhm::TILE_WORDS;
       break;
     default:

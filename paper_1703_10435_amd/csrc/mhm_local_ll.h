@@ -215,8 +215,10 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
         ok = 0;
       } else {
         const bool good = load_elem(b, e, E) && E.rhs0 >= 0 && (FUSED || E.mat0 >= 0);
+        const int nch_e = MC ? (E.r + R_CHUNK - 1) / R_CHUNK : 1;   // right-hand-side tile rows
         if (!good) st = INFO_BAD_DESC;
-        else if ((args.fac ? E.nt : (E.nt * (E.nt + 1)) / 2 + 2 * E.nt) > args.tile_cap || E.n > args.n_cap ||
+        else if ((args.fac ? nch_e * E.nt : (E.nt * (E.nt + 1)) / 2 + (nch_e + 1) * E.nt) > args.tile_cap ||
+                 E.n > args.n_cap ||
                  (!MC && E.r > R_CHUNK) ||
                  E.nt + 1 > NW * RPW || (args.fac && args.fac_off[e] < 0) ||
                  (FUSED && E.NI * (E.s + 1) > args.f_cap))
@@ -247,11 +249,26 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     T* Lb = args.fac ? reinterpret_cast<T*>(static_cast<char*>(args.fac) + args.fac_off[e]) : ws;
     T* rhs_row = args.fac ? ws : ws + (int64_t)((nt * (nt + 1)) / 2) * TILE;
     const bool reuse = args.fac && args.fac_state && args.fac_state[e] == 1;
+    // Right-hand sides: one tile row of 16 columns per chunk.  The chunked
+    // instances eliminate as many chunks as the waves have spare rows for
+    // (tile rows nt .. nrows - 1 below the matrix) with the factorisation;
+    // the others are swept on the finished factor one at a time.
+    const int nch = MC ? (r + R_CHUNK - 1) / R_CHUNK : 1;
+    const int nfused = MC && !reuse ? min(nch, NW * RPW - nt) : 1;
+    const int nrows = nt + nfused;
     auto tl = [&](int I, int J) -> T* {
-      return I == nt ? rhs_row + (int64_t)J * TILE : Lb + (int64_t)((I * (I + 1)) / 2 + J) * TILE;
+      if constexpr (MC) {
+        if (I >= nt) return rhs_row + ((int64_t)(I - nt) * nt + J) * TILE;
+      } else {
+        if (I == nt) return rhs_row + (int64_t)J * TILE;
+      }
+      return Lb + (int64_t)((I * (I + 1)) / 2 + J) * TILE;
     };
-    // L_jj tiles (factor output only), after the right-hand-side row
-    auto ldiag = [&](int J) -> T* { return rhs_row + (int64_t)(nt + J) * TILE; };
+    // row i of the panel loops: a right-hand-side row, or inside the rows held
+    auto rhs_i = [&](int i) -> bool { return MC ? i >= nt : i == nt; };
+    auto held_i = [&](int i) -> bool { return MC ? i < nrows : i <= nt; };
+    // L_jj tiles (factor output only), after the right-hand-side rows
+    auto ldiag = [&](int J) -> T* { return rhs_row + (int64_t)(nch * nt + J) * TILE; };
     const double* kapg = b.kappa + E.tri0;
     auto kap = [&](int t) -> double { return kapg[t]; };
 
@@ -287,21 +304,22 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     if (!FUSED && args.Lout && E.mat0 >= 0) Lo = reinterpret_cast<T*>(args.Lout + E.mat0);
 
     // Initial value of tile (I, J) in the MFMA result layout: Ahat for I < nt,
-    // the transposed right-hand sides Btilde^T for I == nt.
+    // the transposed right-hand sides Btilde^T for I >= nt (chunk I - nt).
     auto init_tile = [&](int I, int J) -> V4 {
       V4 v4;
       const int cl = lane & 15, grp = lane >> 4;
       const int q = 16 * J + cl;
-      if (I == nt) {
+      if (MC ? I >= nt : I == nt) {
+        const int cb = MC ? R_CHUNK * (I - nt) : 0;   // the chunk's first column
         int qi = 0, qj = 0;
         if (FUSED && q < n) node_ij(q, s, qi, qj);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int a = Mfma<T>::row(grp, v);
           double x = 0.0;
-          const int col = MC ? E.c0 + a : a;   // the current chunk's column
-          if (a < (MC ? E.rc : r) && q < n) x = FUSED ? btilde_tab(E, ft, bf, c, colsum, col, q, qi, qj)
-                                                      : args.Btil[E.rhs0 + (int64_t)col * n + q];
+          const int col = cb + a;
+          if (col < r && q < n) x = FUSED ? btilde_tab(E, ft, bf, c, colsum, col, q, qi, qj)
+                                          : args.Btil[E.rhs0 + (int64_t)col * n + q];
           v4[v] = (T)x;
         }
         return v4;
@@ -350,8 +368,8 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     };
 
     T* xb = stage;   // two published solution tiles of the sweeps (staging area)
-    auto backward = [&]() { ll::sweep<T, RPW, true, OCC, NW>(Lb, rhs_row, nt, xb, scr, wave, lane); };
-    auto forward = [&]() { ll::sweep<T, RPW, false, OCC, NW>(Lb, rhs_row, nt, xb, scr, wave, lane); };
+    auto backward = [&](T* row) { ll::sweep<T, RPW, true, OCC, NW>(Lb, row, nt, xb, scr, wave, lane); };
+    auto forward = [&](T* row) { ll::sweep<T, RPW, false, OCC, NW>(Lb, row, nt, xb, scr, wave, lane); };
 
     // ------------------------------------------------------ factorisation
     if (reuse) {
@@ -359,7 +377,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
       for (int J = wave; J < nt; J += NW) st_acc<T>(tl(nt, J), init_tile(nt, J), lane);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       __syncthreads();
-      forward();
+      forward(rhs_row);
     }
     for (int j0 = 0; j0 < (reuse ? 0 : nt); j0 += PW) {
       const int pw = nt - j0 < PW ? nt - j0 : PW;
@@ -372,10 +390,10 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
         const int i = j0 + wave + NW * ri;
 #pragma unroll
         for (int k = 0; k < PW; ++k) acc[ri][k] = V4{0, 0, 0, 0};
-        if (i <= nt) {
+        if (held_i(i)) {
 #pragma unroll 1
           for (int jj = 0; jj < pw; ++jj) {
-            if (i == nt || i >= j0 + jj) {
+            if (rhs_i(i) || i >= j0 + jj) {
               const V4 v = init_tile(i, j0 + jj);
 #pragma unroll
               for (int k = 0; k < PW; ++k) acc[ri][k] = jj == k ? v : acc[ri][k];
@@ -403,7 +421,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
 #pragma unroll
           for (int ri = 0; ri < RPW; ++ri) {
             const int i = j0 + wave + NW * ri;
-            if (i <= nt) ll::ld_row4(tl(i, m), lane, a[ri]);
+            if (held_i(i)) ll::ld_row4(tl(i, m), lane, a[ri]);
           }
 #pragma unroll
           for (int q = 0; q < SPT; ++q) {
@@ -430,10 +448,10 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
 #pragma unroll
           for (int ri = 0; ri < RPW; ++ri) {
             const int i = j0 + wave + NW * ri;
-            if (i <= nt) {
+            if (held_i(i)) {
 #pragma unroll
               for (int jj = 0; jj < PW; ++jj) {
-                if (jj < pw && (i == nt || i >= j0 + jj)) {
+                if (jj < pw && (rhs_i(i) || i >= j0 + jj)) {
                   V4 x = acc[ri][jj];
 #pragma unroll
                   for (int cch = 0; cch < 4; ++cch)
@@ -490,7 +508,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
 #pragma unroll
             for (int ri = 0; ri < RPW; ++ri) {
               const int i = j0 + wave + NW * ri;
-              if (i > col && i <= nt) {
+              if (i > col && held_i(i)) {
                 st_acc<T>(scr, acc[ri][k], lane);
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 V4 x = {0, 0, 0, 0};
@@ -513,7 +531,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
 #pragma unroll
             for (int ri = 0; ri < RPW; ++ri) {
               const int i = j0 + wave + NW * ri;
-              if (i > col && i <= nt) {
+              if (i > col && held_i(i)) {
                 st_acc<T>(scr, acc[ri][k], lane);
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 T a[4];
@@ -521,7 +539,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
                 for (int cch = 0; cch < 4; ++cch) a[cch] = -ld_rowcol(scr, cch, lane);
 #pragma unroll
                 for (int j2 = k + 1; j2 < PW; ++j2) {
-                  if (j2 < pw && (i == nt || i >= j0 + j2)) {
+                  if (j2 < pw && (rhs_i(i) || i >= j0 + j2)) {
                     V4 x = acc[ri][j2];
 #pragma unroll
                     for (int cch = 0; cch < 4; ++cch) x = Mfma<T>::op(a[cch], ld_rowcol(pub + j2 * TILE, cch, lane), x);
@@ -562,7 +580,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     // factor's forward sweep above); later chunks (more than 15 face DoFs)
     // load their columns and run both sweeps on the finished factor, as
     // calls (the kernel's registers stay those of the first chunk).
-    backward();
+    backward(rhs_row);
     const bool failed = bad >= 0;
     double* X = args.X + E.rhs0;
     const int ca = tid >> 4, cl16 = tid & 15;   // 32 groups of 16 lanes; groups 0..15 do column sums
@@ -619,6 +637,8 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     }
     int it_max = 0;
     for (int c0 = 0; c0 < (MC ? r : 1); c0 += R_CHUNK) {
+      const int ch = c0 / R_CHUNK;
+      T* rowc = tl(nt + ch, 0);   // this chunk's tile row
       if (MC && c0 > 0) {
         __syncthreads();
         if (tid == 0) {
@@ -626,24 +646,26 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
           E.rc = r - c0 < R_CHUNK ? r - c0 : R_CHUNK;
         }
         __syncthreads();
-        for (int J = wave; J < nt; J += NW) st_acc<T>(tl(nt, J), init_tile(nt, J), lane);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __syncthreads();
-        ll::sweep_call<T, RPW, false, OCC, NW>(Lb, rhs_row, nt, xb, scr, wave, lane);
-        ll::sweep_call<T, RPW, true, OCC, NW>(Lb, rhs_row, nt, xb, scr, wave, lane);
+        if (ch >= nfused) {   // not eliminated with the factorisation: forward sweep first
+          for (int J = wave; J < nt; J += NW) st_acc<T>(rowc + (int64_t)J * TILE, init_tile(nt + ch, J), lane);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          __syncthreads();
+          ll::sweep_call<T, RPW, false, OCC, NW>(Lb, rowc, nt, xb, scr, wave, lane);
+        }
+        ll::sweep_call<T, RPW, true, OCC, NW>(Lb, rowc, nt, xb, scr, wave, lane);
       }
       const int rc = E.rc;
       double* Xc = X + (int64_t)c0 * n;
       if (fp32) {
         // ------------------------------------- FP64 refinement (FP32 path)
         double* part = part_s;
-        ir_accumulate<T>(Xc, tl(nt, 0), c, n, rc, true, cx, xmax, part);
+        ir_accumulate<T>(Xc, rowc, c, n, rc, true, cx, xmax, part);
         const double* Btg = FUSED ? nullptr : args.Btil + E.rhs0;
         int it = 0;
         for (;; ++it) {
-          const double anorm = ir_residual<T, FUSED>(E, kapg, X, c, cx, g, ft, bf, colsum, Btg, tl(nt, 0), red);
-          if (it == 0) ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, true, bmax, part);
-          ir_colmax<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, false, rmax, part);
+          const double anorm = ir_residual<T, FUSED>(E, kapg, X, c, cx, g, ft, bf, colsum, Btg, rowc, red);
+          if (it == 0) ir_colmax<T, FUSED>(E, rowc, ft, bf, c, colsum, Btg, true, bmax, part);
+          ir_colmax<T, FUSED>(E, rowc, ft, bf, c, colsum, Btg, false, rmax, part);
           if (tid == 0) {
             const double be = ir_backward_error(rmax, xmax, bmax, rc, anorm);
             conv = ir_decide(be, be_prev, it, args.max_iters, args.ir_tol);
@@ -651,9 +673,9 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
           }
           __syncthreads();
           if (conv != 0) break;
-          forward();
-          backward();
-          ir_accumulate<T>(Xc, tl(nt, 0), c, n, rc, false, cx, xmax, part);
+          forward(rowc);
+          backward(rowc);
+          ir_accumulate<T>(Xc, rowc, c, n, rc, false, cx, xmax, part);
         }
         it_max = it > it_max ? it : it_max;
         if (conv < 0) break;
@@ -664,14 +686,14 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
         {
           double v = 0.0;
           if (ca < rc)
-            for (int p = cl16; p < n; p += 16) v += c[p] * (double)tl(nt, p >> 4)[ca * TST + (p & 15)];
+            for (int p = cl16; p < n; p += 16) v += c[p] * (double)rowc[(int64_t)(p >> 4) * TILE + ca * TST + (p & 15)];
           v = group16_sum(v);
           if (cl16 == 0 && ca < 16) cx[ca] = v * E.inv_area;
         }
         __syncthreads();
         for (int idx = tid; idx < n * rc; idx += NTHREADS) {
           const int a = idx / n, p = idx - a * n;
-          Xc[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)] - cx[a];
+          Xc[idx] = (double)rowc[(int64_t)(p >> 4) * TILE + a * TST + (p & 15)] - cx[a];
         }
         __syncthreads();
       }
