@@ -167,6 +167,12 @@ def _batched_leg(torch, ctx, name, sample_per_size, checks, reps=3):
         its = go["ir_iters"].cpu().numpy()[:E]
         leg[f"{tag}_graph_ms"] = ms
         leg[f"{tag}_graph_problems_per_s"] = E / (ms * 1e-3)
+        # algorithmic flops of the batch over the graph time, against the
+        # MFMA peak of the factor's precision
+        tf = float(np.sum(_flops_per_element(db.n, db.r))) / (ms * 1e-3) / 1e12
+        peak = PEAK_FP32_TFLOPS if prec == abi.MHM_FP32_IR else PEAK_FP64_TFLOPS
+        leg[f"{tag}_algorithmic_tflops"] = tf
+        leg[f"{tag}_frac_mfma_peak"] = tf / peak
         leg[f"{tag}_fallbacks"] = int(np.sum(info == -1))
         leg[f"{tag}_bad"] = int(np.sum((info != 0) & (info != -1)))
         if prec == abi.MHM_FP32_IR:
@@ -413,6 +419,26 @@ def extra_legs(torch, ctx, db, out, args, checks):
         ex["C2"] = {"fp64_three_call_ms": ms3, "fp32_ir_fused_ms": ms32,
                     "fp32_ir_steps_mean": float(fp32["ir_iters"].cpu().numpy()[:E].mean()),
                     "fp32_ir_fallbacks": int(np.sum(info == -1))}
+        # the HBM-bound steps of the three-call form on their own
+        o3 = db.alloc_outputs(three_call=True)
+        ms_a = _ms(torch, lambda: ctx.local_assemble(db, o3["Ahat"], o3["Btil"], o3["c"], o3["area"], o3["info"]),
+                   args.steps)
+        engine.run_three_call(ctx, db, abi.MHM_FP64, o3)
+        ms_c = _ms(torch, lambda: ctx.skeleton_contrib(db, o3["X"], o3["M"], o3["E"], o3["B"], o3["F"], o3["info"]),
+                   args.steps)
+        n_, r_, s_ = db.n.astype(np.float64), db.r.astype(np.float64), db.s.astype(np.float64)
+        ni = float(db.NImax)
+        # assemble: kappa, f in; Ahat, Btilde, c, area out.  contrib: the face
+        # rows of X and f in; M, E, B, F out
+        by_a = float(np.sum(16 * s_ ** 2 + 8 * n_ ** 2 + 8 * n_ * r_ + 8 * n_ + 8))
+        by_c = float(np.sum(8 * 3 * s_ * r_ + 8 * s_ ** 2 + 8 * (ni * ni + 2 * ni + 1)))
+        ex["C2"].update({"assemble_ms": ms_a, "assemble_GBps": by_a / (ms_a * 1e-3) / 1e9,
+                         "assemble_frac_hbm": by_a / (ms_a * 1e-3) / 8e12,
+                         "contrib_ms": ms_c, "contrib_GBps": by_c / (ms_c * 1e-3) / 1e9,
+                         "contrib_frac_hbm": by_c / (ms_c * 1e-3) / 8e12,
+                         "bytes": "assemble: 16 s^2 + 8 n^2 + 8 n r + 8 n + 8 per element; contrib: "
+                                  "8 (3 s r + s^2 + NImax^2 + 2 NImax + 1) per element"})
+        del o3
     if "C3" in legs:
         ex["C3"] = _batched_leg(torch, ctx, "C3", 3, checks)
     if "C4" in legs:
