@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
   __shared__ double red[48];
   __shared__ double colsum[R_MAX];
   __shared__ double gam;
-  extern __shared__ double dyn[];   // kappa[s^2] | c[n] | bf[n] | ft[NI(s+1)]
+  extern __shared__ double dyn[];   // kappa[s^2] | c[n] | bf[n] | ft[NI(s+1)] | stencil[7][n] | j[n]
   const int tid = threadIdx.x;
   const int smax = b.s_max, nmax = (smax + 1) * (smax + 2) / 2;
   for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
@@ -43,6 +43,8 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
     double* c = kap + smax * smax;
     double* bf = c + nmax;
     double* ft = bf + nmax;
+    double* sd = ft + nimax(b) * (smax + 1);        // the seven stencil values of node q at sd[k nmax + q]
+    int* sj = reinterpret_cast<int*>(sd + 7 * nmax);  // lattice row j of node q
     for (int t = tid; t < T; t += NTHREADS) kap[t] = b.kappa[E.tri0 + t];
     face_table(E, ft);
     __syncthreads();
@@ -56,6 +58,14 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
       const double bp = E.cunit * node_tri_sum(i, j, s, [&](int t) { return fp[t]; });
       c[p] = cp;
       bf[p] = bp;
+      sd[p] = st.d;
+      sd[nmax + p] = st.e;
+      sd[2 * nmax + p] = st.w;
+      sd[3 * nmax + p] = st.n;
+      sd[4 * nmax + p] = st.so;
+      sd[5 * nmax + p] = st.nw;
+      sd[6 * nmax + p] = st.se;
+      sj[p] = j;
       tr += st.d;
       cc2 += cp * cp;
       fs += bp;
@@ -68,26 +78,55 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
     face_colsums(E, ft, colsum);
     __syncthreads();
     const double g = gam;
-    // Ahat: wave w writes columns q = w, w+4, ...; lanes sweep rows.
-    const int w = tid >> 6, lane = tid & 63;
+    // Ahat, column-major.  Small elements (n <= 256): as one contiguous run
+    // of n^2 values, consecutive threads on consecutive entries (full cache
+    // lines; a column of a few lanes' width would leave most of a wave's last
+    // store idle), each from the stencil table of its column q.  Larger ones:
+    // wave w writes columns q = w, w+4, ... with the column's stencil in
+    // registers, lanes sweeping rows.
     double* A = Ahat + E.mat0;
-    for (int q = w; q < n; q += NWAVES) {
-      int i, j;
-      node_ij(q, s, i, j);
-      const Stencil st = stencil(i, j, s, E.G, [&](int t) { return kap[t]; });
-      const int pE = q + 1, pW = q - 1, pN = q + (s + 1 - j), pS = q - (s + 2 - j), pNW = q + (s - j),
-                pSE = q - (s + 1 - j);
-      const double gcq = g * c[q];
-      for (int p = lane; p < n; p += 64) {
-        double v = gcq * c[p];
-        v += (p == q) ? st.d : 0.0;
-        v += (p == pE) ? st.e : 0.0;
-        v += (p == pW) ? st.w : 0.0;
-        v += (p == pN) ? st.n : 0.0;
-        v += (p == pS) ? st.so : 0.0;
-        v += (p == pNW) ? st.nw : 0.0;
-        v += (p == pSE) ? st.se : 0.0;
-        A[(int64_t)q * n + p] = v;
+    if (n > 256) {
+      const int w = tid >> 6, lane = tid & 63;
+      for (int q = w; q < n; q += NWAVES) {
+        const int j = sj[q];
+        const double d = sd[q], ve = sd[nmax + q], vw = sd[2 * nmax + q], vn = sd[3 * nmax + q],
+                     vs = sd[4 * nmax + q], vnw = sd[5 * nmax + q], vse = sd[6 * nmax + q];
+        const int pE = q + 1, pW = q - 1, pN = q + (s + 1 - j), pS = q - (s + 2 - j), pNW = q + (s - j),
+                  pSE = q - (s + 1 - j);
+        const double gcq = g * c[q];
+        for (int p = lane; p < n; p += 64) {
+          double v = gcq * c[p];
+          v += (p == q) ? d : 0.0;
+          v += (p == pE) ? ve : 0.0;
+          v += (p == pW) ? vw : 0.0;
+          v += (p == pN) ? vn : 0.0;
+          v += (p == pS) ? vs : 0.0;
+          v += (p == pNW) ? vnw : 0.0;
+          v += (p == pSE) ? vse : 0.0;
+          A[(int64_t)q * n + p] = v;
+        }
+      }
+    } else {
+      const int nn = n * n;
+      const int dq = NTHREADS / n, dp = NTHREADS - dq * n;   // index step NTHREADS in (q, p)
+      int q = tid / n, p = tid - q * n;
+      for (int idx = tid; idx < nn; idx += NTHREADS) {
+        const int j = sj[q], off = p - q;
+        double v = g * c[q] * c[p];
+        v += off == 0 ? sd[q] : 0.0;
+        v += off == 1 ? sd[nmax + q] : 0.0;
+        v += off == -1 ? sd[2 * nmax + q] : 0.0;
+        v += off == s + 1 - j ? sd[3 * nmax + q] : 0.0;
+        v += off == -(s + 2 - j) ? sd[4 * nmax + q] : 0.0;
+        v += off == s - j ? sd[5 * nmax + q] : 0.0;
+        v += off == -(s + 1 - j) ? sd[6 * nmax + q] : 0.0;
+        A[idx] = v;
+        p += dp;
+        q += dq;
+        if (p >= n) {
+          p -= n;
+          ++q;
+        }
       }
     }
     double* Bt = Btil + E.rhs0;
@@ -649,7 +688,8 @@ hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, doub
                            int grid, hipStream_t st) {
   const int smax = bt->s_max;
   const int nmax = (smax + 1) * (smax + 2) / 2;
-  const size_t lds = sizeof(double) * ((size_t)smax * smax + 2 * (size_t)nmax + local_face_cap(bt));
+  const size_t lds = sizeof(double) * ((size_t)smax * smax + 9 * (size_t)nmax + local_face_cap(bt)) +
+                     sizeof(int) * (size_t)nmax;
   hipError_t err = hipFuncSetAttribute((const void*)k_assemble, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_assemble, dim3(grid), dim3(NTHREADS), lds, st, to_dev(bt), Ahat, Btil, c, area, info);

@@ -244,7 +244,7 @@ def _assemble_and_factor(ctx, b, prec=0):
 def test_assemble_outputs_match_definition(ctx, which):
     """Ahat = A + gamma c c^T with gamma = trace(A)/(n c^T c), Btilde = B -
     c (1^T B)/|K|, c and |K| against the oracle's A, c, R, b."""
-    b = configs.make("C1") if which == "C1" else _random_batch(21, [1, 3, 5, 16, 7], [0, 1, 4, 2, 3], "asm")
+    b = configs.make("C1") if which == "C1" else _random_batch(21, [1, 3, 5, 16, 7, 24], [0, 1, 4, 2, 3, 1], "asm")
     db, A0, B0, c0, ar, info_a, _ = _assemble_and_factor(ctx, b)
     assert np.all(info_a[:b["n_elem"]] == 0)
     for e in range(b["n_elem"]):
