@@ -223,13 +223,20 @@ mhm_status mhm_reconstruct(mhm_ctx ctx, const mhm_batch* batch, const double* X,
 /* The skeleton solve (the solve of reduceLocalProblems, Algorithm 1):
  * eq. (6) is symmetric and indefinite, [[M, B^T], [B, 0]] [lambda; u_0] =
  * [E; F] with M negative (semi-)definite.  Preconditioned MINRES (the
- * minimal-residual method for symmetric indefinite systems) with the block
- * diagonal preconditioner diag(|diag M|, diag(B |diag M|^-1 B^T)); the paper
- * uses sparse direct solvers and names hybrid direct-iterative ones as
- * future work (Section 6).
+ * minimal-residual method for symmetric indefinite systems) with a block
+ * diagonal preconditioner diag(D, S~): D the lambda_block x lambda_block
+ * diagonal blocks of -M (one face's DoFs), S~^-1 a fixed number of damped
+ * Jacobi sweeps on S = B D^-1 B^T (the u_0 rows; diag(S) alone when the
+ * element count is above about 8,000); with lambda_block = 1, D = |diag M|
+ * and S~ = diag(S).  The paper uses sparse direct solvers and names hybrid
+ * direct-iterative ones as future work (Section 6).
  *   n_rows, n_lambda  rows of the system; rows < n_lambda are multiplier
  *             rows (M, B^T), the others u_0 rows (B, 0), as numbered for
  *             mhm_skeleton_scatter.
+ *   lambda_block  multiplier rows come in groups of this many consecutive
+ *             indices, one group per face (m (l+1) in the numbering of
+ *             mhm_skeleton_scatter); 1 to 8, and a divisor of n_lambda, else
+ *             MHM_E_ARG.
  *   row_ptr [n_rows+1], col_idx, vals (device): the CSR matrix, e.g. as
  *             accumulated by mhm_skeleton_scatter (both triangles).  The
  *             structure is checked on the device first (row pointers from 0,
@@ -243,12 +250,13 @@ mhm_status mhm_reconstruct(mhm_ctx ctx, const mhm_batch* batch, const double* X,
  *             relative residual ||rhs - K sol||_2 / ||rhs||_2.
  * A singular but consistent system (multiplier block rank deficient, l >= s)
  * is fine: u_0, and u of mhm_reconstruct, are unique.  Uses the context's
- * workspace (9 n_rows doubles plus a few KB); synchronises the stream (the
- * host reads the residual estimate every 16 steps); deterministic for a
- * given launch configuration. */
-mhm_status mhm_skeleton_solve(mhm_ctx ctx, int32_t n_rows, int32_t n_lambda, const int32_t* row_ptr,
-                              const int32_t* col_idx, const double* vals, const double* rhs, double* sol,
-                              double tol, int32_t max_iters, int32_t* iters, double* relres);
+ * workspace ((15 + lambda_block) n_rows doubles at most, plus a few KB);
+ * synchronises the stream (the host reads the residual estimate every 16
+ * steps); deterministic for a given launch configuration. */
+mhm_status mhm_skeleton_solve(mhm_ctx ctx, int32_t n_rows, int32_t n_lambda, int32_t lambda_block,
+                              const int32_t* row_ptr, const int32_t* col_idx, const double* vals,
+                              const double* rhs, double* sol, double tol, int32_t max_iters, int32_t* iters,
+                              double* relres);
 
 /* Factor reuse (Section 3: the local matrix is factored once and reused
  * for further load vectors, e.g. over time steps): mhm_local_batch_run with

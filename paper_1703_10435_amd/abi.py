@@ -81,7 +81,7 @@ def load(path: str = LIB_PATH):
         "mhm_skeleton_scatter": (i32, [vp, bp] + [vp] * 8 + [i32] + [vp] * 4),
         "mhm_reconstruct": (i32, [vp, bp, vp, vp, vp, vp, i32, vp, vp]),
         "mhm_local_source_step": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]),
-        "mhm_skeleton_solve": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, ctypes.c_double, i32,
+        "mhm_skeleton_solve": (i32, [vp, i32, i32, i32, vp, vp, vp, vp, vp, ctypes.c_double, i32,
                                      ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
@@ -177,11 +177,13 @@ class Context:
             self.h, ctypes.byref(batch.desc), prec, _ptr(factors), _ptr(factor_off), _ptr(factor_state), _ptr(X),
             _ptr(M), _ptr(E), _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters), max_iters))
 
-    def skeleton_solve(self, n_rows, n_lambda, row_ptr, col_idx, vals, rhs, sol, tol=1e-12, max_iters=20000):
+    def skeleton_solve(self, n_rows, n_lambda, row_ptr, col_idx, vals, rhs, sol, tol=1e-12, max_iters=20000,
+                       lambda_block=1):
         """MINRES on the CSR skeleton system; returns (iterations, relative residual)."""
         it = ctypes.c_int32(0)
         rr = ctypes.c_double(0.0)
-        self._check(self.lib.mhm_skeleton_solve(self.h, int(n_rows), int(n_lambda), _ptr(row_ptr), _ptr(col_idx),
+        self._check(self.lib.mhm_skeleton_solve(self.h, int(n_rows), int(n_lambda), int(lambda_block),
+                                                _ptr(row_ptr), _ptr(col_idx),
                                                 _ptr(vals), _ptr(rhs), _ptr(sol), float(tol), int(max_iters),
                                                 ctypes.byref(it), ctypes.byref(rr)))
         return int(it.value), float(rr.value)

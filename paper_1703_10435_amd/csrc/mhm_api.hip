@@ -661,11 +661,13 @@ mhm_status mhm_skeleton_scatter(mhm_ctx c, const mhm_batch* b, const double* M, 
   return e == hipSuccess ? MHM_OK : hip_fail(c, e, "k_skeleton_scatter launch");
 }
 
-mhm_status mhm_skeleton_solve(mhm_ctx c, int32_t n_rows, int32_t n_lambda, const int32_t* row_ptr,
-                              const int32_t* col_idx, const double* vals, const double* rhs, double* sol, double tol,
-                              int32_t max_iters, int32_t* iters, double* relres) {
+mhm_status mhm_skeleton_solve(mhm_ctx c, int32_t n_rows, int32_t n_lambda, int32_t lambda_block,
+                              const int32_t* row_ptr, const int32_t* col_idx, const double* vals, const double* rhs,
+                              double* sol, double tol, int32_t max_iters, int32_t* iters, double* relres) {
   if (!c) return MHM_E_ARG;
   if (n_rows < 0 || n_lambda < 0 || n_lambda > n_rows) return fail(c, MHM_E_ARG, "need 0 <= n_lambda <= n_rows");
+  if (lambda_block < 1 || lambda_block > mhm::skeleton_block_max() || (n_lambda % lambda_block) != 0)
+    return fail(c, MHM_E_ARG, "lambda_block must be in [1, 8] and divide n_lambda");
   if (!(tol > 0.0) || max_iters < 0) return fail(c, MHM_E_ARG, "need tol > 0 and max_iters >= 0");
   if (iters) *iters = 0;
   if (relres) *relres = 0.0;
@@ -674,7 +676,7 @@ mhm_status mhm_skeleton_solve(mhm_ctx c, int32_t n_rows, int32_t n_lambda, const
     return fail(c, MHM_E_ARG, "row_ptr, col_idx, vals, rhs and sol are required");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-  mhm_status st = ensure_ws(c, mhm::skeleton_solve_bytes(n_rows));
+  mhm_status st = ensure_ws(c, mhm::skeleton_solve_bytes(n_rows, lambda_block));
   if (st != MHM_OK) return st;
   int bad = 0;
   e = mhm::skeleton_csr_check(n_rows, row_ptr, col_idx, c->ws, &bad, c->stream);
@@ -683,7 +685,7 @@ mhm_status mhm_skeleton_solve(mhm_ctx c, int32_t n_rows, int32_t n_lambda, const
   std::vector<double> host_sc(64, 0.0);
   int it = 0;
   double rr = 0.0;
-  e = mhm::skeleton_solve(n_rows, n_lambda, row_ptr, col_idx, vals, rhs, sol, tol, max_iters, c->ws,
+  e = mhm::skeleton_solve(n_rows, n_lambda, lambda_block, row_ptr, col_idx, vals, rhs, sol, tol, max_iters, c->ws,
                           host_sc.data(), &it, &rr, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "skeleton solve");
   if (iters) *iters = it;

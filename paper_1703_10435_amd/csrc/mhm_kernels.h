@@ -73,10 +73,11 @@ int source_step_waves();
 hipError_t launch_source_step(bool fp32, const mhm_batch* bt, const SourceArgs& a, size_t lds, int grid,
                               hipStream_t st);
 
-size_t skeleton_solve_bytes(int n);
+size_t skeleton_solve_bytes(int n, int pb);
+int skeleton_block_max();
 hipError_t skeleton_csr_check(int n, const int32_t* rp, const int32_t* ci, void* work, int* host_bad,
                               hipStream_t st);
-hipError_t skeleton_solve(int n, int n_lambda, const int32_t* rp, const int32_t* ci, const double* va,
+hipError_t skeleton_solve(int n, int n_lambda, int pb, const int32_t* rp, const int32_t* ci, const double* va,
                           const double* b, double* x, double tol, int max_iters, void* work, double* host_sc,
                           int* iters, double* relres, hipStream_t st);
 

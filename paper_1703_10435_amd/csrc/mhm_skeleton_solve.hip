@@ -7,14 +7,23 @@
 // direct-iterative solvers as future work (Section 6).  Here it is solved
 // iteratively with MINRES (Paige and Saunders' minimal-residual method for
 // symmetric indefinite systems, the preconditioned form with an SPD
-// preconditioner), preconditioned by the block diagonal
-//   P = diag(|diag(M)|, diag(B |diag(M)|^-1 B^T)),
-// the Jacobi scaling of the multiplier block and the diagonal of the
-// approximate Schur complement for the u_0 rows.
+// preconditioner), preconditioned by a block diagonal P = diag(D, S~):
+//   - multiplier rows in groups of `lambda_block` (the DoFs of one face):
+//     D = the face blocks of -M, inverted once (lambda_block = 1: |diag(M)|);
+//   - u_0 rows: S = B D^-1 B^T (the Schur complement of the face-block
+//     approximation), assembled once, one row per element with its up to
+//     three face neighbours; S~^-1 is a fixed number of damped Jacobi sweeps
+//     on S from zero (a fixed SPD polynomial in S), run by one workgroup
+//     with the iterate in LDS.  With lambda_block = 1, S~ = diag(S).
+// The u_0 block of the saddle point is an elliptic operator on the coarse
+// mesh; its diagonal alone leaves MINRES thousands of steps on C2's system,
+// the sweeps a few hundred.
 //
-// One MINRES step is three launches: the CSR product with its dot product,
-// the Lanczos vector with the next dot product, and the scalar recurrences
-// together with the update of the direction and the iterate.  Dot products
+// One MINRES step is three launches (four with face blocks): the CSR product
+// with its dot product, the Lanczos vector with the next dot product (with
+// face blocks: the Lanczos vector, then the preconditioner with the dot
+// product), and the scalar recurrences together with the update of the
+// direction and the iterate.  Dot products
 // are reduced in two stages through per-workgroup partials (no atomics),
 // so the iteration is deterministic.  Chunks of 16 steps are captured once
 // in a HIP graph and replayed; the host reads the residual estimate after
@@ -29,6 +38,12 @@ namespace {
 constexpr int SV_THREADS = 256;
 constexpr int SV_MAX_BLOCKS = 1024;
 constexpr int ROW_LANES = 8;   // lanes per CSR row in the products
+constexpr int PB_MAX = 8;      // largest face block of the preconditioner
+constexpr int S_NB = 3;        // face neighbours of an element in S
+constexpr int PA_THREADS = 1024;  // preconditioner launch
+constexpr int PA_ROWS = 4;        // u_0 rows per thread held in registers through the sweeps
+constexpr int JACOBI_SWEEPS = 16;
+constexpr double JACOBI_OMEGA = 0.7;
 
 // scalar slots
 enum : int {
@@ -98,6 +113,250 @@ __global__ void __launch_bounds__(SV_THREADS) k_prec_u0(int n, int n_lambda, con
   }
 }
 
+// Position of column `col` in row `row` (sorted columns), or -1.
+__device__ __forceinline__ int find_col(const int32_t* rp, const int32_t* ci, int row, int col) {
+  int lo = rp[row], hi = rp[row + 1] - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int c = ci[mid];
+    if (c == col) return mid;
+    if (c < col) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+// D_f^-1 for face f: the pb x pb block of -M on rows/columns f pb .. f pb + pb - 1,
+// inverted by Gauss-Jordan elimination without pivoting (the block is SPD).
+// A block that is not (a non-positive pivot) falls back to 1/|diag|.
+__global__ void __launch_bounds__(SV_THREADS) k_blk_inv(int nf, int pb, const int32_t* rp, const int32_t* ci,
+                                                       const double* va, double* dblk) {
+  for (int f = blockIdx.x * SV_THREADS + threadIdx.x; f < nf; f += gridDim.x * SV_THREADS) {
+    double a[PB_MAX][PB_MAX];
+    const int r0 = f * pb;
+#pragma unroll
+    for (int i = 0; i < PB_MAX; ++i)
+#pragma unroll
+      for (int j = 0; j < PB_MAX; ++j) {
+        double v = 0.0;
+        if (i < pb && j < pb) {
+          const int k = find_col(rp, ci, r0 + i, r0 + j);
+          v = k >= 0 ? -va[k] : 0.0;
+        }
+        a[i][j] = v;
+      }
+    double dg[PB_MAX];
+#pragma unroll
+    for (int i = 0; i < PB_MAX; ++i) dg[i] = a[i][i];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < PB_MAX; ++k) {
+      if (k < pb) {
+        const double piv = a[k][k];
+        ok = ok && piv > 0.0;
+        const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
+#pragma unroll
+        for (int j = 0; j < PB_MAX; ++j) a[k][j] = j == k ? inv : a[k][j] * inv;
+#pragma unroll
+        for (int i = 0; i < PB_MAX; ++i) {
+          if (i != k) {
+            const double fct = a[i][k];
+#pragma unroll
+            for (int j = 0; j < PB_MAX; ++j) a[i][j] = j == k ? -fct * inv : a[i][j] - fct * a[k][j];
+          }
+        }
+      }
+    }
+    double* o = dblk + (int64_t)f * pb * pb;
+    for (int i = 0; i < pb; ++i)
+      for (int j = 0; j < pb; ++j) {
+        double v = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < PB_MAX; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < PB_MAX; ++jj)
+            if (ii == i && jj == j) v = a[ii][jj];
+        if (!ok) v = i == j ? (fabs(dg[i]) > 0.0 ? 1.0 / fabs(dg[i]) : 1.0) : 0.0;
+        o[i * pb + j] = v;
+      }
+  }
+}
+
+// S = B D^-1 B^T on the u_0 rows, one element (row n_lambda + t) per thread:
+// for each face f met in the row (sorted columns, so a fixed order),
+// y = D_f^-1 b_t,f adds b_t,f . y to S_tt, and the face's other element t'
+// (the other u_0 column of multiplier row f pb) gets S_tt' = b_t',f . y in
+// the next neighbour slot.  Stores 1 / S_tt and the slots (column -1: none).
+__global__ void __launch_bounds__(SV_THREADS) k_schur(int n, int n_lambda, int pb, const int32_t* rp,
+                                                     const int32_t* ci, const double* va, const double* dblk,
+                                                     double* sdi, int32_t* sc_col, double* sc_val) {
+  const int ne = n - n_lambda;
+  for (int t = blockIdx.x * SV_THREADS + threadIdx.x; t < ne; t += gridDim.x * SV_THREADS) {
+    const int row = n_lambda + t;
+    double stt = 0.0;
+    int ns = 0;
+    int32_t nc[S_NB] = {-1, -1, -1};
+    double nv[S_NB] = {0.0, 0.0, 0.0};
+    int k = rp[row];
+    const int kend = rp[row + 1];
+    while (k < kend && ci[k] < n_lambda) {
+      const int f = ci[k] / pb;
+      double bt[PB_MAX], y[PB_MAX];
+#pragma unroll
+      for (int i = 0; i < PB_MAX; ++i) bt[i] = 0.0;
+      while (k < kend && ci[k] < n_lambda && ci[k] / pb == f) {
+        const int i = ci[k] - f * pb;
+#pragma unroll
+        for (int q = 0; q < PB_MAX; ++q)
+          if (q == i) bt[q] = va[k];
+        ++k;
+      }
+      const double* Df = dblk + (int64_t)f * pb * pb;
+#pragma unroll
+      for (int i = 0; i < PB_MAX; ++i) {
+        double v = 0.0;
+        if (i < pb)
+          for (int j = 0; j < pb; ++j) {
+            double bj = 0.0;
+#pragma unroll
+            for (int q = 0; q < PB_MAX; ++q)
+              if (q == j) bj = bt[q];
+            v += Df[i * pb + j] * bj;
+          }
+        y[i] = v;
+      }
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < PB_MAX; ++i) d += bt[i] * y[i];
+      stt += d;
+      // the other element of face f: a u_0 column of multiplier row f pb other than this row
+      int other = -1;
+      for (int kk = rp[f * pb]; kk < rp[f * pb + 1]; ++kk)
+        if (ci[kk] >= n_lambda && ci[kk] != row) other = ci[kk];
+      if (other >= 0 && ns < S_NB) {
+        double o = 0.0;
+#pragma unroll
+        for (int i = 0; i < PB_MAX; ++i) {
+          if (i < pb) {
+            const int kk = find_col(rp, ci, f * pb + i, other);
+            if (kk >= 0) o += va[kk] * y[i];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < S_NB; ++q)
+          if (q == ns) {
+            nc[q] = other - n_lambda;
+            nv[q] = o;
+          }
+        ++ns;
+      }
+    }
+    sdi[t] = stt > 0.0 ? 1.0 / stt : 1.0;
+#pragma unroll
+    for (int q = 0; q < S_NB; ++q) {
+      sc_col[(int64_t)t * S_NB + q] = nc[q];
+      sc_val[(int64_t)t * S_NB + q] = nv[q];
+    }
+  }
+}
+
+// z = P^-1 v and the partials of <z, v>.  Workgroup 0: the u_0 rows, by
+// JACOBI_SWEEPS damped Jacobi sweeps on S from zero with the iterate in LDS
+// (two buffers), or z = v / S_tt when the rows do not fit (jacobi == 0);
+// the other workgroups: the face blocks.
+__global__ void __launch_bounds__(PA_THREADS) k_prec_apply(int n, int n_lambda, int pb, int jacobi,
+                                                          const double* v, double* z, const double* dblk,
+                                                          const double* sdi, const int32_t* sc_col,
+                                                          const double* sc_val, double* part, const double* sc) {
+  __shared__ double red[PA_THREADS / 64];
+  extern __shared__ double xs[];   // 2 (n - n_lambda) when jacobi
+  if (sc[SC_DONE] != 0.0) return;
+  const int ne = n - n_lambda, nf = n_lambda / pb;
+  double acc = 0.0;
+  if (blockIdx.x == 0) {
+    const double* vu = v + n_lambda;
+    if (jacobi) {
+      double* x0 = xs;
+      double* x1 = xs + ne;
+      // each thread's rows t = tid + k PA_THREADS: S row, 1 / S_tt and v_t
+      // in registers when they fit (ne <= PA_ROWS PA_THREADS), else re-read
+      const bool held = ne <= PA_ROWS * PA_THREADS;
+      double rd[PA_ROWS], rv[PA_ROWS], rsv[PA_ROWS][S_NB];
+      int32_t rsc[PA_ROWS][S_NB];
+#pragma unroll
+      for (int k = 0; k < PA_ROWS; ++k) {
+        const int t = threadIdx.x + k * PA_THREADS;
+        const bool in = held && t < ne;
+        rd[k] = in ? sdi[t] : 0.0;
+        rv[k] = in ? vu[t] : 0.0;
+#pragma unroll
+        for (int q = 0; q < S_NB; ++q) {
+          rsc[k][q] = in ? sc_col[(int64_t)t * S_NB + q] : -1;
+          rsv[k][q] = in ? sc_val[(int64_t)t * S_NB + q] : 0.0;
+        }
+        if (in) x0[t] = JACOBI_OMEGA * rd[k] * rv[k];   // first sweep from 0
+      }
+      if (!held)
+        for (int t = threadIdx.x; t < ne; t += PA_THREADS) x0[t] = JACOBI_OMEGA * sdi[t] * vu[t];
+      __syncthreads();
+      for (int sw = 1; sw < JACOBI_SWEEPS; ++sw) {
+        const double* xa = (sw & 1) ? x0 : x1;
+        double* xn = (sw & 1) ? x1 : x0;
+        if (held) {
+#pragma unroll
+          for (int k = 0; k < PA_ROWS; ++k) {
+            const int t = threadIdx.x + k * PA_THREADS;
+            if (t < ne) {
+              double sx = xa[t] / rd[k];
+#pragma unroll
+              for (int q = 0; q < S_NB; ++q)
+                if (rsc[k][q] >= 0) sx += rsv[k][q] * xa[rsc[k][q]];
+              xn[t] = xa[t] + JACOBI_OMEGA * rd[k] * (rv[k] - sx);
+            }
+          }
+        } else {
+          for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
+            const double di = sdi[t];
+            double sx = xa[t] / di;
+#pragma unroll
+            for (int q = 0; q < S_NB; ++q) {
+              const int c = sc_col[(int64_t)t * S_NB + q];
+              if (c >= 0) sx += sc_val[(int64_t)t * S_NB + q] * xa[c];
+            }
+            xn[t] = xa[t] + JACOBI_OMEGA * di * (vu[t] - sx);
+          }
+        }
+        __syncthreads();
+      }
+      const double* xf = (JACOBI_SWEEPS & 1) ? x0 : x1;
+      for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
+        z[n_lambda + t] = xf[t];
+        acc += xf[t] * vu[t];
+      }
+    } else {
+      for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
+        const double zt = sdi[t] * vu[t];
+        z[n_lambda + t] = zt;
+        acc += zt * vu[t];
+      }
+    }
+  } else {
+    for (int f = (blockIdx.x - 1) * PA_THREADS + threadIdx.x; f < nf; f += (gridDim.x - 1) * PA_THREADS) {
+      const double* Df = dblk + (int64_t)f * pb * pb;
+      const double* vf = v + (int64_t)f * pb;
+      double* zf = z + (int64_t)f * pb;
+      for (int i = 0; i < pb; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < pb; ++j) s += Df[i * pb + j] * vf[j];
+        zf[i] = s;
+        acc += s * vf[i];
+      }
+    }
+  }
+  acc = block_reduce(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
 // Start: v_1 = b, z_1 = P^-1 b, partials of <z_1, v_1>; x, w, w_prev, v_0 = 0.
 __global__ void __launch_bounds__(SV_THREADS) k_start(int n, const double* b, const double* dinv, double* v1,
                                                       double* z1, double* v0, double* w, double* wp, double* x,
@@ -158,6 +417,8 @@ __global__ void __launch_bounds__(SV_THREADS) k_spmv_dot(int n, const int32_t* r
 // v_{j+1} = A z_j / g - (delta/g) v_j - (g/g_prev) v_{j-1} (written over
 // v_{j-1}), z_{j+1} = P^-1 v_{j+1}, partials of <z_{j+1}, v_{j+1}>, with
 // g = gamma_j and delta = <A z_j, z_j> / g^2.
+// With face blocks (dinv == nullptr) only v_{j+1} is written here;
+// k_prec_apply forms z_{j+1} and its partials.
 __global__ void __launch_bounds__(SV_THREADS) k_lanczos(int n, const double* y, const double* vj, double* vprev_next,
                                                         const double* dinv, double* znext, const double* part_in,
                                                         int nb, double* part_out, const double* sc) {
@@ -169,11 +430,14 @@ __global__ void __launch_bounds__(SV_THREADS) k_lanczos(int n, const double* y, 
   double acc = 0.0;
   for (int i = blockIdx.x * SV_THREADS + threadIdx.x; i < n; i += gridDim.x * SV_THREADS) {
     const double vn = y[i] * ig - cv * vj[i] - cp * vprev_next[i];
-    const double zn = vn * dinv[i];
     vprev_next[i] = vn;
-    znext[i] = zn;
-    acc += zn * vn;
+    if (dinv) {
+      const double zn = vn * dinv[i];
+      znext[i] = zn;
+      acc += zn * vn;
+    }
   }
+  if (!dinv) return;
   acc = block_reduce(acc, red);
   if (threadIdx.x == 0) part_out[blockIdx.x] = acc;
 }
@@ -285,10 +549,15 @@ __global__ void k_residual_final(const double* part_r, const double* part_b, int
 
 }  // namespace
 
-size_t skeleton_solve_bytes(int n) {
-  // 9 vectors, two partial arrays, scalars
-  return sizeof(double) * ((size_t)9 * n + 3 * SV_MAX_BLOCKS + 2 * SC_COUNT + 8);
+size_t skeleton_solve_bytes(int n, int pb) {
+  // 9 vectors, three partial arrays, scalars; with face blocks the block
+  // inverses (at most n pb values) and S (1 / S_tt, 3 values and 3 columns
+  // per element row: at most 5 n)
+  const size_t blk = pb > 1 ? (size_t)n * pb + 5 * (size_t)n + 64 : 0;
+  return sizeof(double) * ((size_t)9 * n + 3 * SV_MAX_BLOCKS + 2 * SC_COUNT + 8 + blk);
 }
+
+int skeleton_block_max() { return PB_MAX; }
 
 hipError_t skeleton_csr_check(int n, const int32_t* rp, const int32_t* ci, void* work, int* host_bad,
                               hipStream_t st) {
@@ -303,7 +572,7 @@ hipError_t skeleton_csr_check(int n, const int32_t* rp, const int32_t* ci, void*
   return hipStreamSynchronize(st);
 }
 
-hipError_t skeleton_solve(int n, int n_lambda, const int32_t* rp, const int32_t* ci, const double* va,
+hipError_t skeleton_solve(int n, int n_lambda, int pb, const int32_t* rp, const int32_t* ci, const double* va,
                           const double* b, double* x, double tol, int max_iters, void* work, double* host_sc,
                           int* iters, double* relres, hipStream_t st) {
   double* wk = static_cast<double*>(work);
@@ -321,6 +590,17 @@ hipError_t skeleton_solve(int n, int n_lambda, const int32_t* rp, const int32_t*
   double* scA = part3 + SV_MAX_BLOCKS;   // two scalar sets, alternating by step
   double* scB = scA + SC_COUNT;
   double* res_out = scB + SC_COUNT;
+  // face blocks (pb > 1): D^-1 per face, then S on the u_0 rows
+  const bool blocked = pb > 1 && n_lambda > 0 && n_lambda % pb == 0;
+  const int ne = n - n_lambda, nf = blocked ? n_lambda / pb : 0;
+  double* dblk = res_out + 8;
+  double* sdi = dblk + (size_t)n_lambda * (blocked ? pb : 0);
+  double* sc_val = sdi + ne;
+  int32_t* sc_col = reinterpret_cast<int32_t*>(sc_val + (size_t)S_NB * ne);
+  // the Jacobi sweeps hold two copies of the u_0 iterate in one workgroup's LDS
+  const size_t jac_lds = sizeof(double) * 2 * (size_t)ne;
+  const int jacobi = blocked && ne > 0 && jac_lds <= 128 * 1024 ? 1 : 0;
+  const int nbp = 1 + std::max(1, std::min(SV_MAX_BLOCKS - 1, (nf + PA_THREADS - 1) / PA_THREADS));
   const int nb = std::max(1, std::min(SV_MAX_BLOCKS, (n + SV_THREADS - 1) / SV_THREADS));
   const int nbr = std::max(1, std::min(SV_MAX_BLOCKS, (n + SV_THREADS / ROW_LANES - 1) / (SV_THREADS / ROW_LANES)));
   hipError_t e;
@@ -331,10 +611,37 @@ hipError_t skeleton_solve(int n, int n_lambda, const int32_t* rp, const int32_t*
   SV_CHECK();
   if (n > n_lambda) hipLaunchKernelGGL(k_prec_u0, dim3(nb), dim3(SV_THREADS), 0, st, n, n_lambda, rp, ci, va, dinv);
   SV_CHECK();
+  if (blocked) {
+    if (jacobi) {
+      e = hipFuncSetAttribute((const void*)k_prec_apply, hipFuncAttributeMaxDynamicSharedMemorySize, (int)jac_lds);
+      if (e != hipSuccess) return e;
+    }
+    const int nbf = std::max(1, std::min(SV_MAX_BLOCKS, (nf + SV_THREADS - 1) / SV_THREADS));
+    hipLaunchKernelGGL(k_blk_inv, dim3(nbf), dim3(SV_THREADS), 0, st, nf, pb, rp, ci, va, dblk);
+    SV_CHECK();
+    if (ne > 0) {
+      const int nbe = std::max(1, std::min(SV_MAX_BLOCKS, (ne + SV_THREADS - 1) / SV_THREADS));
+      hipLaunchKernelGGL(k_schur, dim3(nbe), dim3(SV_THREADS), 0, st, n, n_lambda, pb, rp, ci, va, dblk, sdi, sc_col,
+                         sc_val);
+      SV_CHECK();
+    }
+  }
+  // z = P^-1 v with its partials, for the face-block preconditioner
+  auto prec_apply = [&](const double* v, double* z, double* part, const double* sc, hipStream_t s2) {
+    hipLaunchKernelGGL(k_prec_apply, dim3(nbp), dim3(PA_THREADS), jacobi ? jac_lds : 0, s2, n, n_lambda, pb, jacobi,
+                       v, z, dblk, sdi, sc_col, sc_val, part, sc);
+  };
   // v_j in vA, v_{j-1} in vB; z_j in zA; w_j in wA, w_{j-1} in wB
   hipLaunchKernelGGL(k_start, dim3(nb), dim3(SV_THREADS), 0, st, n, b, dinv, vA, zA, vB, wA, wB, x, part1);
   SV_CHECK();
-  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(SV_THREADS), 0, st, part1, nb, scA);
+  if (blocked) {
+    // scalars not set yet: a zeroed slot reads as "not done"
+    e = hipMemsetAsync(scA, 0, sizeof(double) * SC_COUNT, st);
+    if (e != hipSuccess) return e;
+    prec_apply(vA, zA, part1, scA, st);
+    SV_CHECK();
+  }
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(SV_THREADS), 0, st, part1, blocked ? nbp : nb, scA);
   SV_CHECK();
   // Step j reads the buffers in the roles below and swaps them: an even
   // number of steps returns every buffer to its role, so a chunk of an even
@@ -346,10 +653,11 @@ hipError_t skeleton_solve(int n, int n_lambda, const int32_t* rp, const int32_t*
     hipError_t e2 = hipSuccess;
     for (int k = 0; k < count && e2 == hipSuccess; ++k) {
       hipLaunchKernelGGL(k_spmv_dot, dim3(nbr), dim3(SV_THREADS), 0, s, n, rp, ci, va, r.zj, y, part2, r.si);
-      hipLaunchKernelGGL(k_lanczos, dim3(nb), dim3(SV_THREADS), 0, s, n, y, r.vj, r.vp, dinv, r.zn, part2, nbr,
-                         part3, r.si);
-      hipLaunchKernelGGL(k_step, dim3(nb), dim3(SV_THREADS), 0, s, n, part2, nbr, part3, nb, r.si, r.so, r.zj, r.wj,
-                         r.wp, x);
+      hipLaunchKernelGGL(k_lanczos, dim3(nb), dim3(SV_THREADS), 0, s, n, y, r.vj, r.vp, blocked ? nullptr : dinv,
+                         r.zn, part2, nbr, part3, r.si);
+      if (blocked) prec_apply(r.vp, r.zn, part3, r.si, s);   // v_{j+1} is in r.vp now
+      hipLaunchKernelGGL(k_step, dim3(nb), dim3(SV_THREADS), 0, s, n, part2, nbr, part3, blocked ? nbp : nb, r.si,
+                         r.so, r.zj, r.wj, r.wp, x);
       e2 = hipGetLastError();
       std::swap(r.vj, r.vp);   // v_{j+1} was written over v_{j-1}
       std::swap(r.zj, r.zn);

@@ -82,6 +82,9 @@ class SkeletonSystem:
         self.col_idx = torch.as_tensor(self.col_idx_h, **i32)
         self.nnz = int(self.row_ptr_h[-1])
         self.n_lambda = self.n_rows - mesh["elems"].shape[0]   # multiplier rows come first
+        # DoFs of one face: consecutive multiplier rows, the solve's preconditioner blocks
+        # (faces with more than 8 fall back to the diagonal preconditioner)
+        self.face_dofs = m * (l + 1) if m * (l + 1) <= 8 else 1
         self.device = device
 
     def scatter(self, ctx, db, out, vals=None, rhs=None, clear: bool = True):
@@ -117,12 +120,14 @@ class SkeletonSystem:
         ctx.reconstruct(db, out["X"], self.gdof, self.erow, sol, self.n_rows, u, out["info"])
         return u
 
-    def solve(self, ctx, vals, rhs, sol=None, tol: float = 1e-12, max_iters: int = 20000):
+    def solve(self, ctx, vals, rhs, sol=None, tol: float = 1e-12, max_iters: int = 20000, lambda_block=None):
         """mhm_skeleton_solve on the scattered system; returns (sol, iterations,
-        relative residual)."""
+        relative residual).  lambda_block: the preconditioner's face blocks,
+        by default one face's m (l + 1) DoFs (1: the diagonal preconditioner)."""
         import torch
         if sol is None:
             sol = torch.empty(self.n_rows, dtype=torch.float64, device=self.device)
+        pb = self.face_dofs if lambda_block is None else int(lambda_block)
         it, rr = ctx.skeleton_solve(self.n_rows, self.n_lambda, self.row_ptr, self.col_idx, vals, rhs, sol, tol,
-                                    max_iters)
+                                    max_iters, pb)
         return sol, it, rr
