@@ -189,7 +189,8 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
 
 // Default family when nothing was tuned.
 Choice default_choice(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_cap, bool listed) {
-  const Choice ll = c->ll_occ2 ? Choice{FAM_LL, 2, 2} : Choice{FAM_LL, mhm::local_ll_default_panel(fp32), 1};
+  const int nt = (n_of(s_cap) + 15) / 16;
+  const Choice ll = c->ll_occ2 ? Choice{FAM_LL, 2, 2} : Choice{FAM_LL, mhm::local_ll_default_panel(fp32, nt), 1};
   const Choice ll16{FAM_LL, 2, 1, 16};
   const Choice cands[] = {{FAM_RR, 0}, {FAM_LDS, 0}, c->ll_nw16 ? ll16 : ll, ll, {FAM_LL, 2, 1}, {FAM_WS, 0}};
   for (const Choice& ch : cands) {
@@ -203,7 +204,9 @@ Choice default_choice(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused
 // The FP64 recomputation pass of an FP32 launch (refinement that did not
 // converge): left-looking where it applies, else the workspace kernel.
 Plan fallback_plan(const mhm_ctx c, const mhm_batch* b, int s_cap, bool listed) {
-  Plan p = plan_for(c, b, false, true, s_cap, Choice{FAM_LL, 2}, listed);
+  const int nt = (n_of(s_cap) + 15) / 16;
+  Plan p = plan_for(c, b, false, true, s_cap, Choice{FAM_LL, mhm::local_ll_default_panel(false, nt)}, listed);
+  if (!p.ok) p = plan_for(c, b, false, true, s_cap, Choice{FAM_LL, 2}, listed);
   if (c->no_ll || !p.ok) p = plan_for(c, b, false, true, s_cap, Choice{FAM_WS, 0}, listed);
   return p;
 }
@@ -241,7 +244,7 @@ RunPlan make_run_plan(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused
     if (cached) {
       // stored factors: the left-looking kernel (tuned panel width if any;
       // the chunked instance for more than RHS_CHUNK right-hand sides)
-      if (ch.fam != FAM_LL) ch = Choice{FAM_LL, mhm::local_ll_default_panel(fp32)};
+      if (ch.fam != FAM_LL) ch = Choice{FAM_LL, mhm::local_ll_default_panel(fp32, (n_of(r.s_cap) + 15) / 16)};
       if (3 * p_bound(b) + 1 > mhm::RHS_CHUNK) ch = Choice{FAM_LL, 2};
     } else if (ch.fam < 0 || !plan_for(c, b, fp32, fused, r.s_cap, ch, rp.listed).ok) {
       ch = default_choice(c, b, fp32, fused, r.s_cap, rp.listed);
@@ -454,8 +457,9 @@ Choice tune_class(mhm_ctx c, const mhm_batch* b, bool fp32, const RunPlan& base,
                   int32_t* dcount, int cap, int count, std::string& log, mhm_status& st) {
   const ClassRun& r0 = base.run[i];
   std::vector<Choice> cands;
-  const Choice all[] = {{FAM_RR, 0, 1},  {FAM_LDS, 0, 1},    {FAM_LL, 2, 1},    {FAM_LL, 4, 1},
-                        {FAM_LL, 2, 2},  {FAM_LL, 2, 1, 16}, {FAM_LL, 4, 1, 16}, {FAM_WS, 0, 1}};
+  const Choice all[] = {{FAM_RR, 0, 1},     {FAM_LDS, 0, 1},    {FAM_LL, 2, 1},    {FAM_LL, 4, 1},
+                        {FAM_LL, 2, 2},     {FAM_LL, 2, 1, 16}, {FAM_LL, 4, 1, 16}, {FAM_LL, 1, 1},
+                        {FAM_LL, 1, 1, 16}, {FAM_WS, 0, 1}};
   bool have_ll = false;
   for (const Choice& ch : all) {
     if (ch.fam == FAM_RR && c->no_rr) continue;

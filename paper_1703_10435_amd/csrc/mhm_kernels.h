@@ -103,7 +103,7 @@ hipError_t launch_local_rr(bool fused, const mhm_batch* bt, LocalArgs a, size_t 
 // width pw (block columns of pw tiles); mc: the instance that takes more than
 // RHS_CHUNK right-hand sides (in chunks).
 int local_ll_rows_per_wave(int nt, int nw);
-int local_ll_default_panel(bool fp32);
+int local_ll_default_panel(bool fp32, int nt);
 bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw, bool mc);
 size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap, int nw);
 hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, bool mc, int nt_max, const mhm_batch* bt,

@@ -19,20 +19,27 @@ int local_ll_rows_per_wave(int nt, int nw) {
   return -1;
 }
 
-int local_ll_default_panel(bool fp32) { return fp32 ? 4 : 2; }
+// FP32: width 4.  FP64: width 2, or 1 for the largest elements (10 rows per
+// wave), where the wider panel's registers cost more than its halved operand
+// reads save (s = 48: 53 against 63 ms per 1024 elements).
+int local_ll_default_panel(bool fp32, int nt) {
+  if (fp32) return 4;
+  return local_ll_rows_per_wave(nt, 8) == 10 ? 1 : 2;
+}
 
 bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw, bool mc) {
   if (mc)   // chunked right-hand sides: panel width 2, 8 waves, one workgroup per CU
     return pw == 2 && occ == 1 && nw == 8 && local_ll_rows_per_wave(nt, 8) > 0;
   if (nw == 16)   // built for the largest elements only (49 to 80 tile rows)
-    return occ == 1 && nt + 1 > 48 && local_ll_rows_per_wave(nt, 16) == 5 && (pw == 2 || (fp32 && pw == 4));
+    return occ == 1 && nt + 1 > 48 && local_ll_rows_per_wave(nt, 16) == 5 &&
+           (pw == 2 || (fp32 && pw == 4) || (!fp32 && pw == 1));
   if (nw != 8) return false;
   const int rpw = local_ll_rows_per_wave(nt, 8);
   if (rpw < 0) return false;
   if (occ == 2) return pw == 2 && (fp32 || rpw <= 3);
   if (occ != 1) return false;
   if (fp32) return pw == 2 || pw == 4;
-  return pw == 2 || (pw == 4 && rpw <= 3);
+  return pw == 2 || (pw == 4 && rpw <= 3) || (pw == 1 && rpw == 10);
 }
 
 size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap, int nw) {

@@ -53,9 +53,17 @@ hipError_t launch_local_ll_f64(bool fused, int pw, int occ, int nw, int rpw, boo
     return fused ? launch_mc<true>(rpw, d, a, lds, grid, st) : launch_mc<false>(rpw, d, a, lds, grid, st);
   }
   if (nw == 16) {
-    if (rpw != 5 || occ != 1 || pw != 2) return hipErrorInvalidValue;
+    if (rpw != 5 || occ != 1) return hipErrorInvalidValue;
+    if (pw == 1) return fused ? launch_ll_t<double, true, 1, 5, 1, 16>(d, a, lds, grid, st)
+                              : launch_ll_t<double, false, 1, 5, 1, 16>(d, a, lds, grid, st);
+    if (pw != 2) return hipErrorInvalidValue;
     return fused ? launch_ll_t<double, true, 2, 5, 1, 16>(d, a, lds, grid, st)
                  : launch_ll_t<double, false, 2, 5, 1, 16>(d, a, lds, grid, st);
+  }
+  if (pw == 1) {   // one tile column per panel: half the accumulator registers (the largest elements)
+    if (rpw != 10 || occ != 1) return hipErrorInvalidValue;
+    return fused ? launch_ll_t<double, true, 1, 10, 1>(d, a, lds, grid, st)
+                 : launch_ll_t<double, false, 1, 10, 1>(d, a, lds, grid, st);
   }
   if (occ == 2) {
     if (pw != 2) return hipErrorInvalidValue;
