@@ -551,9 +551,9 @@ __global__ void k_residual_final(const double* part_r, const double* part_b, int
 
 size_t skeleton_solve_bytes(int n, int pb) {
   // 9 vectors, three partial arrays, scalars; with face blocks the block
-  // inverses (at most n pb values) and S (1 / S_tt, 3 values and 3 columns
-  // per element row: at most 5 n)
-  const size_t blk = pb > 1 ? (size_t)n * pb + 5 * (size_t)n + 64 : 0;
+  // inverses (n_lambda pb <= n pb values) and S per element row (1 / S_tt,
+  // 3 values, 3 int32 columns: 5.5 doubles' worth, at most 6 n)
+  const size_t blk = pb > 1 ? (size_t)n * pb + 6 * (size_t)n + 64 : 0;
   return sizeof(double) * ((size_t)9 * n + 3 * SV_MAX_BLOCKS + 2 * SC_COUNT + 8 + blk);
 }
 
