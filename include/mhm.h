@@ -174,8 +174,9 @@ mhm_status mhm_local_factor_solve(mhm_ctx ctx, const mhm_batch* batch, mhm_prec 
 
 /* Step a6: the element's contribution to eq. (6) from its solutions X.
  * M [n_elem][NImax*NImax] (column-major NImax x NImax, zero padded),
- * E [n_elem][NImax], B [n_elem][NImax], F [n_elem]; NImax = 3(l_max+1).
- * Elements whose info[e] != 0 on entry are skipped (info may be NULL). */
+ * E [n_elem][NImax], B [n_elem][NImax], F [n_elem]; NImax = 3 p_max
+ * (3 (l_max+1) when p_max is 0).  Elements whose info[e] on entry is other
+ * than 0 or -1 are skipped (info may be NULL). */
 mhm_status mhm_skeleton_contrib(mhm_ctx ctx, const mhm_batch* batch, const double* X,
                                 double* M, double* E, double* B, double* F,
                                 const int32_t* info);
@@ -192,7 +193,7 @@ mhm_status mhm_local_batch_run(mhm_ctx ctx, const mhm_batch* batch, mhm_prec pre
  * element contributions (the reduce step of reduceLocalProblems,
  * Algorithm 1) and computeSolution, eq. (4).  The global numbering is the
  * caller's; both calls take
- *   gdof   [n_elem * NImax] device int32, NImax = 3 (l_max + 1): global row
+ *   gdof   [n_elem * NImax] device int32, NImax as for the blocks: global row
  *          of local face DoF a of element e (entries a >= N_I of the element
  *          are not read),
  *   erow   [n_elem] device int32: global row of the element's constant u_0,
