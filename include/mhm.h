@@ -226,10 +226,10 @@ mhm_status mhm_reconstruct(mhm_ctx ctx, const mhm_batch* batch, const double* X,
  * [E; F] with M negative (semi-)definite.  Preconditioned MINRES (the
  * minimal-residual method for symmetric indefinite systems) with a block
  * diagonal preconditioner diag(D, S~): D the lambda_block x lambda_block
- * diagonal blocks of -M (one face's DoFs), S~^-1 a fixed number of damped
- * Jacobi sweeps on S = B D^-1 B^T (the u_0 rows; diag(S) alone when the
- * element count is above about 8,000); with lambda_block = 1, D = |diag M|
- * and S~ = diag(S).  The paper uses sparse direct solvers and names hybrid
+ * diagonal blocks of -M (one face's DoFs), S~^-1 a fixed number of
+ * Chebyshev steps on S = B D^-1 B^T (the u_0 rows; damped Jacobi sweeps
+ * above 4,096 elements, diag(S) alone above 8,192); with lambda_block = 1,
+ * D = |diag M| and S~ = diag(S).  The paper uses sparse direct solvers and names hybrid
  * direct-iterative ones as future work (Section 6).
  *   n_rows, n_lambda  rows of the system; rows < n_lambda are multiplier
  *             rows (M, B^T), the others u_0 rows (B, 0), as numbered for

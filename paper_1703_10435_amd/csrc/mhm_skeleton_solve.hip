@@ -12,12 +12,13 @@
 //     D = the face blocks of -M, inverted once (lambda_block = 1: |diag(M)|);
 //   - u_0 rows: S = B D^-1 B^T (the Schur complement of the face-block
 //     approximation), assembled once, one row per element with its up to
-//     three face neighbours; S~^-1 is a fixed number of damped Jacobi sweeps
-//     on S from zero (a fixed SPD polynomial in S), run by one workgroup
-//     with the iterate in LDS.  With lambda_block = 1, S~ = diag(S).
+//     three face neighbours; S~^-1 is a fixed number of Chebyshev steps on
+//     S from zero (damped Jacobi sweeps above 4096 elements), a fixed SPD
+//     polynomial in S, run by one workgroup with the iterate in LDS.  With
+//     lambda_block = 1, S~ = diag(S).
 // The u_0 block of the saddle point is an elliptic operator on the coarse
 // mesh; its diagonal alone leaves MINRES thousands of steps on C2's system,
-// the sweeps a few hundred.
+// the Chebyshev steps a few hundred.
 //
 // One MINRES step is three launches (four with face blocks): the CSR product
 // with its dot product, the Lanczos vector with the next dot product (with
@@ -44,6 +45,8 @@ constexpr int PA_THREADS = 1024;  // preconditioner launch
 constexpr int PA_ROWS = 4;        // u_0 rows per thread held in registers through the sweeps
 constexpr int JACOBI_SWEEPS = 16;
 constexpr double JACOBI_OMEGA = 0.7;
+constexpr int CHEB_STEPS = 16;            // Chebyshev steps (one product with S each)
+constexpr double CHEB_RATIO = 300.0;      // assumed lambda_max / lambda_min of D^-1 S
 
 // scalar slots
 enum : int {
@@ -261,9 +264,11 @@ __global__ void __launch_bounds__(SV_THREADS) k_schur(int n, int n_lambda, int p
 }
 
 // z = P^-1 v and the partials of <z, v>.  Workgroup 0: the u_0 rows, by
-// JACOBI_SWEEPS damped Jacobi sweeps on S from zero with the iterate in LDS
-// (two buffers), or z = v / S_tt when the rows do not fit (jacobi == 0);
-// the other workgroups: the face blocks.
+// CHEB_STEPS Chebyshev steps on S from zero when each thread can hold its
+// rows in registers (up to PA_ROWS PA_THREADS rows), else JACOBI_SWEEPS
+// damped Jacobi sweeps, with the shared vector in LDS (two buffers); z = v /
+// S_tt when even that does not fit (jacobi == 0).  The other workgroups:
+// the face blocks.
 __global__ void __launch_bounds__(PA_THREADS) k_prec_apply(int n, int n_lambda, int pb, int jacobi,
                                                           const double* v, double* z, const double* dblk,
                                                           const double* sdi, const int32_t* sc_col,
@@ -294,27 +299,78 @@ __global__ void __launch_bounds__(PA_THREADS) k_prec_apply(int n, int n_lambda, 
           rsc[k][q] = in ? sc_col[(int64_t)t * S_NB + q] : -1;
           rsv[k][q] = in ? sc_val[(int64_t)t * S_NB + q] : 0.0;
         }
-        if (in) x0[t] = JACOBI_OMEGA * rd[k] * rv[k];   // first sweep from 0
       }
-      if (!held)
-        for (int t = threadIdx.x; t < ne; t += PA_THREADS) x0[t] = JACOBI_OMEGA * sdi[t] * vu[t];
-      __syncthreads();
-      for (int sw = 1; sw < JACOBI_SWEEPS; ++sw) {
-        const double* xa = (sw & 1) ? x0 : x1;
-        double* xn = (sw & 1) ? x1 : x0;
-        if (held) {
+      if (held) {
+        // Chebyshev iteration on S x = v_u (Jacobi-scaled, x_0 = 0) over the
+        // interval [lmax / CHEB_RATIO, lmax], lmax the Gershgorin bound of
+        // D^-1 S: a fixed polynomial p(D^-1 S) D^-1, positive on (0, lmax],
+        // so the preconditioner stays SPD; it reduces the error of the low
+        // modes far faster than Jacobi sweeps of the same count.
+        double gl = 0.0, xr[PA_ROWS], rr[PA_ROWS];
+#pragma unroll
+        for (int k = 0; k < PA_ROWS; ++k) {
+          const int t = threadIdx.x + k * PA_THREADS;
+          double g = 0.0;
+          if (t < ne) {
+            g = 1.0;
+#pragma unroll
+            for (int q = 0; q < S_NB; ++q) g += fabs(rsv[k][q]) * rd[k];
+          }
+          gl = fmax(gl, g);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) gl = fmax(gl, __shfl_xor(gl, o, 64));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = gl;
+        __syncthreads();
+        double lmax = 0.0;
+        for (int w = 0; w < PA_THREADS / 64; ++w) lmax = fmax(lmax, red[w]);
+        lmax = lmax > 0.0 ? lmax : 1.0;
+        const double lmin = lmax / CHEB_RATIO;
+        const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma1 = theta / delta;
+        double rho = 1.0 / sigma1;
+#pragma unroll
+        for (int k = 0; k < PA_ROWS; ++k) {
+          const int t = threadIdx.x + k * PA_THREADS;
+          xr[k] = 0.0;
+          rr[k] = rv[k];
+          if (t < ne) x0[t] = rd[k] * rv[k] / theta;   // d_0
+        }
+        __syncthreads();
+        for (int it = 0; it < CHEB_STEPS; ++it) {
+          const double* dc = (it & 1) ? x1 : x0;
+          double* dn = (it & 1) ? x0 : x1;
+          const double rho_n = 1.0 / (2.0 * sigma1 - rho);
 #pragma unroll
           for (int k = 0; k < PA_ROWS; ++k) {
             const int t = threadIdx.x + k * PA_THREADS;
             if (t < ne) {
-              double sx = xa[t] / rd[k];
+              const double dt = dc[t];
+              double sd = dt / rd[k];
 #pragma unroll
               for (int q = 0; q < S_NB; ++q)
-                if (rsc[k][q] >= 0) sx += rsv[k][q] * xa[rsc[k][q]];
-              xn[t] = xa[t] + JACOBI_OMEGA * rd[k] * (rv[k] - sx);
+                if (rsc[k][q] >= 0) sd += rsv[k][q] * dc[rsc[k][q]];
+              xr[k] += dt;
+              rr[k] -= sd;
+              dn[t] = rho_n * rho * dt + 2.0 * rho_n / delta * rd[k] * rr[k];
             }
           }
-        } else {
+          rho = rho_n;
+          __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < PA_ROWS; ++k) {
+          const int t = threadIdx.x + k * PA_THREADS;
+          if (t < ne) {
+            z[n_lambda + t] = xr[k];
+            acc += xr[k] * vu[t];
+          }
+        }
+      } else {
+        for (int t = threadIdx.x; t < ne; t += PA_THREADS) x0[t] = JACOBI_OMEGA * sdi[t] * vu[t];
+        __syncthreads();
+        for (int sw = 1; sw < JACOBI_SWEEPS; ++sw) {
+          const double* xa = (sw & 1) ? x0 : x1;
+          double* xn = (sw & 1) ? x1 : x0;
           for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
             const double di = sdi[t];
             double sx = xa[t] / di;
@@ -325,13 +381,13 @@ __global__ void __launch_bounds__(PA_THREADS) k_prec_apply(int n, int n_lambda, 
             }
             xn[t] = xa[t] + JACOBI_OMEGA * di * (vu[t] - sx);
           }
+          __syncthreads();
         }
-        __syncthreads();
-      }
-      const double* xf = (JACOBI_SWEEPS & 1) ? x0 : x1;
-      for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
-        z[n_lambda + t] = xf[t];
-        acc += xf[t] * vu[t];
+        const double* xf = (JACOBI_SWEEPS & 1) ? x0 : x1;
+        for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
+          z[n_lambda + t] = xf[t];
+          acc += xf[t] * vu[t];
+        }
       }
     } else {
       for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
