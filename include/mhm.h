@@ -227,9 +227,8 @@ mhm_status mhm_reconstruct(mhm_ctx ctx, const mhm_batch* batch, const double* X,
  * minimal-residual method for symmetric indefinite systems) with a block
  * diagonal preconditioner diag(D, S~): D the lambda_block x lambda_block
  * diagonal blocks of -M (one face's DoFs), S~^-1 a fixed number of
- * Chebyshev steps on S = B D^-1 B^T (the u_0 rows; damped Jacobi sweeps
- * above 4,096 elements, diag(S) alone above 8,192); with lambda_block = 1,
- * D = |diag M| and S~ = diag(S).  The paper uses sparse direct solvers and names hybrid
+ * Chebyshev steps on S = B D^-1 B^T (the u_0 rows; diag(S) alone above
+ * 8,192 elements); with lambda_block = 1, D = |diag M| and S~ = diag(S).  The paper uses sparse direct solvers and names hybrid
  * direct-iterative ones as future work (Section 6).
  *   n_rows, n_lambda  rows of the system; rows < n_lambda are multiplier
  *             rows (M, B^T), the others u_0 rows (B, 0), as numbered for
@@ -251,7 +250,7 @@ mhm_status mhm_reconstruct(mhm_ctx ctx, const mhm_batch* batch, const double* X,
  *             relative residual ||rhs - K sol||_2 / ||rhs||_2.
  * A singular but consistent system (multiplier block rank deficient, l >= s)
  * is fine: u_0, and u of mhm_reconstruct, are unique.  Uses the context's
- * workspace ((15 + lambda_block) n_rows doubles at most, plus a few KB);
+ * workspace ((17 + lambda_block) n_rows doubles at most, plus a few KB);
  * synchronises the stream (the host reads the residual estimate every 16
  * steps); deterministic for a given launch configuration. */
 mhm_status mhm_skeleton_solve(mhm_ctx ctx, int32_t n_rows, int32_t n_lambda, int32_t lambda_block,

@@ -13,9 +13,9 @@
 //   - u_0 rows: S = B D^-1 B^T (the Schur complement of the face-block
 //     approximation), assembled once, one row per element with its up to
 //     three face neighbours; S~^-1 is a fixed number of Chebyshev steps on
-//     S from zero (damped Jacobi sweeps above 4096 elements), a fixed SPD
-//     polynomial in S, run by one workgroup with the iterate in LDS.  With
-//     lambda_block = 1, S~ = diag(S).
+//     S from zero, a fixed SPD polynomial in S, run by one workgroup with
+//     the search direction in LDS (up to 8192 elements; diag(S) above).
+//     With lambda_block = 1, S~ = diag(S).
 // The u_0 block of the saddle point is an elliptic operator on the coarse
 // mesh; its diagonal alone leaves MINRES thousands of steps on C2's system,
 // the Chebyshev steps a few hundred.
@@ -43,8 +43,6 @@ constexpr int PB_MAX = 8;      // largest face block of the preconditioner
 constexpr int S_NB = 3;        // face neighbours of an element in S
 constexpr int PA_THREADS = 1024;  // preconditioner launch
 constexpr int PA_ROWS = 4;        // u_0 rows per thread held in registers through the sweeps
-constexpr int JACOBI_SWEEPS = 16;
-constexpr double JACOBI_OMEGA = 0.7;
 constexpr int CHEB_STEPS = 16;            // Chebyshev steps (one product with S each)
 constexpr double CHEB_RATIO = 300.0;      // assumed lambda_max / lambda_min of D^-1 S
 
@@ -264,15 +262,13 @@ __global__ void __launch_bounds__(SV_THREADS) k_schur(int n, int n_lambda, int p
 }
 
 // z = P^-1 v and the partials of <z, v>.  Workgroup 0: the u_0 rows, by
-// CHEB_STEPS Chebyshev steps on S from zero when each thread can hold its
-// rows in registers (up to PA_ROWS PA_THREADS rows), else JACOBI_SWEEPS
-// damped Jacobi sweeps, with the shared vector in LDS (two buffers); z = v /
-// S_tt when even that does not fit (jacobi == 0).  The other workgroups:
-// the face blocks.
+// CHEB_STEPS Chebyshev steps on S from zero (jacobi != 0: the shared vector
+// fits in LDS), else z = v / S_tt.  The other workgroups: the face blocks.
 __global__ void __launch_bounds__(PA_THREADS) k_prec_apply(int n, int n_lambda, int pb, int jacobi,
                                                           const double* v, double* z, const double* dblk,
                                                           const double* sdi, const int32_t* sc_col,
-                                                          const double* sc_val, double* part, const double* sc) {
+                                                          const double* sc_val, double* cx, double* cr,
+                                                          double* part, const double* sc) {
   __shared__ double red[PA_THREADS / 64];
   extern __shared__ double xs[];   // 2 (n - n_lambda) when jacobi
   if (sc[SC_DONE] != 0.0) return;
@@ -281,65 +277,76 @@ __global__ void __launch_bounds__(PA_THREADS) k_prec_apply(int n, int n_lambda, 
   if (blockIdx.x == 0) {
     const double* vu = v + n_lambda;
     if (jacobi) {
+      // Chebyshev iteration on S x = v_u (Jacobi-scaled, x_0 = 0) over the
+      // interval [lmax / CHEB_RATIO, lmax], lmax the Gershgorin bound of
+      // D^-1 S: a fixed polynomial p(D^-1 S) D^-1, positive on (0, lmax],
+      // so the preconditioner stays SPD; it reduces the error of the low
+      // modes far faster than Jacobi sweeps of the same count.  The search
+      // direction is shared through LDS (two buffers).  Each thread's rows
+      // t = tid + k PA_THREADS (S row, 1 / S_tt, v_t, iterate, residual) stay
+      // in registers when they fit (ne <= PA_ROWS PA_THREADS); otherwise the
+      // rows are re-read each step and the iterate and residual live in the
+      // workspace (cx, cr: each thread touches only its own rows).
       double* x0 = xs;
       double* x1 = xs + ne;
-      // each thread's rows t = tid + k PA_THREADS: S row, 1 / S_tt and v_t
-      // in registers when they fit (ne <= PA_ROWS PA_THREADS), else re-read
       const bool held = ne <= PA_ROWS * PA_THREADS;
-      double rd[PA_ROWS], rv[PA_ROWS], rsv[PA_ROWS][S_NB];
+      double rd[PA_ROWS], rv[PA_ROWS], rsv[PA_ROWS][S_NB], xr[PA_ROWS], rr[PA_ROWS];
       int32_t rsc[PA_ROWS][S_NB];
+      double gl = 0.0;
 #pragma unroll
       for (int k = 0; k < PA_ROWS; ++k) {
         const int t = threadIdx.x + k * PA_THREADS;
         const bool in = held && t < ne;
         rd[k] = in ? sdi[t] : 0.0;
         rv[k] = in ? vu[t] : 0.0;
+        double g = in ? 1.0 : 0.0;
 #pragma unroll
         for (int q = 0; q < S_NB; ++q) {
           rsc[k][q] = in ? sc_col[(int64_t)t * S_NB + q] : -1;
           rsv[k][q] = in ? sc_val[(int64_t)t * S_NB + q] : 0.0;
+          g += fabs(rsv[k][q]) * rd[k];
         }
+        gl = fmax(gl, g);
+        xr[k] = 0.0;
+        rr[k] = rv[k];
       }
-      if (held) {
-        // Chebyshev iteration on S x = v_u (Jacobi-scaled, x_0 = 0) over the
-        // interval [lmax / CHEB_RATIO, lmax], lmax the Gershgorin bound of
-        // D^-1 S: a fixed polynomial p(D^-1 S) D^-1, positive on (0, lmax],
-        // so the preconditioner stays SPD; it reduces the error of the low
-        // modes far faster than Jacobi sweeps of the same count.
-        double gl = 0.0, xr[PA_ROWS], rr[PA_ROWS];
+      if (!held)
+        for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
+          double g = 1.0;
 #pragma unroll
-        for (int k = 0; k < PA_ROWS; ++k) {
-          const int t = threadIdx.x + k * PA_THREADS;
-          double g = 0.0;
-          if (t < ne) {
-            g = 1.0;
-#pragma unroll
-            for (int q = 0; q < S_NB; ++q) g += fabs(rsv[k][q]) * rd[k];
-          }
+          for (int q = 0; q < S_NB; ++q) g += fabs(sc_val[(int64_t)t * S_NB + q]) * sdi[t];
           gl = fmax(gl, g);
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) gl = fmax(gl, __shfl_xor(gl, o, 64));
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = gl;
-        __syncthreads();
-        double lmax = 0.0;
-        for (int w = 0; w < PA_THREADS / 64; ++w) lmax = fmax(lmax, red[w]);
-        lmax = lmax > 0.0 ? lmax : 1.0;
-        const double lmin = lmax / CHEB_RATIO;
-        const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma1 = theta / delta;
-        double rho = 1.0 / sigma1;
+      for (int o = 32; o > 0; o >>= 1) gl = fmax(gl, __shfl_xor(gl, o, 64));
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = gl;
+      __syncthreads();
+      double lmax = 0.0;
+      for (int w = 0; w < PA_THREADS / 64; ++w) lmax = fmax(lmax, red[w]);
+      lmax = lmax > 0.0 ? lmax : 1.0;
+      const double lmin = lmax / CHEB_RATIO;
+      const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma1 = theta / delta;
+      double rho = 1.0 / sigma1;
+      if (held) {
 #pragma unroll
         for (int k = 0; k < PA_ROWS; ++k) {
           const int t = threadIdx.x + k * PA_THREADS;
-          xr[k] = 0.0;
-          rr[k] = rv[k];
           if (t < ne) x0[t] = rd[k] * rv[k] / theta;   // d_0
         }
-        __syncthreads();
-        for (int it = 0; it < CHEB_STEPS; ++it) {
-          const double* dc = (it & 1) ? x1 : x0;
-          double* dn = (it & 1) ? x0 : x1;
-          const double rho_n = 1.0 / (2.0 * sigma1 - rho);
+      } else {
+        for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
+          cx[t] = 0.0;
+          cr[t] = vu[t];
+          x0[t] = sdi[t] * vu[t] / theta;
+        }
+      }
+      __syncthreads();
+      for (int it = 0; it < CHEB_STEPS; ++it) {
+        const double* dc = (it & 1) ? x1 : x0;
+        double* dn = (it & 1) ? x0 : x1;
+        const double rho_n = 1.0 / (2.0 * sigma1 - rho);
+        const double c1 = rho_n * rho, c2 = 2.0 * rho_n / delta;
+        if (held) {
 #pragma unroll
           for (int k = 0; k < PA_ROWS; ++k) {
             const int t = threadIdx.x + k * PA_THREADS;
@@ -351,12 +358,28 @@ __global__ void __launch_bounds__(PA_THREADS) k_prec_apply(int n, int n_lambda, 
                 if (rsc[k][q] >= 0) sd += rsv[k][q] * dc[rsc[k][q]];
               xr[k] += dt;
               rr[k] -= sd;
-              dn[t] = rho_n * rho * dt + 2.0 * rho_n / delta * rd[k] * rr[k];
+              dn[t] = c1 * dt + c2 * rd[k] * rr[k];
             }
           }
-          rho = rho_n;
-          __syncthreads();
+        } else {
+          for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
+            const double di = sdi[t], dt = dc[t];
+            double sd = dt / di;
+#pragma unroll
+            for (int q = 0; q < S_NB; ++q) {
+              const int c = sc_col[(int64_t)t * S_NB + q];
+              if (c >= 0) sd += sc_val[(int64_t)t * S_NB + q] * dc[c];
+            }
+            cx[t] += dt;
+            const double rt = cr[t] - sd;
+            cr[t] = rt;
+            dn[t] = c1 * dt + c2 * di * rt;
+          }
         }
+        rho = rho_n;
+        __syncthreads();
+      }
+      if (held) {
 #pragma unroll
         for (int k = 0; k < PA_ROWS; ++k) {
           const int t = threadIdx.x + k * PA_THREADS;
@@ -366,27 +389,9 @@ __global__ void __launch_bounds__(PA_THREADS) k_prec_apply(int n, int n_lambda, 
           }
         }
       } else {
-        for (int t = threadIdx.x; t < ne; t += PA_THREADS) x0[t] = JACOBI_OMEGA * sdi[t] * vu[t];
-        __syncthreads();
-        for (int sw = 1; sw < JACOBI_SWEEPS; ++sw) {
-          const double* xa = (sw & 1) ? x0 : x1;
-          double* xn = (sw & 1) ? x1 : x0;
-          for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
-            const double di = sdi[t];
-            double sx = xa[t] / di;
-#pragma unroll
-            for (int q = 0; q < S_NB; ++q) {
-              const int c = sc_col[(int64_t)t * S_NB + q];
-              if (c >= 0) sx += sc_val[(int64_t)t * S_NB + q] * xa[c];
-            }
-            xn[t] = xa[t] + JACOBI_OMEGA * di * (vu[t] - sx);
-          }
-          __syncthreads();
-        }
-        const double* xf = (JACOBI_SWEEPS & 1) ? x0 : x1;
         for (int t = threadIdx.x; t < ne; t += PA_THREADS) {
-          z[n_lambda + t] = xf[t];
-          acc += xf[t] * vu[t];
+          z[n_lambda + t] = cx[t];
+          acc += cx[t] * vu[t];
         }
       }
     } else {
@@ -607,9 +612,10 @@ __global__ void k_residual_final(const double* part_r, const double* part_b, int
 
 size_t skeleton_solve_bytes(int n, int pb) {
   // 9 vectors, three partial arrays, scalars; with face blocks the block
-  // inverses (n_lambda pb <= n pb values) and S per element row (1 / S_tt,
-  // 3 values, 3 int32 columns: 5.5 doubles' worth, at most 6 n)
-  const size_t blk = pb > 1 ? (size_t)n * pb + 6 * (size_t)n + 64 : 0;
+  // inverses (n_lambda pb <= n pb values), S per element row (1 / S_tt,
+  // 3 values, 3 int32 columns: 5.5 doubles' worth) and the Chebyshev
+  // iterate and residual (2 per element row): at most 8 n
+  const size_t blk = pb > 1 ? (size_t)n * pb + 8 * (size_t)n + 64 : 0;
   return sizeof(double) * ((size_t)9 * n + 3 * SV_MAX_BLOCKS + 2 * SC_COUNT + 8 + blk);
 }
 
@@ -653,6 +659,8 @@ hipError_t skeleton_solve(int n, int n_lambda, int pb, const int32_t* rp, const 
   double* sdi = dblk + (size_t)n_lambda * (blocked ? pb : 0);
   double* sc_val = sdi + ne;
   int32_t* sc_col = reinterpret_cast<int32_t*>(sc_val + (size_t)S_NB * ne);
+  double* cheb_x = sc_val + (size_t)S_NB * ne + ((size_t)S_NB * ne + 1) / 2;   // after the int32 columns
+  double* cheb_r = cheb_x + ne;
   // the Jacobi sweeps hold two copies of the u_0 iterate in one workgroup's LDS
   const size_t jac_lds = sizeof(double) * 2 * (size_t)ne;
   const int jacobi = blocked && ne > 0 && jac_lds <= 128 * 1024 ? 1 : 0;
@@ -685,7 +693,7 @@ hipError_t skeleton_solve(int n, int n_lambda, int pb, const int32_t* rp, const 
   // z = P^-1 v with its partials, for the face-block preconditioner
   auto prec_apply = [&](const double* v, double* z, double* part, const double* sc, hipStream_t s2) {
     hipLaunchKernelGGL(k_prec_apply, dim3(nbp), dim3(PA_THREADS), jacobi ? jac_lds : 0, s2, n, n_lambda, pb, jacobi,
-                       v, z, dblk, sdi, sc_col, sc_val, part, sc);
+                       v, z, dblk, sdi, sc_col, sc_val, cheb_x, cheb_r, part, sc);
   };
   // v_j in vA, v_{j-1} in vB; z_j in zA; w_j in wA, w_{j-1} in wB
   hipLaunchKernelGGL(k_start, dim3(nb), dim3(SV_THREADS), 0, st, n, b, dinv, vA, zA, vB, wA, wB, x, part1);

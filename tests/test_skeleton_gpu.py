@@ -264,9 +264,9 @@ def test_face_block_preconditioner_takes_fewer_steps(ctx, N, s, l, m):
 @pytest.mark.parametrize("N", [48, 68])
 def test_schur_preconditioner_on_large_meshes(ctx, N):
     """More elements than the Chebyshev steps hold in registers: 4,608
-    elements take the Jacobi sweeps, 9,248 the diagonal of S.  The solve
-    reaches a small true residual (computed on the device from the CSR
-    system) and u is finite."""
+    elements re-read their rows of S each step, 9,248 take the diagonal of
+    S.  The solve reaches a small true residual (computed on the device from
+    the CSR system) and u is finite."""
     mesh, b, out, db, sk, vals, rhs = _gpu_system(ctx, N, 2, 1, 1, _ones)
     say(f"[gpu] skeleton preconditioner paths N={N} elements={b['n_elem']} rows={sk.n_rows}")
     sol, it, rr = sk.solve(ctx, vals, rhs, tol=1e-11)
