@@ -262,21 +262,21 @@ __global__ void __launch_bounds__(SV_THREADS) k_schur(int n, int n_lambda, int p
 }
 
 // z = P^-1 v and the partials of <z, v>.  Workgroup 0: the u_0 rows, by
-// CHEB_STEPS Chebyshev steps on S from zero (jacobi != 0: the shared vector
+// CHEB_STEPS Chebyshev steps on S from zero (cheb != 0: the shared vector
 // fits in LDS), else z = v / S_tt.  The other workgroups: the face blocks.
-__global__ void __launch_bounds__(PA_THREADS) k_prec_apply(int n, int n_lambda, int pb, int jacobi,
+__global__ void __launch_bounds__(PA_THREADS) k_prec_apply(int n, int n_lambda, int pb, int cheb,
                                                           const double* v, double* z, const double* dblk,
                                                           const double* sdi, const int32_t* sc_col,
                                                           const double* sc_val, double* cx, double* cr,
                                                           double* part, const double* sc) {
   __shared__ double red[PA_THREADS / 64];
-  extern __shared__ double xs[];   // 2 (n - n_lambda) when jacobi
+  extern __shared__ double xs[];   // 2 (n - n_lambda) when cheb
   if (sc[SC_DONE] != 0.0) return;
   const int ne = n - n_lambda, nf = n_lambda / pb;
   double acc = 0.0;
   if (blockIdx.x == 0) {
     const double* vu = v + n_lambda;
-    if (jacobi) {
+    if (cheb) {
       // Chebyshev iteration on S x = v_u (Jacobi-scaled, x_0 = 0) over the
       // interval [lmax / CHEB_RATIO, lmax], lmax the Gershgorin bound of
       // D^-1 S: a fixed polynomial p(D^-1 S) D^-1, positive on (0, lmax],
@@ -661,9 +661,9 @@ hipError_t skeleton_solve(int n, int n_lambda, int pb, const int32_t* rp, const 
   int32_t* sc_col = reinterpret_cast<int32_t*>(sc_val + (size_t)S_NB * ne);
   double* cheb_x = sc_val + (size_t)S_NB * ne + ((size_t)S_NB * ne + 1) / 2;   // after the int32 columns
   double* cheb_r = cheb_x + ne;
-  // the Jacobi sweeps hold two copies of the u_0 iterate in one workgroup's LDS
-  const size_t jac_lds = sizeof(double) * 2 * (size_t)ne;
-  const int jacobi = blocked && ne > 0 && jac_lds <= 128 * 1024 ? 1 : 0;
+  // the Chebyshev steps hold two copies of the u_0 search direction in one workgroup's LDS
+  const size_t cheb_lds = sizeof(double) * 2 * (size_t)ne;
+  const int cheb = blocked && ne > 0 && cheb_lds <= 128 * 1024 ? 1 : 0;
   const int nbp = 1 + std::max(1, std::min(SV_MAX_BLOCKS - 1, (nf + PA_THREADS - 1) / PA_THREADS));
   const int nb = std::max(1, std::min(SV_MAX_BLOCKS, (n + SV_THREADS - 1) / SV_THREADS));
   const int nbr = std::max(1, std::min(SV_MAX_BLOCKS, (n + SV_THREADS / ROW_LANES - 1) / (SV_THREADS / ROW_LANES)));
@@ -676,8 +676,8 @@ hipError_t skeleton_solve(int n, int n_lambda, int pb, const int32_t* rp, const 
   if (n > n_lambda) hipLaunchKernelGGL(k_prec_u0, dim3(nb), dim3(SV_THREADS), 0, st, n, n_lambda, rp, ci, va, dinv);
   SV_CHECK();
   if (blocked) {
-    if (jacobi) {
-      e = hipFuncSetAttribute((const void*)k_prec_apply, hipFuncAttributeMaxDynamicSharedMemorySize, (int)jac_lds);
+    if (cheb) {
+      e = hipFuncSetAttribute((const void*)k_prec_apply, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cheb_lds);
       if (e != hipSuccess) return e;
     }
     const int nbf = std::max(1, std::min(SV_MAX_BLOCKS, (nf + SV_THREADS - 1) / SV_THREADS));
@@ -692,7 +692,7 @@ hipError_t skeleton_solve(int n, int n_lambda, int pb, const int32_t* rp, const 
   }
   // z = P^-1 v with its partials, for the face-block preconditioner
   auto prec_apply = [&](const double* v, double* z, double* part, const double* sc, hipStream_t s2) {
-    hipLaunchKernelGGL(k_prec_apply, dim3(nbp), dim3(PA_THREADS), jacobi ? jac_lds : 0, s2, n, n_lambda, pb, jacobi,
+    hipLaunchKernelGGL(k_prec_apply, dim3(nbp), dim3(PA_THREADS), cheb ? cheb_lds : 0, s2, n, n_lambda, pb, cheb,
                        v, z, dblk, sdi, sc_col, sc_val, cheb_x, cheb_r, part, sc);
   };
   // v_j in vA, v_{j-1} in vB; z_j in zA; w_j in wA, w_{j-1} in wB
