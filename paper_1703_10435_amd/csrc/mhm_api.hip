@@ -62,6 +62,7 @@ struct mhm_ctx_s {
   bool no_ll = false;          // MHM_NO_LL=1: never use the left-looking kernel
   bool ll_occ2 = false;        // MHM_LL_OCC2=1: left-looking default with two workgroups per CU
   bool ll_nw16 = false;        // MHM_LL_NW16=1: left-looking default with 16 waves where it applies
+  int ll_pw = 0;               // MHM_LL_PW=1|2|4: left-looking default panel width, where built
   void* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t aux[kNumClasses] = {};   // class streams of ragged runs
@@ -190,7 +191,8 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
 // Default family when nothing was tuned.
 Choice default_choice(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_cap, bool listed) {
   const int nt = (n_of(s_cap) + 15) / 16;
-  const Choice ll = c->ll_occ2 ? Choice{FAM_LL, 2, 2} : Choice{FAM_LL, mhm::local_ll_default_panel(fp32, nt), 1};
+  const int pw = c->ll_pw > 0 ? c->ll_pw : mhm::local_ll_default_panel(fp32, nt);
+  const Choice ll = c->ll_occ2 ? Choice{FAM_LL, 2, 2} : Choice{FAM_LL, pw, 1};
   const Choice ll16{FAM_LL, 2, 1, 16};
   const Choice cands[] = {{FAM_RR, 0}, {FAM_LDS, 0}, c->ll_nw16 ? ll16 : ll, ll, {FAM_LL, 2, 1}, {FAM_WS, 0}};
   for (const Choice& ch : cands) {
@@ -540,6 +542,8 @@ mhm_status mhm_create(mhm_ctx* out, int device, void* hip_stream) {
   c->ll_occ2 = occ2 && occ2[0] == '1';
   const char* nw16 = std::getenv("MHM_LL_NW16");
   c->ll_nw16 = nw16 && nw16[0] == '1';
+  const char* llpw = std::getenv("MHM_LL_PW");
+  if (llpw && (llpw[0] == '1' || llpw[0] == '2' || llpw[0] == '4') && llpw[1] == 0) c->ll_pw = llpw[0] - '0';
   c->stream = static_cast<hipStream_t>(hip_stream);
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0) c->n_cu = v;

@@ -191,6 +191,14 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
   typedef typename Mfma<T>::v4 V4;
   constexpr int NW = NWV;
   constexpr int NTHREADS = 64 * NW;
+  // Row passes per block column: with ten rows per wave, a panel wider than
+  // 80 accumulator registers per lane (two FP32 or one FP64 tile per row)
+  // would not fit next to the operands, so the rows are updated and solved
+  // in passes of five or two; the earlier columns' B tiles are staged once
+  // per pass, the A tiles (the bulk of the reads) still once per panel.
+  constexpr int ACC = PW * 4 * (int)(sizeof(T) / 4);   // accumulator registers per row
+  constexpr int RS = (MC || OCC != 1 || NW != 8 || RPW != 10) ? 1 : 10 * ACC <= 80 ? 1 : 5 * ACC <= 80 ? 2 : 5;
+  constexpr int RH = RPW / RS;
   __shared__ Elem E;
   __shared__ int ok, bad, conv;
   __shared__ double be_prev;
@@ -238,9 +246,9 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     double* bf = c + args.n_cap;
     double* ft = bf + args.n_cap;
     T* stage = reinterpret_cast<T*>(ft + args.f_cap);  // 2 x PW tiles
-    T* Wt = stage + 2 * PW * TILE;                       // current diagonal inverse
-    T* pub = Wt + TILE;                                  // PW published panel tiles
-    T* scr = pub + PW * TILE + wave * TILE;              // this wave's scratch tile
+    T* Wt = stage + 2 * PW * TILE;                       // the panel's PW diagonal inverses
+    T* pub = Wt + PW * TILE;                             // PW x PW published panel tiles
+    T* scr = pub + PW * PW * TILE + wave * TILE;         // this wave's scratch tile
     T* ws = reinterpret_cast<T*>(args.ws) + (int64_t)blockIdx.x * args.ws_slot;
     // Tiles of the factor (lower triangle, W_jj = L_jj^{-1} on the diagonal):
     // in the workgroup's workspace slot, or in the caller's factor store
@@ -381,179 +389,193 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     }
     for (int j0 = 0; j0 < (reuse ? 0 : nt); j0 += PW) {
       const int pw = nt - j0 < PW ? nt - j0 : PW;
-      V4 acc[RPW][PW];
-      // (a) initial panel: rows are unrolled, the PW columns of a row run in
-      // a loop whose result is moved into its register slot by selects
-      // (a branch chain here would leave the panel array in scratch memory)
-#pragma unroll
-      for (int ri = 0; ri < RPW; ++ri) {
-        const int i = j0 + wave + NW * ri;
-#pragma unroll
-        for (int k = 0; k < PW; ++k) acc[ri][k] = V4{0, 0, 0, 0};
-        if (held_i(i)) {
 #pragma unroll 1
-          for (int jj = 0; jj < pw; ++jj) {
-            if (rhs_i(i) || i >= j0 + jj) {
-              const V4 v = init_tile(i, j0 + jj);
+      for (int h = 0; h < RS; ++h) {
+        // rows of this pass: slots h RH .. h RH + RH - 1 of the wave
+        auto row_of = [&](int ri) { return j0 + wave + NW * (h * RH + ri); };
+        V4 acc[RH][PW];
+        // (a) initial panel: rows are unrolled, the PW columns of a row run in
+        // a loop whose result is moved into its register slot by selects
+        // (a branch chain here would leave the panel array in scratch memory)
 #pragma unroll
-              for (int k = 0; k < PW; ++k) acc[ri][k] = jj == k ? v : acc[ri][k];
+        for (int ri = 0; ri < RH; ++ri) {
+          const int i = row_of(ri);
+#pragma unroll
+          for (int k = 0; k < PW; ++k) acc[ri][k] = V4{0, 0, 0, 0};
+          if (held_i(i)) {
+#pragma unroll 1
+            for (int jj = 0; jj < pw; ++jj) {
+              if (rhs_i(i) || i >= j0 + jj) {
+                const V4 v = init_tile(i, j0 + jj);
+#pragma unroll
+                for (int k = 0; k < PW; ++k) acc[ri][k] = jj == k ? v : acc[ri][k];
+              }
             }
           }
         }
-      }
-      // (b) earlier tile columns.  The operands of column m + 1 (A operands
-      // in registers, B tiles for the LDS stage) are loaded while the MFMAs
-      // of column m run; one barrier per column (stage buffers alternate).
-      if (j0 > 0) {
-        constexpr int SPT = (PW * TILE + NTHREADS - 1) / NTHREADS;
-        // operand buffers (prefetch depth) within a register estimate
-        constexpr int W = (int)sizeof(T) / 4;
-        // (budgets for 256 registers per lane, or 128 with 16 waves)
-        constexpr int B3 = NW == 16 ? 72 : 144, B2 = NW == 16 ? 96 : 160;
-        constexpr int NB = OCC == 2                                               ? 1
-                           : RPW * PW * 4 * W + 3 * (RPW * 4 + SPT) * W <= B3 ? 3
-                           : RPW * PW * 4 * W + 2 * (RPW * 4 + SPT) * W <= B2 ? 2
+        // (b) earlier tile columns.  The operands of column m + 1 (A operands
+        // in registers, B tiles for the LDS stage) are loaded while the MFMAs
+        // of column m run; one barrier per column (stage buffers alternate).
+        if (j0 > 0) {
+          constexpr int SPT = (PW * TILE + NTHREADS - 1) / NTHREADS;
+          // operand buffers (prefetch depth) within a register estimate
+          constexpr int W = (int)sizeof(T) / 4;
+          // (budgets for 256 registers per lane, or 128 with 16 waves)
+          constexpr int B3 = NW == 16 ? 72 : 144, B2 = NW == 16 ? 96 : 160;
+          constexpr int NB = OCC == 2                                            ? 1
+                             : RH * PW * 4 * W + 3 * (RH * 4 + SPT) * W <= B3 ? 3
+                             : RH * PW * 4 * W + 2 * (RH * 4 + SPT) * W <= B2 ? 2
                                                                               : 1;
-        T ab[NB][RPW][4];
-        T sb[NB][SPT];
-        auto fetch = [&](int m, T (&a)[RPW][4], T (&sv)[SPT]) {
-          if (m >= j0) return;
+          T ab[NB][RH][4];
+          T sb[NB][SPT];
+          auto fetch = [&](int m, T (&a)[RH][4], T (&sv)[SPT]) {
+            if (m >= j0) return;
 #pragma unroll
-          for (int ri = 0; ri < RPW; ++ri) {
-            const int i = j0 + wave + NW * ri;
-            if (held_i(i)) ll::ld_row4(tl(i, m), lane, a[ri]);
-          }
+            for (int ri = 0; ri < RH; ++ri) {
+              const int i = row_of(ri);
+              if (held_i(i)) ll::ld_row4(tl(i, m), lane, a[ri]);
+            }
 #pragma unroll
-          for (int q = 0; q < SPT; ++q) {
-            const int idx = tid + q * NTHREADS;
-            if (idx < pw * TILE) sv[q] = tl(j0 + idx / TILE, m)[idx % TILE];
-          }
-        };
-        auto apply = [&](int m, const T (&a)[RPW][4], const T (&sv)[SPT]) {
-          T* st = stage + (m & 1) * PW * TILE;
+            for (int q = 0; q < SPT; ++q) {
+              const int idx = tid + q * NTHREADS;
+              if (idx < pw * TILE) sv[q] = tl(j0 + idx / TILE, m)[idx % TILE];
+            }
+          };
+          auto apply = [&](int m, const T (&a)[RH][4], const T (&sv)[SPT]) {
+            T* st = stage + (m & 1) * PW * TILE;
 #pragma unroll
-          for (int q = 0; q < SPT; ++q) {
-            const int idx = tid + q * NTHREADS;
-            if (idx < pw * TILE) st[idx] = sv[q];
-          }
-          __syncthreads();
-          // B operands (the staged tiles L_jm): in FP32 read once and used by
-          // every row (registers to spare); in FP64 read per row
-          constexpr bool HOIST = sizeof(T) == 4;
-          T bo[PW][4];
-          if constexpr (HOIST) {
+            for (int q = 0; q < SPT; ++q) {
+              const int idx = tid + q * NTHREADS;
+              if (idx < pw * TILE) st[idx] = sv[q];
+            }
+            __syncthreads();
+            // B operands (the staged tiles L_jm): in FP32 read once and used by
+            // every row (registers to spare); in FP64 read per row
+            constexpr bool HOIST = sizeof(T) == 4;
+            T bo[PW][4];
+            if constexpr (HOIST) {
 #pragma unroll
-            for (int jj = 0; jj < PW; ++jj) ll::ld_row4(st + jj * TILE, lane, bo[jj]);
-          }
+              for (int jj = 0; jj < PW; ++jj) ll::ld_row4(st + jj * TILE, lane, bo[jj]);
+            }
 #pragma unroll
-          for (int ri = 0; ri < RPW; ++ri) {
-            const int i = j0 + wave + NW * ri;
-            if (held_i(i)) {
+            for (int ri = 0; ri < RH; ++ri) {
+              const int i = row_of(ri);
+              if (held_i(i)) {
 #pragma unroll
-              for (int jj = 0; jj < PW; ++jj) {
-                if (jj < pw && (rhs_i(i) || i >= j0 + jj)) {
-                  V4 x = acc[ri][jj];
+                for (int jj = 0; jj < PW; ++jj) {
+                  if (jj < pw && (rhs_i(i) || i >= j0 + jj)) {
+                    V4 x = acc[ri][jj];
 #pragma unroll
-                  for (int cch = 0; cch < 4; ++cch)
-                    x = Mfma<T>::op(-a[ri][cch],
-                                    HOIST ? bo[jj][cch] : st[jj * TILE + (lane & 15) * TST + 4 * (lane >> 4) + cch], x);
-                  acc[ri][jj] = x;
+                    for (int cch = 0; cch < 4; ++cch)
+                      x = Mfma<T>::op(
+                          -a[ri][cch], HOIST ? bo[jj][cch] : st[jj * TILE + (lane & 15) * TST + 4 * (lane >> 4) + cch],
+                          x);
+                    acc[ri][jj] = x;
+                  }
+                }
+              }
+            }
+          };
+          if constexpr (NB == 1) {
+            for (int m = 0; m < j0; ++m) {
+              fetch(m, ab[0], sb[0]);
+              apply(m, ab[0], sb[0]);
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) fetch(q, ab[q], sb[q]);
+            for (int m = 0; m < j0; m += NB) {
+#pragma unroll
+              for (int q = 0; q < NB; ++q) {
+                if (m + q < j0) {
+                  apply(m + q, ab[q], sb[q]);
+                  fetch(m + q + NB, ab[q], sb[q]);
                 }
               }
             }
           }
-        };
-        if constexpr (NB == 1) {
-          for (int m = 0; m < j0; ++m) {
-            fetch(m, ab[0], sb[0]);
-            apply(m, ab[0], sb[0]);
+        }
+        // (c) factor the panel, one column at a time (run-time loop; the tile
+        // code that touches the register panel matches the column statically).
+        // The diagonal tiles and the panel's own rows belong to the first pass;
+        // a second pass reuses their W_j and L tiles from LDS, wave by wave.
+#pragma unroll 1
+        for (int jj = 0; jj < pw; ++jj) {
+          const int col = j0 + jj;
+          T* Wj = Wt + jj * TILE;
+          // diagonal tile (row col is local row jj: wave jj, slot 0 of pass 0)
+          if (h == 0) {
+            if (wave == jj) {
+#pragma unroll
+              for (int k = 0; k < PW; ++k)
+                if (k == jj) st_acc<T>(Wj, acc[0][k], lane);
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+              const int bj = potrf_c<T>(Wj, nullptr, n, col, lane, Lo ? ldiag(col) : nullptr);
+              if (lane == 0 && bj >= 0 && bad < 0) bad = 16 * col + bj;
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+              T* dst = tl(col, col);
+              for (int idx = lane; idx < TILE; idx += 64) dst[idx] = Wj[idx];
+            }
+            __syncthreads();
           }
-        } else {
+          // panel solve L_i,col = C_i,col W^T for the rows below, then the
+          // in-panel update C_i,j -= L_i,col L_j,col^T of the later columns
 #pragma unroll
-          for (int q = 0; q < NB; ++q) fetch(q, ab[q], sb[q]);
-          for (int m = 0; m < j0; m += NB) {
+          for (int k = 0; k < PW; ++k) {
+            if (k == jj) {
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-              if (m + q < j0) {
-                apply(m + q, ab[q], sb[q]);
-                fetch(m + q + NB, ab[q], sb[q]);
+              for (int ri = 0; ri < RH; ++ri) {
+                const int i = row_of(ri);
+                if (i > col && held_i(i)) {
+                  st_acc<T>(scr, acc[ri][k], lane);
+                  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                  V4 x = {0, 0, 0, 0};
+#pragma unroll
+                  for (int cch = 0; cch < 4; ++cch)
+                    x = Mfma<T>::op(ld_rowcol(scr, cch, lane), ld_rowcol(Wj, cch, lane), x);
+                  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                  acc[ri][k] = x;
+                  st_acc<T>(tl(i, col), x, lane);
+                  if (i < j0 + pw) st_acc<T>(pub + (jj * PW + i - j0) * TILE, x, lane);
+                }
               }
             }
           }
-        }
-      }
-      // (c) factor the panel, one column at a time (run-time loop; the tile
-      // code that touches the register panel matches the column statically)
-#pragma unroll 1
-      for (int jj = 0; jj < pw; ++jj) {
-        const int col = j0 + jj;
-        // diagonal tile (row col is local row jj: wave jj, slot 0)
-        if (wave == jj) {
+          if (h == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __syncthreads();
+          }
 #pragma unroll
-          for (int k = 0; k < PW; ++k)
-            if (k == jj) st_acc<T>(Wt, acc[0][k], lane);
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-          const int bj = potrf_c<T>(Wt, nullptr, n, col, lane, Lo ? ldiag(col) : nullptr);
-          if (lane == 0 && bj >= 0 && bad < 0) bad = 16 * col + bj;
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-          T* dst = tl(col, col);
-          for (int idx = lane; idx < TILE; idx += 64) dst[idx] = Wt[idx];
-        }
-        __syncthreads();
-        // panel solve L_i,col = C_i,col W^T for the rows below, then the
-        // in-panel update C_i,j -= L_i,col L_j,col^T of the later columns
+          for (int k = 0; k < PW - 1; ++k) {
+            if (k == jj && jj + 1 < pw) {
 #pragma unroll
-        for (int k = 0; k < PW; ++k) {
-          if (k == jj) {
+              for (int ri = 0; ri < RH; ++ri) {
+                const int i = row_of(ri);
+                if (i > col && held_i(i)) {
+                  st_acc<T>(scr, acc[ri][k], lane);
+                  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                  T a[4];
 #pragma unroll
-            for (int ri = 0; ri < RPW; ++ri) {
-              const int i = j0 + wave + NW * ri;
-              if (i > col && held_i(i)) {
-                st_acc<T>(scr, acc[ri][k], lane);
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                V4 x = {0, 0, 0, 0};
+                  for (int cch = 0; cch < 4; ++cch) a[cch] = -ld_rowcol(scr, cch, lane);
 #pragma unroll
-                for (int cch = 0; cch < 4; ++cch)
-                  x = Mfma<T>::op(ld_rowcol(scr, cch, lane), ld_rowcol(Wt, cch, lane), x);
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                acc[ri][k] = x;
-                st_acc<T>(tl(i, col), x, lane);
-                if (i < j0 + pw) st_acc<T>(pub + (i - j0) * TILE, x, lane);
+                  for (int j2 = k + 1; j2 < PW; ++j2) {
+                    if (j2 < pw && (rhs_i(i) || i >= j0 + j2)) {
+                      V4 x = acc[ri][j2];
+#pragma unroll
+                      for (int cch = 0; cch < 4; ++cch)
+                        x = Mfma<T>::op(a[cch], ld_rowcol(pub + (jj * PW + j2) * TILE, cch, lane), x);
+                      acc[ri][j2] = x;
+                    }
+                  }
+                  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                }
               }
             }
           }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PW - 1; ++k) {
-          if (k == jj && jj + 1 < pw) {
-#pragma unroll
-            for (int ri = 0; ri < RPW; ++ri) {
-              const int i = j0 + wave + NW * ri;
-              if (i > col && held_i(i)) {
-                st_acc<T>(scr, acc[ri][k], lane);
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                T a[4];
-#pragma unroll
-                for (int cch = 0; cch < 4; ++cch) a[cch] = -ld_rowcol(scr, cch, lane);
-#pragma unroll
-                for (int j2 = k + 1; j2 < PW; ++j2) {
-                  if (j2 < pw && (rhs_i(i) || i >= j0 + j2)) {
-                    V4 x = acc[ri][j2];
-#pragma unroll
-                    for (int cch = 0; cch < 4; ++cch) x = Mfma<T>::op(a[cch], ld_rowcol(pub + j2 * TILE, cch, lane), x);
-                    acc[ri][j2] = x;
-                  }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-              }
-            }
-          }
-        }
       }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      __syncthreads();
     }
 
     // -------------------------------------------- factor output (three-call)

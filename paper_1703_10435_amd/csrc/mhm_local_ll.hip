@@ -19,12 +19,13 @@ int local_ll_rows_per_wave(int nt, int nw) {
   return -1;
 }
 
-// FP32: width 4.  FP64: width 2, or 1 for the largest elements (10 rows per
-// wave), where the wider panel's registers cost more than its halved operand
-// reads save (s = 48: 53 against 63 ms per 1024 elements).
+// FP32: width 4.  FP64: width 2.  With ten rows per wave (the largest
+// elements) both take the rows in two passes (s = 48, 1024 elements: FP64
+// 33 ms against 52 ms with one-tile panels, FP32 23 against 24 ms with
+// two-tile panels).
 int local_ll_default_panel(bool fp32, int nt) {
-  if (fp32) return 4;
-  return local_ll_rows_per_wave(nt, 8) == 10 ? 1 : 2;
+  (void)nt;
+  return fp32 ? 4 : 2;
 }
 
 bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw, bool mc) {
@@ -39,12 +40,12 @@ bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw, bool mc) {
   if (occ == 2) return pw == 2 && (fp32 || rpw <= 3);
   if (occ != 1) return false;
   if (fp32) return pw == 2 || pw == 4;
-  return pw == 2 || (pw == 4 && rpw <= 3) || (pw == 1 && rpw == 10);
+  return pw == 2 || (pw == 4 && (rpw <= 3 || rpw == 10)) || (pw == 1 && rpw == 10);
 }
 
 size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap, int nw) {
   return sizeof(double) * (2 * (size_t)n_cap + (size_t)f_cap) +
-         (size_t)(2 * pw + 1 + pw + nw) * TILE * (fp32 ? sizeof(float) : sizeof(double));
+         (size_t)(2 * pw + pw + pw * pw + nw) * TILE * (fp32 ? sizeof(float) : sizeof(double));
 }
 
 hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, bool mc, int nt_max, const mhm_batch* bt,

@@ -1,7 +1,8 @@
 // FP64 instances of the left-looking kernel (panel width 2; width 4 for up to
-// 24 tile rows, where the register panel still fits; width 2 with two
-// resident workgroups per CU for up to 24 tile rows; 16 waves per element
-// for the largest elements).
+// 24 tile rows, where the register panel still fits, and for the largest
+// elements in row passes; width 2 with two resident workgroups per CU for up
+// to 24 tile rows; width 1 and 16 waves per element for the largest
+// elements).
 #include "mhm_local_ll.h"
 
 namespace mhm {
@@ -21,6 +22,7 @@ static hipError_t launch_rpw4(int rpw, const BatchDev& d, LocalArgs a, size_t ld
   switch (rpw) {
     case 2: return launch_ll_t<double, FUSED, 4, 2, 1>(d, a, lds, grid, st);
     case 3: return launch_ll_t<double, FUSED, 4, 3, 1>(d, a, lds, grid, st);
+    case 10: return launch_ll_t<double, FUSED, 4, 10, 1>(d, a, lds, grid, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -70,11 +70,14 @@ def test_every_size_class_in_one_batch(ctx, prec):
 
 
 @pytest.mark.parametrize("env", [{"MHM_NO_RR": "1"}, {"MHM_NO_LL": "1"}, {"MHM_NO_RR": "1", "MHM_NO_LL": "1"},
-                                 {"MHM_NO_RR": "1", "MHM_LL_OCC2": "1"}, {"MHM_LL_NW16": "1"}])
+                                 {"MHM_NO_RR": "1", "MHM_LL_OCC2": "1"}, {"MHM_LL_NW16": "1"}, {"MHM_LL_PW": "1"},
+                                 {"MHM_LL_PW": "4"}])
 def test_kernel_families_agree_with_oracle(env):
     """The families the defaults do not pick (LDS tiles for small FP64
     elements, the right-looking workspace kernel for large ones, the
-    left-looking kernel built for two workgroups per CU or with 16 waves)."""
+    left-looking kernel built for two workgroups per CU, with 16 waves, with
+    one-tile panels in FP64 and two-tile panels in FP32 at s = 48, or with
+    four-tile FP64 panels taken in five row passes)."""
     from paper_1703_10435_amd import engine
     c = _ctx(env)
     try:
