@@ -47,7 +47,7 @@ const char* fam_name(int f) {
 struct Choice {
   int fam = -1;
   int pw = 0;    // panel width (left-looking)
-  int occ = 1;   // resident workgroups per CU the kernel is built for (left-looking)
+  int occ = 1;   // resident workgroups per CU the kernel is built for (left-looking, register tiles)
   int nw = 8;    // waves per element (left-looking)
 };
 
@@ -63,6 +63,7 @@ struct mhm_ctx_s {
   bool ll_occ2 = false;        // MHM_LL_OCC2=1: left-looking default with two workgroups per CU
   bool ll_nw16 = false;        // MHM_LL_NW16=1: left-looking default with 16 waves where it applies
   int ll_pw = 0;               // MHM_LL_PW=1|2|4: left-looking default panel width, where built
+  int rr_occ = 0;              // MHM_RR_OCC=2|3: register-tile kernel default workgroups per CU
   void* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t aux[kNumClasses] = {};   // class streams of ragged runs
@@ -151,9 +152,12 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
   const int slots = std::min(b->n_elem, 2 * c->n_cu);
   switch (ch.fam) {
     case FAM_RR:
+      // two or three resident workgroups per CU; by default three for the
+      // fused kernel, two for the factor-and-solve one (more registers)
+      if (p.ch.occ != 2 && p.ch.occ != 3) p.ch.occ = c->rr_occ ? c->rr_occ : fused ? 3 : 2;
       p.ok = !fp32 && p.nt <= mhm::local_rr_max_nt() && one_chunk;
       p.k_cap = k_lds;
-      p.lds = mhm::local_rr_lds_bytes(p.n_cap, p.f_cap, k_lds);
+      p.lds = mhm::local_rr_lds_bytes(p.n_cap, p.f_cap, k_lds, p.ch.occ);
       p.grid = one_each;
       break;
     case FAM_LDS:
@@ -307,7 +311,7 @@ struct RunIO {
 
 hipError_t launch_plan(const Plan& p, const mhm_batch* b, const mhm::LocalArgs& a, hipStream_t st) {
   switch (p.ch.fam) {
-    case FAM_RR: return mhm::launch_local_rr(p.fused, b, a, p.lds, p.grid, st);
+    case FAM_RR: return mhm::launch_local_rr(p.fused, p.ch.occ, b, a, p.lds, p.grid, st);
     case FAM_LDS: return mhm::launch_local(p.fp32, true, p.fused, b, a, p.lds, p.grid, st);
     case FAM_LL:
       return mhm::launch_local_ll(p.fp32, p.fused, p.ch.pw, p.ch.occ, p.ch.nw, p.mc, p.nt, b, a, p.lds, p.grid, st);
@@ -459,9 +463,9 @@ Choice tune_class(mhm_ctx c, const mhm_batch* b, bool fp32, const RunPlan& base,
                   int32_t* dcount, int cap, int count, std::string& log, mhm_status& st) {
   const ClassRun& r0 = base.run[i];
   std::vector<Choice> cands;
-  const Choice all[] = {{FAM_RR, 0, 1},     {FAM_LDS, 0, 1},    {FAM_LL, 2, 1},    {FAM_LL, 4, 1},
-                        {FAM_LL, 2, 2},     {FAM_LL, 2, 1, 16}, {FAM_LL, 4, 1, 16}, {FAM_LL, 1, 1},
-                        {FAM_LL, 1, 1, 16}, {FAM_WS, 0, 1}};
+  const Choice all[] = {{FAM_RR, 0, 3},     {FAM_RR, 0, 2},     {FAM_LDS, 0, 1},    {FAM_LL, 2, 1},
+                        {FAM_LL, 4, 1},     {FAM_LL, 2, 2},     {FAM_LL, 2, 1, 16}, {FAM_LL, 4, 1, 16},
+                        {FAM_LL, 1, 1},     {FAM_LL, 1, 1, 16}, {FAM_WS, 0, 1}};
   bool have_ll = false;
   for (const Choice& ch : all) {
     if (ch.fam == FAM_RR && c->no_rr) continue;
@@ -544,6 +548,8 @@ mhm_status mhm_create(mhm_ctx* out, int device, void* hip_stream) {
   c->ll_nw16 = nw16 && nw16[0] == '1';
   const char* llpw = std::getenv("MHM_LL_PW");
   if (llpw && (llpw[0] == '1' || llpw[0] == '2' || llpw[0] == '4') && llpw[1] == 0) c->ll_pw = llpw[0] - '0';
+  const char* rrocc = std::getenv("MHM_RR_OCC");
+  if (rrocc && (rrocc[0] == '2' || rrocc[0] == '3') && rrocc[1] == 0) c->rr_occ = rrocc[0] - '0';
   c->stream = static_cast<hipStream_t>(hip_stream);
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0) c->n_cu = v;

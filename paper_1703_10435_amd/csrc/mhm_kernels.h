@@ -96,9 +96,11 @@ hipError_t launch_contrib(const mhm_batch* bt, const double* X, double* M, doubl
 size_t local_lds_bytes(bool fp32, bool in_lds, int n_cap, int f_cap, int k_cap, int tile_cap);
 int local_face_cap(const mhm_batch* bt);
 // Register-resident FP64 kernel for elements with n <= 16 * local_rr_max_nt().
-size_t local_rr_lds_bytes(int n_cap, int f_cap, int k_cap);
+size_t local_rr_lds_bytes(int n_cap, int f_cap, int k_cap, int occ);
 int local_rr_max_nt();
-hipError_t launch_local_rr(bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid, hipStream_t st);
+// occ: resident workgroups per CU the kernel is built for (2 or 3).
+hipError_t launch_local_rr(bool fused, int occ, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
+                           hipStream_t st);
 // Left-looking kernel for large elements (tiles in a workspace slot), panel
 // width pw (block columns of pw tiles); mc: the instance that takes more than
 // RHS_CHUNK right-hand sides (in chunks).

@@ -2,7 +2,8 @@
 // n <= 16*RR_NT nodes.
 //
 // Same steps and results as k_local<double, ...> (a2-a6), organised so that
-// two elements fit on one CU at a time:
+// two or three elements fit on one CU at a time (built for either, with 256
+// or 168 registers per lane):
 //  * the 16x16 tiles of the lower triangle of Ahat live in the MFMA
 //    accumulators of the four waves (tile number t of the column-major
 //    triangle is owned by wave t%4, slot t/4); the right-hand-side row
@@ -15,7 +16,11 @@
 //    an L tile held in registers feeds the backward solve directly;
 //  * LDS holds the current panel column, the inverses W_j of the diagonal
 //    tiles, the right-hand-side row and the per-element tables (about 72 KB
-//    at n = 153).
+//    at n = 153).  Built for three workgroups per CU, the diagonal tile's
+//    register slot keeps W_j once that tile is factored (its own value is
+//    dead from then on) for the backward solve, LDS keeps only the current
+//    W_k, and the kappa and stencil tables share the panel column's space
+//    (dead once the tiles are filled): about 50 KB.
 #include "mhm_device.h"
 #include "mhm_kernels.h"
 
@@ -193,8 +198,10 @@ __device__ __forceinline__ void store_L(double* Lo, int n, int I, int J, const V
 
 }  // namespace rr
 
-template <bool FUSED>
-__global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalArgs args) {
+// OCC: resident workgroups per CU the registers are budgeted for (2: 256
+// per lane; 3: 168, with some spilling in the update loops).
+template <bool FUSED, int OCC>
+__global__ void __launch_bounds__(rr::NTHREADS, OCC) k_local_rr(BatchDev b, LocalArgs args) {
   using namespace rr;
   __shared__ Elem E;
   __shared__ int ok, bad;
@@ -202,22 +209,37 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
   __shared__ double colsum[R_CHUNK];   // one chunk only (r <= 16): two workgroups per CU need every byte
   __shared__ double cx[16];
   __shared__ double gam;
-  extern __shared__ double dyn[];      // c | bf | ft | kap | stencil[8][n] | P[NT] | W[NT] | R[NT]
+  extern __shared__ double dyn[];      // c | bf | ft | P[NT] (kap | stencil[8][n] until the fill ends) | W | R[NT]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int NImax = nimax(b);
 
   double* c = dyn;
   double* bf = c + args.n_cap;
   double* ft = bf + args.n_cap;
-  double* kapl = ft + args.f_cap;
-  double* stt = kapl + args.k_cap;     // node tables, entry k of node p at k n_cap + p (fused): the
+  // Three workgroups per CU (WREG): the inverse W_j of a factored diagonal
+  // tile moves into that tile's register slot and LDS keeps only the current
+  // one; kappa and the node tables share the panel column's space (they are
+  // dead once the tiles are filled).  Two per CU: every W_j in LDS.
+  constexpr bool WREG = OCC == 3;
+  double *kapl, *stt, *P, *Wb, *Rb;    // node tables: entry k of node p at k n_cap + p (fused), the
                                        // stencil d e w n s nw se, then 256 j + i
-  double* P = stt + 8 * args.n_cap;    // panel column L_ik
-  double* Wb = P + NT * TILE;          // inverses of the diagonal tiles
-  double* Rb = Wb + NT * TILE;         // right-hand-side row: tile J holds Z_J^T
-  auto Pt = [&](int I) -> double* { return P + I * TILE; };
-  auto Wt = [&](int J) -> double* { return Wb + J * TILE; };
-  auto Rt = [&](int J) -> double* { return Rb + J * TILE; };
+  if constexpr (WREG) {
+    P = ft + args.f_cap;
+    kapl = P;
+    stt = kapl + args.k_cap;
+    const int p_len = NT * TILE > args.k_cap + 8 * args.n_cap ? NT * TILE : args.k_cap + 8 * args.n_cap;
+    Wb = P + p_len;
+    Rb = Wb + TILE;
+  } else {
+    kapl = ft + args.f_cap;
+    stt = kapl + args.k_cap;
+    P = stt + 8 * args.n_cap;
+    Wb = P + NT * TILE;
+    Rb = Wb + NT * TILE;
+  }
+  auto Pt = [&](int I) -> double* { return P + I * TILE; };          // panel column L_ik
+  auto Wt = [&](int J) -> double* { return WREG ? Wb : Wb + J * TILE; };  // diagonal inverses
+  auto Rt = [&](int J) -> double* { return Rb + J * TILE; };         // RHS row: tile J holds Z_J^T
 
   V4 acc[S];
 
@@ -456,6 +478,15 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
         const int bj = rr::potrf_inv(Wt(k + 1), Lo, n, k + 1, lane);
         if (lane == 0 && bj >= 0 && bad < 0) bad = 16 * (k + 1) + bj;
         __builtin_amdgcn_s_setprio(0);
+        if constexpr (WREG) {
+          // the tile's own register slot is free from here on: it keeps
+          // W_k+1 for the backward solve (the result layout is its B-operand
+          // layout)
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+          for (int sl = 0; sl < S; ++sl)
+            if (sI[sl] == k + 1 && sJ[sl] == k + 1) acc[sl] = ld_acc<double>(Wt(k + 1), lane);
+        }
       }
       if (k >= 0) {
 #pragma unroll
@@ -493,11 +524,24 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
 
     // --------------------------------------------- backward solve X = L^{-T} Y
     for (int j = nt - 1; j >= 0; --j) {
-      if (wave == (j & 3)) {
+      // X_j^T = Z_j^T W_j: by the owner of tile (j, j), which holds W_j, or
+      // with W_j from LDS
+      if constexpr (WREG) {
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) {
+          if (sI[sl] == j && sJ[sl] == j) {
+            V4 x = {0, 0, 0, 0};
+#pragma unroll
+            for (int cch = 0; cch < 4; ++cch) x = Mfma<double>::op(ld_rowcol(Rt(j), cch, lane), acc[sl][cch], x);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            st_acc<double>(Rt(j), x, lane);
+          }
+        }
+      } else if (wave == (j & 3)) {
         V4 x = {0, 0, 0, 0};
 #pragma unroll
         for (int cch = 0; cch < 4; ++cch)
-          x = Mfma<double>::op(ld_rowcol(Rt(j), cch, lane), ld_colrow(Wt(j), cch, lane), x);   // Z_j^T W_j
+          x = Mfma<double>::op(ld_rowcol(Rt(j), cch, lane), ld_colrow(Wt(j), cch, lane), x);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         st_acc<double>(Rt(j), x, lane);
       }
@@ -580,19 +624,29 @@ __global__ void __launch_bounds__(rr::NTHREADS, 2) k_local_rr(BatchDev b, LocalA
 }
 
 // ------------------------------------------------------------------ launch
-size_t local_rr_lds_bytes(int n_cap, int f_cap, int k_cap) {
-  return sizeof(double) * (10 * (size_t)n_cap + (size_t)f_cap + (size_t)k_cap + (size_t)(3 * rr::NT) * TILE);
+size_t local_rr_lds_bytes(int n_cap, int f_cap, int k_cap, int occ) {
+  if (occ != 3)
+    return sizeof(double) * (10 * (size_t)n_cap + (size_t)f_cap + (size_t)k_cap + (size_t)(3 * rr::NT) * TILE);
+  const size_t p_len = std::max((size_t)rr::NT * TILE, (size_t)k_cap + 8 * (size_t)n_cap);
+  return sizeof(double) * (2 * (size_t)n_cap + (size_t)f_cap + p_len + TILE + (size_t)rr::NT * TILE);
 }
 int local_rr_max_nt() { return rr::NT; }
 
-hipError_t launch_local_rr(bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid, hipStream_t st) {
-  const BatchDev d = to_dev(bt);
-  const void* kern = fused ? (const void*)k_local_rr<true> : (const void*)k_local_rr<false>;
-  hipError_t err = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+template <bool FUSED, int OCC>
+static hipError_t launch_rr_t(const BatchDev& d, LocalArgs a, size_t lds, int grid, hipStream_t st) {
+  auto kern = k_local_rr<FUSED, OCC>;
+  hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
-  if (fused) hipLaunchKernelGGL(k_local_rr<true>, dim3(grid), dim3(rr::NTHREADS), lds, st, d, a);
-  else hipLaunchKernelGGL(k_local_rr<false>, dim3(grid), dim3(rr::NTHREADS), lds, st, d, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(rr::NTHREADS), lds, st, d, a);
   return hipGetLastError();
+}
+
+hipError_t launch_local_rr(bool fused, int occ, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
+                           hipStream_t st) {
+  if (occ != 2 && occ != 3) return hipErrorInvalidValue;
+  const BatchDev d = to_dev(bt);
+  if (fused) return occ == 3 ? launch_rr_t<true, 3>(d, a, lds, grid, st) : launch_rr_t<true, 2>(d, a, lds, grid, st);
+  return occ == 3 ? launch_rr_t<false, 3>(d, a, lds, grid, st) : launch_rr_t<false, 2>(d, a, lds, grid, st);
 }
 
 }  // namespace mhm

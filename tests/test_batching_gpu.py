@@ -90,6 +90,23 @@ def test_kernel_families_agree_with_oracle(env):
         c.close()
 
 
+@pytest.mark.parametrize("occ", ["2", "3"])
+@pytest.mark.parametrize("mode", ["fused", "three"])
+def test_register_tile_kernel_both_occupancies(occ, mode):
+    """The FP64 register-tile kernel built for two and for three resident
+    workgroups per CU (the defaults: three fused, two for the factor and
+    solve call), fused and as the three calls."""
+    from paper_1703_10435_amd import engine
+    c = _ctx({"MHM_RR_OCC": occ})
+    try:
+        b = _random_batch(26, [2, 5, 9, 12, 16, 16, 7], [0, 1, 2, 3, 2, 3, 1], "occupancy")
+        say(f"[gpu] register tiles occ={occ} mode={mode}")
+        res, out, db = engine.solve_batch(b, prec=0, mode=mode, ctx=c)
+        _check(res, b, range(b["n_elem"]), 0, f"register tiles occ={occ} {mode}")
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_graph_replays_match_eager(ctx, prec):
     import torch
