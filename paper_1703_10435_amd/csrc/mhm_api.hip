@@ -152,9 +152,10 @@ Plan plan_for(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused, int s_
   const int slots = std::min(b->n_elem, 2 * c->n_cu);
   switch (ch.fam) {
     case FAM_RR:
-      // two or three resident workgroups per CU; by default three for the
-      // fused kernel, two for the factor-and-solve one (more registers)
-      if (p.ch.occ != 2 && p.ch.occ != 3) p.ch.occ = c->rr_occ ? c->rr_occ : fused ? 3 : 2;
+      // two or three resident workgroups per CU; by default two (the build
+      // for three spills in its factorisation loop: at C2 it is 3% faster
+      // but moves eight times the bytes, so only the tuner picks it)
+      if (p.ch.occ != 2 && p.ch.occ != 3) p.ch.occ = c->rr_occ ? c->rr_occ : 2;
       p.ok = !fp32 && p.nt <= mhm::local_rr_max_nt() && one_chunk;
       p.k_cap = k_lds;
       p.lds = mhm::local_rr_lds_bytes(p.n_cap, p.f_cap, k_lds, p.ch.occ);

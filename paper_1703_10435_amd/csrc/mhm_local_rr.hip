@@ -199,7 +199,7 @@ __device__ __forceinline__ void store_L(double* Lo, int n, int I, int J, const V
 }  // namespace rr
 
 // OCC: resident workgroups per CU the registers are budgeted for (2: 256
-// per lane; 3: 168, with some spilling in the update loops).
+// per lane, no spills; 3: 168, with spills in the factorisation loop).
 template <bool FUSED, int OCC>
 __global__ void __launch_bounds__(rr::NTHREADS, OCC) k_local_rr(BatchDev b, LocalArgs args) {
   using namespace rr;

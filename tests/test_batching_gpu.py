@@ -93,9 +93,9 @@ def test_kernel_families_agree_with_oracle(env):
 @pytest.mark.parametrize("occ", ["2", "3"])
 @pytest.mark.parametrize("mode", ["fused", "three"])
 def test_register_tile_kernel_both_occupancies(occ, mode):
-    """The FP64 register-tile kernel built for two and for three resident
-    workgroups per CU (the defaults: three fused, two for the factor and
-    solve call), fused and as the three calls."""
+    """The FP64 register-tile kernel built for two (the default) and for
+    three resident workgroups per CU (a tuner candidate), fused and as the
+    three calls."""
     from paper_1703_10435_amd import engine
     c = _ctx({"MHM_RR_OCC": occ})
     try:
