@@ -17,7 +17,9 @@
 //       panel solve and in-panel updates in registers) and written once.
 // Each tile of L is therefore written once and read once per later block
 // column, about n^3/(6*16*PW) tile reads per element instead of the
-// n^3/(3*16) read-modify-writes of a right-looking sweep.
+// n^3/(3*16) read-modify-writes of a right-looking sweep.  Where a wave's
+// rows of a wide panel would not fit in registers, (a)-(c) run over the
+// rows in passes (the constant RS of the kernel).
 #pragma once
 #include "mhm_common.h"
 #include "mhm_kernels.h"
