@@ -408,6 +408,7 @@ def _skeleton_leg(torch, ctx, batch, db, out, steps):
 
 def extra_legs(torch, ctx, db, out, args, checks):
     from paper_1703_10435_amd import abi, engine
+    from paper_1703_10435_amd.batch import DeviceBatch
     E = db.n_elem
     ex = {}
     legs = [x.strip().upper() for x in args.legs.split(",") if x.strip()]
@@ -439,6 +440,23 @@ def extra_legs(torch, ctx, db, out, args, checks):
                          "bytes": "assemble: 16 s^2 + 8 n^2 + 8 n r + 8 n + 8 per element; contrib: "
                                   "8 (3 s r + s^2 + NImax^2 + 2 NImax + 1) per element"})
         del o3
+        # host to host: the host batch validated, offset and uploaded, the
+        # fused FP64 run, and X, M, E, B, F, info copied back (never `value`)
+        def h2h():
+            dbh = DeviceBatch(args.batch)
+            oh = dbh.alloc_outputs(three_call=False)
+            engine.run_fused(ctx, dbh, abi.MHM_FP64, oh)
+            return [oh[k].cpu() for k in ("X", "M", "E", "B", "F", "info")]
+        h2h()
+        torch.cuda.synchronize()
+        reps = max(3, min(args.steps, 10))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            h2h()
+        ms_h = (time.perf_counter() - t0) * 1e3 / reps
+        ex["C2"].update({"host_to_host_ms": ms_h, "host_to_host_problems_per_s": E / (ms_h * 1e-3),
+                         "host_to_host": "host batch validated and uploaded, fused FP64 run, "
+                                         "X, M, E, B, F, info downloaded; wall clock"})
     if "C3" in legs:
         ex["C3"] = _batched_leg(torch, ctx, "C3", 3, checks)
     if "C4" in legs:
