@@ -600,9 +600,17 @@ def main():
         for leg, ok in verdict.items():
             line["extra"][leg]["error_check"] = "pass" if ok else "FAIL"
             line["extra"][leg]["tolerance"] = "max(1e-10 FP64 | 1e-8 FP32+IR, 10 cond2(Ahat) u64) per element"
+        model = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+        except OSError:
+            pass
         line["cpu_baseline"] = {"value": cb["rate"], "unit": "local problems/s", "cores": cores, "kind": "oracle",
                                 "sample": f"{len(idx)} of the {E} elements (seeded), one element per task, "
-                                          f"{cb['cpu_seconds']:.1f} CPU-s in {cb['wall']:.1f} s wall"}
+                                          f"{cb['cpu_seconds']:.1f} CPU-s in {cb['wall']:.1f} s wall; "
+                                          f"one core: {len(idx) / max(cb['cpu_seconds'], 1e-9):.0f} local problems/s; "
+                                          f"{model}"}
         line["max_rel_err"] = float(np.max(errs))
         line["rel_err_p99"] = float(np.percentile(errs, 99))
         line["error_check"] = "pass" if line["max_rel_err"] <= 1e-10 and line["info_nonzero"] == 0 else "FAIL"
