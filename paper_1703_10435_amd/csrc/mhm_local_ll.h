@@ -193,13 +193,17 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
   typedef typename Mfma<T>::v4 V4;
   constexpr int NW = NWV;
   constexpr int NTHREADS = 64 * NW;
-  // Row passes per block column: with ten rows per wave, a panel wider than
-  // 80 accumulator registers per lane (two FP32 or one FP64 tile per row)
-  // would not fit next to the operands, so the rows are updated and solved
-  // in passes of five or two; the earlier columns' B tiles are staged once
+  // Row passes per block column: with ten rows per wave (8 waves), a panel
+  // wider than 80 accumulator registers per lane (two FP32 or one FP64 tile
+  // per row) would not fit next to the operands, so the rows are updated and
+  // solved in passes of five or two; with 16 waves (128 registers) the limit
+  // is 40, passes of one row.  The earlier columns' B tiles are staged once
   // per pass, the A tiles (the bulk of the reads) still once per panel.
   constexpr int ACC = PW * 4 * (int)(sizeof(T) / 4);   // accumulator registers per row
-  constexpr int RS = (MC || OCC != 1 || NW != 8 || RPW != 10) ? 1 : 10 * ACC <= 80 ? 1 : 5 * ACC <= 80 ? 2 : 5;
+  constexpr int RS = (MC || OCC != 1)            ? 1
+                     : NW == 8 && RPW == 10       ? (10 * ACC <= 80 ? 1 : 5 * ACC <= 80 ? 2 : 5)
+                     : NW == 16 && RPW == 5       ? (5 * ACC <= 40 ? 1 : 5)
+                                                  : 1;
   constexpr int RH = RPW / RS;
   __shared__ Elem E;
   __shared__ int ok, bad, conv;
