@@ -410,6 +410,76 @@ def test_rank_one_augmented_matrix_gives_same_solution_for_any_gamma():
         assert np.abs(X - r["X"]).max() < 1e-12 * scale
 
 
+def _exact_bordered_solve(A, c, B):
+    """The bordered system [[A, c], [c^T, 0]] [X; mu] = [B; 0] solved in
+    exact rational arithmetic (Gaussian elimination on Fractions of the FP64
+    entries), rounded to FP64."""
+    n, r = B.shape
+    N = n + 1
+    M = [[Fraction(float(A[i, j])) for j in range(n)] + [Fraction(float(c[i]))] for i in range(n)]
+    M.append([Fraction(float(x)) for x in c] + [Fraction(0)])
+    R = [[Fraction(float(B[i, k])) for k in range(r)] for i in range(n)] + [[Fraction(0)] * r]
+    for k in range(N):
+        piv = next(i for i in range(k, N) if M[i][k] != 0)
+        M[k], M[piv] = M[piv], M[k]
+        R[k], R[piv] = R[piv], R[k]
+        for i in range(k + 1, N):
+            if M[i][k] == 0:
+                continue
+            f = M[i][k] / M[k][k]
+            for j in range(k, N):
+                M[i][j] -= f * M[k][j]
+            for j in range(r):
+                R[i][j] -= f * R[k][j]
+    X = [[Fraction(0)] * r for _ in range(N)]
+    for i in reversed(range(N)):
+        for j in range(r):
+            X[i][j] = (R[i][j] - sum(M[i][k] * X[k][j] for k in range(i + 1, N))) / M[i][i]
+    return np.array([[float(X[i][j]) for j in range(r)] for i in range(n)])
+
+
+@pytest.mark.parametrize("s,contrast", [(6, 1.0e8), (8, 1.0e10), (8, 1.0e4)])
+def test_refined_solve_is_the_exact_solution_of_high_contrast_elements(s, contrast):
+    """A channel of sub-triangles with kappa = contrast across the element
+    (two row strips), kappa = 1 elsewhere: the condition number of the
+    bordered system reaches 1e9-1e12, where a plain FP64 LU solve is off by
+    1e-10-1e-7.  The oracle's refined solve equals the exact rational
+    solution of the same FP64 system to rounding."""
+    h = 0.25
+    vert = np.array([0.0, 0.0, h, 0.0, h, h])
+    kap = np.ones(s * s)
+    for j in (s // 2, s // 2 + 1):
+        for i in range(s - j):
+            kap[j * (2 * s - j) + 2 * i] = contrast
+            if i < s - j - 1:
+                kap[j * (2 * s - j) + 2 * i + 1] = contrast
+    sig = np.array([1, -1, 1], dtype=np.int8)
+    fl = np.array([0, 1, 0], dtype=np.int8)
+    rng = np.random.default_rng(int(s))
+    f = rng.uniform(0.5, 1.5, s * s)
+    A = local.stiffness(vert, s, kap)
+    c = local.mean_vector(vert, s)
+    B = np.column_stack([local.face_loads(vert, s, 1, sig, fl), local.source_load(vert, s, f)])
+    Xe = _exact_bordered_solve(A, c, B)
+    scale = np.abs(Xe).max()
+    X, _ = local.solve_zero_mean(A, c, B)
+    assert np.abs(X - Xe).max() <= 2e-16 * scale
+    X0, _ = local.solve_zero_mean(A, c, B, refine=False)
+    if contrast >= 1e8:   # the plain solve really is inaccurate here
+        assert np.abs(X0 - Xe).max() > 1e-12 * scale
+
+
+@pytest.mark.parametrize("s", [1, 2, 5, 16])
+def test_subtriangle_order_matches_the_coefficient_sampling_points(s):
+    """kappa and f are sampled at mhm_inputs' sub-triangle centroids; the
+    oracle's sub-triangle t must be the one whose centroid is sample t."""
+    from mhm_inputs.mesh import subtri_centroids
+    vert = np.array([0.1, 0.2, 0.9, 0.3, 0.4, 1.1])
+    nodes, tris = local.submesh(vert, s)
+    cent = nodes[tris].mean(axis=1)
+    np.testing.assert_allclose(cent, subtri_centroids(vert, s), rtol=0, atol=1e-14)
+
+
 # ------------------------------------------------------------ skeleton level
 def _solve_global(N, s, l, kfun, ffun):
     mesh = coarse_mesh(N)
