@@ -137,6 +137,40 @@ mhm_status mhm_create(mhm_ctx* ctx, int device, void* hip_stream);
 mhm_status mhm_destroy(mhm_ctx ctx);
 /* Change the stream subsequent calls enqueue on. */
 mhm_status mhm_set_stream(mhm_ctx ctx, void* hip_stream);
+
+/* Context options (mhm_set_option); every one defaults to 0.
+ *  MHM_OPT_REFINE64  the FP64 path's refinement step.  A plain FP64
+ *                    Cholesky solve has a forward error that grows with the
+ *                    condition number of Ahat, roughly the coefficient
+ *                    contrast (max kappa / min kappa over the element) times
+ *                    s^2: below 1e-13 for smooth fields, about 1e-10 for a
+ *                    contrast of 1e4 at s = 32.  0: elements whose contrast
+ *                    times s^2 exceeds 2^20 get one refinement step, its
+ *                    residual Btilde - Ahat X accumulated in double-double
+ *                    (the solution then matches the exact one of the
+ *                    assembled system to about 1e-15); 1: every element;
+ *                    -1: none.  ir_iters reports the step (1).
+ *  Launch configuration (the results do not depend on them, beyond
+ *  rounding; used to exercise kernel families the defaults do not pick, and
+ *  reproduced by mhm_autotune's timings):
+ *  MHM_OPT_NO_RR     1: never the register-tile kernel
+ *  MHM_OPT_NO_LL     1: never the left-looking kernel
+ *  MHM_OPT_LL_OCC2   1: left-looking default with two workgroups per CU
+ *  MHM_OPT_LL_NW16   1: left-looking default with 16 waves, where built
+ *  MHM_OPT_LL_PW     0, 1, 2, 4: left-looking default panel width, where built
+ *  MHM_OPT_RR_OCC    0, 2, 3: register-tile kernel's workgroups per CU
+ * Returns MHM_E_ARG for an unknown option or value.  Applies to later calls
+ * (a captured graph keeps the configuration of its capture). */
+typedef enum {
+  MHM_OPT_REFINE64 = 0,
+  MHM_OPT_NO_RR = 1,
+  MHM_OPT_NO_LL = 2,
+  MHM_OPT_LL_OCC2 = 3,
+  MHM_OPT_LL_NW16 = 4,
+  MHM_OPT_LL_PW = 5,
+  MHM_OPT_RR_OCC = 6
+} mhm_option;
+mhm_status mhm_set_option(mhm_ctx ctx, int option, int value);
 /* Text of the last call-level error on this context ("" if none); with a
  * NULL context, the last error of a context-less call (mhm_create) on the
  * calling thread. */
@@ -166,7 +200,8 @@ mhm_status mhm_local_assemble(mhm_ctx ctx, const mhm_batch* batch,
  *            strict upper part is unspecified.
  *   Btilde   in: compatible right-hand sides.
  *   X        out: n x r solutions (FP64).
- *   ir_iters out (may be NULL): refinement steps taken per element.
+ *   ir_iters out (may be NULL): refinement steps taken per element (FP64:
+ *            0, or 1 where MHM_OPT_REFINE64 gave the element its step).
  *   max_iters: refinement step limit (MHM_FP32_IR; ignored for MHM_FP64). */
 mhm_status mhm_local_factor_solve(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec,
                                   double* Ahat_io, const double* Btilde, double* X,

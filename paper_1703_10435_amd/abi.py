@@ -23,8 +23,15 @@ EXPORTS = (
     "mhm_local_assemble", "mhm_local_factor_solve", "mhm_skeleton_contrib", "mhm_local_batch_run",
     "mhm_autotune", "mhm_tune_report", "mhm_graph_create", "mhm_graph_launch", "mhm_graph_destroy",
     "mhm_factor_bytes", "mhm_local_batch_run_cached", "mhm_skeleton_scatter", "mhm_reconstruct",
-    "mhm_local_source_step", "mhm_skeleton_solve",
+    "mhm_local_source_step", "mhm_skeleton_solve", "mhm_set_option",
 )
+
+# Context options (mhm_set_option)
+MHM_OPT_REFINE64, MHM_OPT_NO_RR, MHM_OPT_NO_LL, MHM_OPT_LL_OCC2, MHM_OPT_LL_NW16, MHM_OPT_LL_PW, MHM_OPT_RR_OCC = \
+    range(7)
+OPTION_NAMES = {"refine64": MHM_OPT_REFINE64, "no_rr": MHM_OPT_NO_RR, "no_ll": MHM_OPT_NO_LL,
+                "ll_occ2": MHM_OPT_LL_OCC2, "ll_nw16": MHM_OPT_LL_NW16, "ll_pw": MHM_OPT_LL_PW,
+                "rr_occ": MHM_OPT_RR_OCC}
 
 
 class mhm_batch(ctypes.Structure):
@@ -64,6 +71,7 @@ def load(path: str = LIB_PATH):
         "mhm_create": (i32, [ctypes.POINTER(vp), i32, vp]),
         "mhm_destroy": (i32, [vp]),
         "mhm_set_stream": (i32, [vp, vp]),
+        "mhm_set_option": (i32, [vp, i32, i32]),
         "mhm_last_error": (ctypes.c_char_p, [vp]),
         "mhm_sync": (i32, [vp]),
         "mhm_workspace_bytes": (ctypes.c_size_t, [vp, bp, i32]),
@@ -104,7 +112,10 @@ def _ptr(t):
 class Context:
     """An ``mhm_ctx`` bound to a device and a torch HIP stream."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, **options):
+        """``options``: context options by name (``refine64``, ``no_rr``,
+        ``no_ll``, ``ll_occ2``, ``ll_nw16``, ``ll_pw``, ``rr_occ``; see
+        mhm_set_option)."""
         import torch
         lib = load()
         self.lib = lib
@@ -117,6 +128,13 @@ class Context:
         if st != MHM_OK:
             raise MhmError(st, "mhm_create: " + lib.mhm_last_error(None).decode())
         self.h = h
+        for name, value in options.items():
+            self.set_option(name, value)
+
+    def set_option(self, option, value: int):
+        """mhm_set_option; ``option`` is an MHM_OPT_* value or its name."""
+        opt = OPTION_NAMES[option] if isinstance(option, str) else int(option)
+        self._check(self.lib.mhm_set_option(self.h, opt, int(value)))
 
     def set_stream(self, stream):
         self.stream = stream

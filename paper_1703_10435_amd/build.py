@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmhm.so")
 SOURCES = ["mhm_kernels.hip", "mhm_local_rr.hip", "mhm_local_ll.hip", "mhm_local_ll_f32.hip", "mhm_local_ll_f64.hip",
+           "mhm_local_ll_f64r.hip",
            "mhm_source_step.hip", "mhm_skeleton_solve.hip", "mhm_api.hip", "mhm_server.hip"]
 ARCH = "gfx950"
 

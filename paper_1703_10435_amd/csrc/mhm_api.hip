@@ -58,12 +58,14 @@ struct mhm_ctx_s {
   hipStream_t stream = nullptr;
   int n_cu = 256;
   size_t lds_limit = 160 * 1024;
-  bool no_rr = false;          // MHM_NO_RR=1: never use the register-tile kernel
-  bool no_ll = false;          // MHM_NO_LL=1: never use the left-looking kernel
-  bool ll_occ2 = false;        // MHM_LL_OCC2=1: left-looking default with two workgroups per CU
-  bool ll_nw16 = false;        // MHM_LL_NW16=1: left-looking default with 16 waves where it applies
-  int ll_pw = 0;               // MHM_LL_PW=1|2|4: left-looking default panel width, where built
-  int rr_occ = 0;              // MHM_RR_OCC=2|3: register-tile kernel default workgroups per CU
+  // options (mhm_set_option)
+  bool no_rr = false;          // never use the register-tile kernel
+  bool no_ll = false;          // never use the left-looking kernel
+  bool ll_occ2 = false;        // left-looking default with two workgroups per CU
+  bool ll_nw16 = false;        // left-looking default with 16 waves where it applies
+  int ll_pw = 0;               // left-looking default panel width (1, 2, 4), where built
+  int rr_occ = 0;              // register-tile kernel default workgroups per CU (2, 3)
+  int refine64 = 0;            // FP64 refinement: 0 where needed, 1 every element, -1 none
   void* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t aux[kNumClasses] = {};   // class streams of ragged runs
@@ -125,6 +127,7 @@ int grid_for(const mhm_batch* b) { return std::min(b->n_elem, kGridCap); }
 struct Plan {
   bool ok = false, fp32 = false, fused = false;
   bool mc = false;   // more than RHS_CHUNK right-hand sides (left-looking kernel only)
+  bool ref = false;  // FP64 left-looking instance with the refinement step (the FP64 pass)
   Choice ch;
   int nt = 0, tile_cap = 0, n_cap = 0, f_cap = 0, k_cap = 0, grid = 0;
   size_t lds = 0, ws_need = 0;
@@ -208,19 +211,34 @@ Choice default_choice(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused
   return Choice{FAM_WS, 0};
 }
 
-// The FP64 recomputation pass of an FP32 launch (refinement that did not
-// converge): left-looking where it applies, else the workspace kernel.
-Plan fallback_plan(const mhm_ctx c, const mhm_batch* b, int s_cap, bool listed) {
-  const int nt = (n_of(s_cap) + 15) / 16;
-  Plan p = plan_for(c, b, false, true, s_cap, Choice{FAM_LL, mhm::local_ll_default_panel(false, nt)}, listed);
-  if (!p.ok) p = plan_for(c, b, false, true, s_cap, Choice{FAM_LL, 2}, listed);
-  if (c->no_ll || !p.ok) p = plan_for(c, b, false, true, s_cap, Choice{FAM_WS, 0}, listed);
+// The FP64 pass after a launch, always from kappa (fused): the
+// recomputation of an FP32 launch's elements whose refinement did not
+// converge, or the elements an FP64 launch deferred because they need the
+// refinement step (after a three-call factor_solve it also writes their
+// factor).  Left-looking where it applies, else the workspace kernel.
+Plan fallback_plan(const mhm_ctx c, const mhm_batch* b, int s_cap, bool listed, bool cached = false) {
+  // the left-looking instances with the refinement step: panel width 2, 8
+  // waves (with stored factors: the deferred elements of a cached FP64 run)
+  Plan p = plan_for(c, b, false, true, s_cap, Choice{FAM_LL, 2, 1, 8}, listed, cached);
+  if (!cached && (c->no_ll || !p.ok)) p = plan_for(c, b, false, true, s_cap, Choice{FAM_WS, 0}, listed);
+  p.ref = true;
   return p;
+}
+
+// Whether an FP64 pass follows a main launch: always after FP32 (the
+// recomputation of elements whose refinement did not converge); after the
+// FP64 register-tile kernel and the one-chunk FP64 left-looking instances
+// when they may defer elements that need the refinement step.
+bool has_fp64_pass(const mhm_ctx c, const Plan& m) {
+  if (m.fp32) return true;
+  if (c->refine64 < 0) return false;
+  return (m.ch.fam == FAM_RR && m.fused) || (m.ch.fam == FAM_LL && !m.mc);
 }
 
 // Everything one run of the local problems enqueues.
 struct ClassRun {
   int cls = 0, s_cap = 0;
+  bool has_fb = false;   // an FP64 pass follows the main launch
   Plan main, fb;
   size_t ws_off = 0;   // this class's workspace (main and fallback pass share it)
 };
@@ -257,9 +275,12 @@ RunPlan make_run_plan(const mhm_ctx c, const mhm_batch* b, bool fp32, bool fused
       ch = default_choice(c, b, fp32, fused, r.s_cap, rp.listed);
     }
     r.main = plan_for(c, b, fp32, fused, r.s_cap, ch, rp.listed, cached);
-    if (fp32) r.fb = fallback_plan(c, b, r.s_cap, rp.listed);
+    // the FP64 pass: FP32 recomputation, or the elements an FP64 launch
+    // defers (those that need the refinement step)
+    r.has_fb = has_fp64_pass(c, r.main);
+    if (r.has_fb) r.fb = fallback_plan(c, b, r.s_cap, rp.listed, !fp32 && cached);
     r.ws_off = off;
-    off += std::max(r.main.ws_need, fp32 ? r.fb.ws_need : 0);
+    off += std::max(r.main.ws_need, r.has_fb ? r.fb.ws_need : 0);
   }
   rp.ws_total = off;
   return rp;
@@ -315,14 +336,17 @@ hipError_t launch_plan(const Plan& p, const mhm_batch* b, const mhm::LocalArgs& 
     case FAM_RR: return mhm::launch_local_rr(p.fused, p.ch.occ, b, a, p.lds, p.grid, st);
     case FAM_LDS: return mhm::launch_local(p.fp32, true, p.fused, b, a, p.lds, p.grid, st);
     case FAM_LL:
-      return mhm::launch_local_ll(p.fp32, p.fused, p.ch.pw, p.ch.occ, p.ch.nw, p.mc, p.nt, b, a, p.lds, p.grid, st);
+      return mhm::launch_local_ll(p.fp32, p.fused, p.ch.pw, p.ch.occ, p.ch.nw, p.mc, p.ref, p.nt, b, a, p.lds, p.grid,
+                                  st);
     default: return mhm::launch_local(p.fp32, false, p.fused, b, a, p.lds, p.grid, st);
   }
 }
 
-mhm::LocalArgs local_args(const Plan& p, const RunIO& io, void* ws, const int32_t* elist, const int32_t* ecount) {
+mhm::LocalArgs local_args(const mhm_ctx c, const Plan& p, const RunIO& io, void* ws, const int32_t* elist,
+                          const int32_t* ecount) {
   mhm::LocalArgs a;
   std::memset(&a, 0, sizeof(a));
+  a.refine64 = c->refine64;
   a.Ahat = io.Ahat;
   a.Btil = io.Btil;
   a.Lout = io.Lout;
@@ -349,28 +373,42 @@ mhm::LocalArgs local_args(const Plan& p, const RunIO& io, void* ws, const int32_
   return a;
 }
 
-// One class: the main pass, then (FP32) the FP64 pass of the elements whose
-// refinement did not converge.
+// One class: the main pass, then the FP64 pass: of the elements whose FP32
+// refinement did not converge, or of those an FP64 register-tile launch
+// deferred to a kernel with the refinement step.
 mhm_status enqueue_class(mhm_ctx c, const ClassRun& r, const mhm_batch* b, const RunIO& io, char* ws,
                          const int32_t* elist, const int32_t* ecount, hipStream_t st, bool fallback_only = false) {
   hipError_t e = hipSuccess;
   if (!fallback_only) {
-    mhm::LocalArgs a = local_args(r.main, io, ws + r.ws_off, elist, ecount);
+    mhm::LocalArgs a = local_args(c, r.main, io, ws + r.ws_off, elist, ecount);
     e = launch_plan(r.main, b, a, st);
     if (e != hipSuccess) return hip_fail(c, e, "local kernel launch");
   }
-  if (r.main.fp32) {
+  if (r.has_fb && r.main.fp32) {
     RunIO f = io;
     f.Ahat = nullptr;
     f.Btil = nullptr;
+    f.Lout = nullptr;  // the FP32 factor stays in Ahat_io
     f.fac = nullptr;   // the FP64 recomputation does not store its factor
     f.fac_off = nullptr;
     f.fac_state = nullptr;
     if (!r.main.fused) f.M = f.E = f.B = f.F = nullptr;
-    mhm::LocalArgs fa = local_args(r.fb, f, ws + r.ws_off, elist, ecount);
+    mhm::LocalArgs fa = local_args(c, r.fb, f, ws + r.ws_off, elist, ecount);
     fa.only_fallback = 1;
     e = launch_plan(r.fb, b, fa, st);
     if (e != hipSuccess) return hip_fail(c, e, "FP64 fallback launch");
+  } else if (r.has_fb) {
+    // deferred elements of an FP64 launch: recomputed from kappa, with the
+    // same outputs (the three-call form's factor into Ahat_io, the contribution
+    // blocks of the fused form), and their info ends 0
+    RunIO f = io;
+    f.Ahat = nullptr;
+    f.Btil = nullptr;
+    mhm::LocalArgs fa = local_args(c, r.fb, f, ws + r.ws_off, elist, ecount);
+    fa.only_fallback = 1;
+    fa.fb_final = 1;
+    e = launch_plan(r.fb, b, fa, st);
+    if (e != hipSuccess) return hip_fail(c, e, "FP64 refinement pass launch");
   }
   return MHM_OK;
 }
@@ -495,6 +533,8 @@ Choice tune_class(mhm_ctx c, const mhm_batch* b, bool fp32, const RunPlan& base,
   for (const Choice& ch : cands) {
     ClassRun r = r0;
     r.main = plan_for(c, b, fp32, true, r.s_cap, ch, base.listed);
+    r.has_fb = has_fp64_pass(c, r.main);
+    if (r.has_fb) r.fb = fallback_plan(c, b, r.s_cap, base.listed);
     r.ws_off = base.list_bytes;   // classes are tuned one after another
     float ms = 0.0f;
     for (int rep = 0; rep < 3 && st == MHM_OK; ++rep) {   // first repetition warms up
@@ -539,18 +579,6 @@ mhm_status mhm_create(mhm_ctx* out, int device, void* hip_stream) {
   if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
   mhm_ctx c = new mhm_ctx_s();
   c->device = device;
-  const char* nrr = std::getenv("MHM_NO_RR");
-  c->no_rr = nrr && nrr[0] == '1';
-  const char* nll = std::getenv("MHM_NO_LL");
-  c->no_ll = nll && nll[0] == '1';
-  const char* occ2 = std::getenv("MHM_LL_OCC2");
-  c->ll_occ2 = occ2 && occ2[0] == '1';
-  const char* nw16 = std::getenv("MHM_LL_NW16");
-  c->ll_nw16 = nw16 && nw16[0] == '1';
-  const char* llpw = std::getenv("MHM_LL_PW");
-  if (llpw && (llpw[0] == '1' || llpw[0] == '2' || llpw[0] == '4') && llpw[1] == 0) c->ll_pw = llpw[0] - '0';
-  const char* rrocc = std::getenv("MHM_RR_OCC");
-  if (rrocc && (rrocc[0] == '2' || rrocc[0] == '3') && rrocc[1] == 0) c->rr_occ = rrocc[0] - '0';
   c->stream = static_cast<hipStream_t>(hip_stream);
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0) c->n_cu = v;
@@ -575,6 +603,34 @@ mhm_status mhm_destroy(mhm_ctx c) {
   if (c->ws) (void)hipFree(c->ws);
   delete c;
   return MHM_OK;
+}
+
+mhm_status mhm_set_option(mhm_ctx c, int option, int value) {
+  if (!c) return MHM_E_ARG;
+  auto flag = [&](bool& dst) {
+    if (value != 0 && value != 1) return fail(c, MHM_E_ARG, "option value must be 0 or 1");
+    dst = value != 0;
+    return MHM_OK;
+  };
+  switch (option) {
+    case MHM_OPT_REFINE64:
+      if (value < -1 || value > 1) return fail(c, MHM_E_ARG, "MHM_OPT_REFINE64 takes -1, 0 or 1");
+      c->refine64 = value;
+      return MHM_OK;
+    case MHM_OPT_NO_RR: return flag(c->no_rr);
+    case MHM_OPT_NO_LL: return flag(c->no_ll);
+    case MHM_OPT_LL_OCC2: return flag(c->ll_occ2);
+    case MHM_OPT_LL_NW16: return flag(c->ll_nw16);
+    case MHM_OPT_LL_PW:
+      if (value != 0 && value != 1 && value != 2 && value != 4) return fail(c, MHM_E_ARG, "MHM_OPT_LL_PW takes 0, 1, 2 or 4");
+      c->ll_pw = value;
+      return MHM_OK;
+    case MHM_OPT_RR_OCC:
+      if (value != 0 && value != 2 && value != 3) return fail(c, MHM_E_ARG, "MHM_OPT_RR_OCC takes 0, 2 or 3");
+      c->rr_occ = value;
+      return MHM_OK;
+    default: return fail(c, MHM_E_ARG, "unknown option " + std::to_string(option));
+  }
 }
 
 mhm_status mhm_set_stream(mhm_ctx c, void* hip_stream) {
@@ -755,6 +811,7 @@ mhm_status mhm_local_source_step(mhm_ctx c, const mhm_batch* b, mhm_prec prec, c
   a.info = info;
   a.ir_iters = ir_iters;
   a.max_iters = std::max(0, max_iters);
+  a.refine64 = c->refine64;
   a.ir_tol = kIrTol;
   a.n_cap = n_of(b->s_max);
   const size_t lds = mhm::source_step_lds(fp32, a.n_cap, a.wave_words);
@@ -790,7 +847,8 @@ mhm_status mhm_autotune(mhm_ctx c, const mhm_batch* b, mhm_prec prec, double* X,
       const Plan p = plan_for(c, b, fp32, true, base.run[i].s_cap, ch, base.listed);
       if (p.ok) need = std::max(need, p.ws_need);
     }
-    need = std::max(need, base.run[i].fb.ws_need);
+    // the FP64 pass (FP32 recomputation, or the register-tile kernel's deferred elements)
+    need = std::max(need, fallback_plan(c, b, base.run[i].s_cap, base.listed).ws_need);
   }
   const size_t cnt_off = base.list_bytes + need;
   st = ensure_ws(c, std::max(base.ws_total, cnt_off + kAlign));

@@ -365,7 +365,11 @@ namespace mhm {
 // into the right-hand-side tiles (tile J holds rows 16J.. of R^T; cx holds
 // c^T X per column).  Returns the row-sum norm of Ahat (all threads).
 // Btilde comes from the tables (fused) or from Btg (column-major n x r).
-template <typename T, bool FUSED>
+// DD: the products and their sum in double-double, rounded once (the FP64
+// path's refinement, which must see the residual of an FP64 iterate).  An
+// error in c^T X only moves the residual along c, whose correction is a
+// constant that the zero-mean projection removes.
+template <typename T, bool FUSED, bool DD = false>
 __device__ __forceinline__ double ir_residual_body(const Elem& E, const double* kapp, const double* X,
                                                    const double* c, const double* cx, double g, const double* ft,
                                                    const double* bf, const double* colsum, const double* Btg,
@@ -393,12 +397,31 @@ __device__ __forceinline__ double ir_residual_body(const Elem& E, const double* 
 #pragma unroll 4
     for (int a = 0; a < r; ++a) {
       const double* xa = X + (int64_t)(c0 + a) * n;
-      double ax = st.d * xa[p] + cp * (g * cx[a]);
-      if (hasE) ax += st.e * xa[pE] + st.n * xa[pN];
-      if (hasW) ax += st.w * xa[pW] + st.nw * xa[pNW];
-      if (hasS) ax += st.so * xa[pS] + st.se * xa[pSE];
       const double b = FUSED ? btilde_tab(E, ft, bf, c, colsum, c0 + a, p, i, j) : Btg[(int64_t)(c0 + a) * n + p];
-      rt[a * TST] = (T)(b - ax);
+      if constexpr (DD) {
+        double hi = 0.0, lo = 0.0;
+        dd_add_prod(hi, lo, st.d, xa[p]);
+        dd_add_prod(hi, lo, cp, g * cx[a]);
+        if (hasE) {
+          dd_add_prod(hi, lo, st.e, xa[pE]);
+          dd_add_prod(hi, lo, st.n, xa[pN]);
+        }
+        if (hasW) {
+          dd_add_prod(hi, lo, st.w, xa[pW]);
+          dd_add_prod(hi, lo, st.nw, xa[pNW]);
+        }
+        if (hasS) {
+          dd_add_prod(hi, lo, st.so, xa[pS]);
+          dd_add_prod(hi, lo, st.se, xa[pSE]);
+        }
+        rt[a * TST] = (T)dd_sub_from(b, hi, lo);
+      } else {
+        double ax = st.d * xa[p] + cp * (g * cx[a]);
+        if (hasE) ax += st.e * xa[pE] + st.n * xa[pN];
+        if (hasW) ax += st.w * xa[pW] + st.nw * xa[pNW];
+        if (hasS) ax += st.so * xa[pS] + st.se * xa[pSE];
+        rt[a * TST] = (T)(b - ax);
+      }
     }
   }
   return block_max(anorm, red);   // its barriers also publish the residual tiles
@@ -502,11 +525,11 @@ __device__ __forceinline__ void ir_accumulate_body(double* X, const T* rhs_row, 
 // The three refinement passes as separate functions, for kernels whose
 // registers are already taken by their tiles (pointers may be to LDS or
 // global memory); kernels with tiles in LDS inline the bodies instead.
-template <typename T, bool FUSED>
+template <typename T, bool FUSED, bool DD = false>
 __device__ __noinline__ double ir_residual(const Elem& E, const double* kapp, const double* X, const double* c,
                                            const double* cx, double g, const double* ft, const double* bf,
                                            const double* colsum, const double* Btg, T* rhs_row, double* red) {
-  return ir_residual_body<T, FUSED>(E, kapp, X, c, cx, g, ft, bf, colsum, Btg, rhs_row, red);
+  return ir_residual_body<T, FUSED, DD>(E, kapp, X, c, cx, g, ft, bf, colsum, Btg, rhs_row, red);
 }
 template <typename T, bool FUSED>
 __device__ __noinline__ void ir_colmax(const Elem& E, const T* rhs_row, const double* ft, const double* bf,

@@ -283,6 +283,62 @@ __device__ __forceinline__ int face_pos(int e, int i, int j, int s) {
   return (j == 0) ? i : -1;
 }
 
+// ------------------------------------------------- FP64 refinement criterion
+// The forward error of a plain FP64 Cholesky solve of Ahat grows like its
+// condition number, roughly (max K / min K) s^2 (times a constant of the
+// element's shape): well below 1e-13 on smooth fields (contrast up to a few
+// hundred), but about 1e-10 for a contrast of 1e4 at s = 32.  Elements above
+// this bound get one refinement step with a double-double residual in the
+// FP64 path.
+constexpr double REFINE64_SCALE = 1048576.0;   // 2^20: contrast 1024 at s = 32, 455 at s = 48
+
+// mode > 0: every element, mode < 0: none, 0: contrast s^2 above the bound.
+// Called by every thread of the block (two barriers); `red` holds one double
+// per wave.
+__device__ __forceinline__ bool refine64_needed(int mode, const double* kap, int s, double* red) {
+  if (mode != 0) return mode > 0;
+  double kmax = 0.0, kinv = 0.0;
+  for (int t = threadIdx.x; t < s * s; t += blockDim.x) {
+    const double k = kap[t];
+    kmax = fmax(kmax, k);
+    kinv = fmax(kinv, 1.0 / k);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    kmax = fmax(kmax, __shfl_xor(kmax, o, 64));
+    kinv = fmax(kinv, __shfl_xor(kinv, o, 64));
+  }
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = kmax * kinv;
+  __syncthreads();
+  double con = red[0];
+  for (int k = 1; k < nw; ++k) con = fmax(con, red[k]);
+  // a NaN or infinite contrast (bad coefficients) also takes the refinement
+  return !(con * ((double)s * s) <= REFINE64_SCALE);
+}
+
+// Double-double accumulation (error-free transformations; contraction off
+// so that the error terms are exact): (hi, lo) += a b.
+__device__ __forceinline__ void dd_add_prod(double& hi, double& lo, double a, double b) {
+#pragma clang fp contract(off)
+  const double p = a * b;
+  const double pe = __builtin_fma(a, b, -p);
+  const double t = hi + p;
+  const double bb = t - hi;
+  const double e = (hi - (t - bb)) + (p - bb);
+  hi = t;
+  lo += e + pe;
+}
+// b - (hi + lo), rounded once more to double.
+__device__ __forceinline__ double dd_sub_from(double b, double hi, double lo) {
+#pragma clang fp contract(off)
+  const double t = b - hi;
+  const double bb = t - b;
+  const double e = (b - (t - bb)) + (-hi - bb);
+  return t + (e - lo);
+}
+
 // ------------------------------------------------------------------ MFMA tiles
 // Result layout of v_mfma_*_16x16x4 (one block): lane l holds column l%16 and
 // four rows, item v = 0..3.  For f32 they are rows 4*(l/16)+v; for f64 the

@@ -21,6 +21,10 @@ struct LocalArgs {
   int32_t* ir_iters;    // may be null
   int max_iters;
   int only_fallback;    // process only elements whose info is -1
+  int fb_final;         // with only_fallback: a pass of an FP64 run (elements deferred by the
+                        // register-tile kernel); a finished element's info becomes 0
+  int refine64;         // FP64 refinement with a double-double residual: 0 where the element
+                        // needs it (refine64_needed), 1 every element, -1 none
   double ir_tol;        // normwise backward-error target of the refinement
   void* ws;             // workspace mode: per-workgroup tile slots
   int64_t ws_slot;      // elements (of the tile type) per slot
@@ -48,6 +52,7 @@ struct SourceArgs {
   int32_t* info;
   int32_t* ir_iters;        // may be null
   int max_iters;
+  int refine64;             // as LocalArgs::refine64 (FP64 factors)
   double ir_tol;
   int n_cap;                // largest n of the launch
   int wave_words;           // LDS doubles per wave
@@ -103,13 +108,15 @@ hipError_t launch_local_rr(bool fused, int occ, const mhm_batch* bt, LocalArgs a
                            hipStream_t st);
 // Left-looking kernel for large elements (tiles in a workspace slot), panel
 // width pw (block columns of pw tiles); mc: the instance that takes more than
-// RHS_CHUNK right-hand sides (in chunks).
+// RHS_CHUNK right-hand sides (in chunks); ref (FP64): an instance with the
+// refinement step (pw 2, 8 waves, one workgroup per CU; the chunked ones
+// always have it), required for a pass over deferred elements.
 int local_ll_rows_per_wave(int nt, int nw);
 int local_ll_default_panel(bool fp32, int nt);
 bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw, bool mc);
 size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap, int nw);
-hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, bool mc, int nt_max, const mhm_batch* bt,
-                           LocalArgs a, size_t lds, int grid, hipStream_t st);
+hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, bool mc, bool ref, int nt_max,
+                           const mhm_batch* bt, LocalArgs a, size_t lds, int grid, hipStream_t st);
 hipError_t launch_local(bool fp32, bool in_lds, bool fused, const mhm_batch* bt, LocalArgs a, size_t lds, int grid,
                         hipStream_t st);
 

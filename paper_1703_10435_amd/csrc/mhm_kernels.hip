@@ -197,8 +197,10 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
                  (FUSED && E.NI * (E.s + 1) > args.f_cap) || (FUSED && IN_LDS && E.s * E.s > args.k_cap))
           st = INFO_TOO_LARGE;
         ok = st == INFO_OK;
-        if (!ok || !args.only_fallback) args.info[e] = st;
-        if (args.ir_iters && !args.only_fallback) args.ir_iters[e] = 0;
+        // a pass over the elements an FP64 run deferred owns their info; the
+        // FP64 pass of an FP32 run leaves -1 (and the FP32 step count) on them
+        if (!ok || !args.only_fallback || args.fb_final) args.info[e] = st;
+        if (args.ir_iters && (!args.only_fallback || args.fb_final)) args.ir_iters[e] = 0;
       }
       bad = -1;
       conv = 0;
@@ -249,6 +251,9 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
       if (FUSED) face_colsums(E, ft, colsum);
     }
     __syncthreads();
+    // FP64: one refinement step with a double-double residual where a plain
+    // FP64 solve is not accurate enough (the FP32 path always refines)
+    const bool ref64 = !fp32 && refine64_needed(args.refine64, kapg, s, red);
 
     // ---------------------------------------------------------- fill tiles
     if (FUSED) {
@@ -423,30 +428,40 @@ __global__ void __launch_bounds__(NTHREADS) k_local(BatchDev b, LocalArgs args) 
     double* X = args.X + E.rhs0;
     const int ca = tid >> 4, cl16 = tid & 15;   // 16 columns x 16 lanes for column sums
 
-    if (fp32 && !failed) {
-      // --------------------------------------- FP64 refinement (FP32 path)
+    if ((fp32 || ref64) && !failed) {
+      // ----------------------------------------------- FP64 refinement
+      // FP32 factor: FP64 residuals until the backward error target;
+      // FP64 factor: one step with a double-double residual.
       ir_accumulate_body<T>(X, tl(nt, 0), c, n, r, true, cx, xmax, part_s);
       const double* Btg = FUSED ? nullptr : args.Btil + E.rhs0;
       const double g = gam;
       int it = 0;
       for (;; ++it) {
-        const double anorm = ir_residual_body<T, FUSED>(E, kap_lds ? kapl : kapg, X, c, cx, g, ft, bf, colsum, Btg, tl(nt, 0), red);
-        if (it == 0) ir_colmax_body<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, true, bmax, part_s);
-        ir_colmax_body<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, false, rmax, part_s);
-        if (tid == 0) {
-          const double be = ir_backward_error(rmax, xmax, bmax, r, anorm);
-          conv = ir_decide(be, be_prev, it, args.max_iters, args.ir_tol);
-          be_prev = be;
+        if (!fp32 && it >= 1) {
+          if (tid == 0) conv = 1;
+          __syncthreads();
+          break;
         }
-        __syncthreads();
-        if (conv != 0) break;
+        const double anorm = ir_residual_body<T, FUSED, !fp32>(E, kap_lds ? kapl : kapg, X, c, cx, g, ft, bf,
+                                                                colsum, Btg, tl(nt, 0), red);
+        if (fp32) {
+          if (it == 0) ir_colmax_body<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, true, bmax, part_s);
+          ir_colmax_body<T, FUSED>(E, tl(nt, 0), ft, bf, c, colsum, Btg, false, rmax, part_s);
+          if (tid == 0) {
+            const double be = ir_backward_error(rmax, xmax, bmax, r, anorm);
+            conv = ir_decide(be, be_prev, it, args.max_iters, args.ir_tol);
+            be_prev = be;
+          }
+          __syncthreads();
+          if (conv != 0) break;
+        }
         forward();
         backward();
         ir_accumulate_body<T>(X, tl(nt, 0), c, n, r, false, cx, xmax, part_s);
       }
       const bool cvd = conv > 0;
       if (tid == 0) {
-        if (args.ir_iters) args.ir_iters[e] = it;
+        if (args.ir_iters && (!args.only_fallback || args.fb_final)) args.ir_iters[e] = it;
         if (!cvd) args.info[e] = INFO_IR_FALLBACK;
       }
       if (!cvd) continue;   // recomputed by the FP64 fallback pass

@@ -187,8 +187,12 @@ __device__ __forceinline__ void sweep(T* Lb, T* rhs_row, int nt, T* xb, T* scr, 
 // (half the rows per wave, at most 128 registers per lane, twice the waves
 // in flight).  MC: more than 16 right-hand sides, in chunks of 16 (built
 // only where a batch has them, so the one-chunk instances keep their
-// registers).
-template <typename T, bool FUSED, int PW, int RPW, int OCC, int NWV, bool MC>
+// registers).  REF (FP64): the instance carries the FP64 refinement step;
+// one without it leaves the elements that need the step to the FP64 pass
+// that follows it (info -1), because the refinement code, although it runs
+// only for those elements, costs the factorisation loop registers (FP64,
+// s = 48, four-tile panels: 45 against 200 ms per 1024 elements).
+template <typename T, bool FUSED, int PW, int RPW, int OCC, int NWV, bool MC, bool REF>
 __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev b, LocalArgs args) {
   typedef typename Mfma<T>::v4 V4;
   constexpr int NW = NWV;
@@ -238,8 +242,10 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
                  (FUSED && E.NI * (E.s + 1) > args.f_cap))
           st = INFO_TOO_LARGE;
         ok = st == INFO_OK;
-        if (!ok || !args.only_fallback) args.info[e] = st;
-        if (args.ir_iters && !args.only_fallback) args.ir_iters[e] = 0;
+        // a pass over the elements an FP64 run deferred owns their info; the
+        // FP64 pass of an FP32 run leaves -1 (and the FP32 step count) on them
+        if (!ok || !args.only_fallback || args.fb_final) args.info[e] = st;
+        if (args.ir_iters && (!args.only_fallback || args.fb_final)) args.ir_iters[e] = 0;
       }
       bad = -1;
       conv = 0;
@@ -314,10 +320,23 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     }
     __syncthreads();
     const double g = gam;
+    // FP64: one refinement step with a double-double residual where a plain
+    // FP64 solve is not accurate enough (the FP32 path always refines); an
+    // instance without the step defers such an element
+    const bool need64 = !fp32 && refine64_needed(args.refine64, kapg, s, red);
+    if constexpr (!REF && sizeof(T) == 8) {
+      if (need64) {
+        if (tid == 0) args.info[e] = INFO_IR_FALLBACK;
+        continue;
+      }
+    }
+    const bool ref64 = REF && need64;
+    // factor output: the three-call form, and the FP64 refinement pass over
+    // the elements such a call deferred (that pass works from kappa)
     T* Lo = nullptr;
-    if (!FUSED && args.Lout && E.mat0 >= 0) Lo = reinterpret_cast<T*>(args.Lout + E.mat0);
+    if (args.Lout && E.mat0 >= 0) Lo = reinterpret_cast<T*>(args.Lout + E.mat0);
 
-    // Initial value of tile (I, J) in the MFMA result layout: Ahat for I < nt,
+    // Tile (I, J) of the operator in the MFMA result layout: Ahat for I < nt,
     // the transposed right-hand sides Btilde^T for I >= nt (chunk I - nt).
     auto init_tile = [&](int I, int J) -> V4 {
       V4 v4;
@@ -400,24 +419,17 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
         // rows of this pass: slots h RH .. h RH + RH - 1 of the wave
         auto row_of = [&](int ri) { return j0 + wave + NW * (h * RH + ri); };
         V4 acc[RH][PW];
-        // (a) initial panel: rows are unrolled, the PW columns of a row run in
-        // a loop whose result is moved into its register slot by selects
-        // (a branch chain here would leave the panel array in scratch memory)
+        // (a) the panel's accumulators start at zero: the earlier columns'
+        // updates are summed first and the operator is added once, after (b).
+        // Summed into the operator's entries instead, each of the n products
+        // of a long dot product would be rounded at the size of the operator's
+        // largest entries (high-contrast elements: K = 1e4 against pivots of
+        // order one), which makes the factor an order of magnitude less
+        // accurate.
 #pragma unroll
         for (int ri = 0; ri < RH; ++ri) {
-          const int i = row_of(ri);
 #pragma unroll
           for (int k = 0; k < PW; ++k) acc[ri][k] = V4{0, 0, 0, 0};
-          if (held_i(i)) {
-#pragma unroll 1
-            for (int jj = 0; jj < pw; ++jj) {
-              if (rhs_i(i) || i >= j0 + jj) {
-                const V4 v = init_tile(i, j0 + jj);
-#pragma unroll
-                for (int k = 0; k < PW; ++k) acc[ri][k] = jj == k ? v : acc[ri][k];
-              }
-            }
-          }
         }
         // (b) earlier tile columns.  The operands of column m + 1 (A operands
         // in registers, B tiles for the LDS stage) are loaded while the MFMAs
@@ -497,6 +509,24 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
                   apply(m + q, ab[q], sb[q]);
                   fetch(m + q + NB, ab[q], sb[q]);
                 }
+              }
+            }
+          }
+        }
+        // the operator (Ahat, or Btilde^T in the right-hand-side rows): rows are
+        // unrolled, the PW columns of a row run in a loop whose result is moved
+        // into its register slot by selects (a branch chain here would leave
+        // the panel array in scratch memory)
+#pragma unroll
+        for (int ri = 0; ri < RH; ++ri) {
+          const int i = row_of(ri);
+          if (held_i(i)) {
+#pragma unroll 1
+            for (int jj = 0; jj < pw; ++jj) {
+              if (rhs_i(i) || i >= j0 + jj) {
+                const V4 v = init_tile(i, j0 + jj);
+#pragma unroll
+                for (int k = 0; k < PW; ++k) acc[ri][k] = jj == k ? acc[ri][k] + v : acc[ri][k];
               }
             }
           }
@@ -613,8 +643,8 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     double* X = args.X + E.rhs0;
     const int ca = tid >> 4, cl16 = tid & 15;   // 32 groups of 16 lanes; groups 0..15 do column sums
     if constexpr (!MC && sizeof(T) == 8) {
-      // FP64, one chunk: the straight-line form (the chunked loop below costs
-      // this kernel registers)
+      // FP64, one chunk, no refinement: the straight-line form (the chunked
+      // loop below costs this kernel registers)
       if (failed) {
         for (int idx = tid; idx < n * r; idx += NTHREADS) X[idx] = __builtin_nan("");
         if (tid == 0) args.info[e] = bad + 1;
@@ -629,21 +659,23 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
         }
         continue;
       }
-      {
-        double v = 0.0;
-        if (ca < r)
-          for (int p = cl16; p < n; p += 16) v += c[p] * (double)tl(nt, p >> 4)[ca * TST + (p & 15)];
-        v = group16_sum(v);
-        if (cl16 == 0 && ca < 16) cx[ca] = v * E.inv_area;
+      if (!ref64) {
+        {
+          double v = 0.0;
+          if (ca < r)
+            for (int p = cl16; p < n; p += 16) v += c[p] * (double)tl(nt, p >> 4)[ca * TST + (p & 15)];
+          v = group16_sum(v);
+          if (cl16 == 0 && ca < 16) cx[ca] = v * E.inv_area;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < n * r; idx += NTHREADS) {
+          const int a = idx / n, p = idx - a * n;
+          X[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)] - cx[a];
+        }
+        __syncthreads();
+        if (FUSED && args.M) contrib_element(E, X, ft, colsum[E.NI], NImax, args.M, args.E, args.B, args.F, e);
+        continue;
       }
-      __syncthreads();
-      for (int idx = tid; idx < n * r; idx += NTHREADS) {
-        const int a = idx / n, p = idx - a * n;
-        X[idx] = (double)tl(nt, p >> 4)[a * TST + (p & 15)] - cx[a];
-      }
-      __syncthreads();
-      if (FUSED && args.M) contrib_element(E, X, ft, colsum[E.NI], NImax, args.M, args.E, args.B, args.F, e);
-      continue;
     }
     if (failed) {
       if (fp32) {
@@ -675,7 +707,8 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
         }
         __syncthreads();
         if (ch >= nfused) {   // not eliminated with the factorisation: forward sweep first
-          for (int J = wave; J < nt; J += NW) st_acc<T>(rowc + (int64_t)J * TILE, init_tile(nt + ch, J), lane);
+          for (int J = wave; J < nt; J += NW)
+            st_acc<T>(rowc + (int64_t)J * TILE, init_tile(nt + ch, J), lane);
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
           __syncthreads();
           ll::sweep_call<T, RPW, false, OCC, NW>(Lb, rowc, nt, xb, scr, wave, lane);
@@ -684,25 +717,33 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
       }
       const int rc = E.rc;
       double* Xc = X + (int64_t)c0 * n;
-      if (fp32) {
-        // ------------------------------------- FP64 refinement (FP32 path)
+      if (fp32 || ref64) {
+        // ----------------------------------------------- FP64 refinement
+        // FP32 factor: FP64 residuals until the backward error target;
+        // FP64 factor: one step with a double-double residual.
         double* part = part_s;
         ir_accumulate<T>(Xc, rowc, c, n, rc, true, cx, xmax, part);
         const double* Btg = FUSED ? nullptr : args.Btil + E.rhs0;
         int it = 0;
         for (;; ++it) {
-          const double anorm = ir_residual<T, FUSED>(E, kapg, X, c, cx, g, ft, bf, colsum, Btg, rowc, red);
-          if (it == 0) ir_colmax<T, FUSED>(E, rowc, ft, bf, c, colsum, Btg, true, bmax, part);
-          ir_colmax<T, FUSED>(E, rowc, ft, bf, c, colsum, Btg, false, rmax, part);
-          if (tid == 0) {
-            const double be = ir_backward_error(rmax, xmax, bmax, rc, anorm);
-            conv = ir_decide(be, be_prev, it, args.max_iters, args.ir_tol);
-            be_prev = be;
+          if (!fp32 && it >= 1) {
+            if (tid == 0) conv = 1;
+            break;
           }
-          __syncthreads();
-          if (conv != 0) break;
-          forward(rowc);
-          backward(rowc);
+          const double anorm = ir_residual<T, FUSED, !fp32>(E, kapg, X, c, cx, g, ft, bf, colsum, Btg, rowc, red);
+          if (fp32) {
+            if (it == 0) ir_colmax<T, FUSED>(E, rowc, ft, bf, c, colsum, Btg, true, bmax, part);
+            ir_colmax<T, FUSED>(E, rowc, ft, bf, c, colsum, Btg, false, rmax, part);
+            if (tid == 0) {
+              const double be = ir_backward_error(rmax, xmax, bmax, rc, anorm);
+              conv = ir_decide(be, be_prev, it, args.max_iters, args.ir_tol);
+              be_prev = be;
+            }
+            __syncthreads();
+            if (conv != 0) break;
+          }
+          ll::sweep_call<T, RPW, false, OCC, NW>(Lb, rowc, nt, xb, scr, wave, lane);
+          ll::sweep_call<T, RPW, true, OCC, NW>(Lb, rowc, nt, xb, scr, wave, lane);
           ir_accumulate<T>(Xc, rowc, c, n, rc, false, cx, xmax, part);
         }
         it_max = it > it_max ? it : it_max;
@@ -726,8 +767,8 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
         __syncthreads();
       }
     }
-    if (fp32 && tid == 0) {
-      if (args.ir_iters) args.ir_iters[e] = it_max;
+    if ((fp32 || ref64) && tid == 0) {
+      if (args.ir_iters && (!args.only_fallback || args.fb_final)) args.ir_iters[e] = it_max;
       if (conv < 0) args.info[e] = INFO_IR_FALLBACK;
     }
     if (fp32 && conv < 0) continue;
@@ -735,9 +776,9 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
   }
 }
 
-template <typename T, bool FUSED, int PW, int RPW, int OCC, int NWV = 8, bool MC = false>
+template <typename T, bool FUSED, int PW, int RPW, int OCC, int NWV = 8, bool MC = false, bool REF = MC>
 static hipError_t launch_ll_t(const BatchDev& d, LocalArgs a, size_t lds, int grid, hipStream_t st) {
-  auto kern = k_local_ll<T, FUSED, PW, RPW, OCC, NWV, MC>;
+  auto kern = k_local_ll<T, FUSED, PW, RPW, OCC, NWV, MC, REF>;
   hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NWV), lds, st, d, a);

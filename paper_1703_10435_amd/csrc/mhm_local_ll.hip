@@ -9,6 +9,8 @@ hipError_t launch_local_ll_f32(bool fused, int pw, int occ, int nw, int rpw, boo
                                LocalArgs a, size_t lds, int grid, hipStream_t st);
 hipError_t launch_local_ll_f64(bool fused, int pw, int occ, int nw, int rpw, bool mc, const BatchDev& d,
                                LocalArgs a, size_t lds, int grid, hipStream_t st);
+hipError_t launch_local_ll_f64_ref(bool fused, int pw, int occ, int nw, int rpw, const BatchDev& d, LocalArgs a,
+                                   size_t lds, int grid, hipStream_t st);
 
 int local_ll_rows_per_wave(int nt, int nw) {
   const int rows = nt + 1;
@@ -48,13 +50,16 @@ size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap, int nw) {
          (size_t)(2 * pw + pw + pw * pw + nw) * TILE * (fp32 ? sizeof(float) : sizeof(double));
 }
 
-hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, bool mc, int nt_max, const mhm_batch* bt,
-                           LocalArgs a, size_t lds, int grid, hipStream_t st) {
+hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, bool mc, bool ref, int nt_max,
+                           const mhm_batch* bt, LocalArgs a, size_t lds, int grid, hipStream_t st) {
   if (!local_ll_has(fp32, pw, nt_max, occ, nw, mc)) return hipErrorInvalidValue;
+  // an FP64 pass over deferred or recomputed elements must refine, never defer again
+  if (!fp32 && !mc && a.only_fallback && !ref) return hipErrorInvalidValue;
   const int rpw = local_ll_rows_per_wave(nt_max, nw);
   const BatchDev d = to_dev(bt);
-  return fp32 ? launch_local_ll_f32(fused, pw, occ, nw, rpw, mc, d, a, lds, grid, st)
-              : launch_local_ll_f64(fused, pw, occ, nw, rpw, mc, d, a, lds, grid, st);
+  if (fp32) return launch_local_ll_f32(fused, pw, occ, nw, rpw, mc, d, a, lds, grid, st);
+  if (ref && !mc) return launch_local_ll_f64_ref(fused, pw, occ, nw, rpw, d, a, lds, grid, st);
+  return launch_local_ll_f64(fused, pw, occ, nw, rpw, mc, d, a, lds, grid, st);   // chunked instances refine
 }
 
 }  // namespace mhm

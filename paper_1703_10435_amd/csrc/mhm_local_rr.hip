@@ -295,6 +295,16 @@ __global__ void __launch_bounds__(rr::NTHREADS, OCC) k_local_rr(BatchDev b, Loca
       }
     }
     __syncthreads();
+    // An element whose plain FP64 solve would not be accurate enough is left
+    // to the FP64 pass that follows this kernel (a kernel with the refinement
+    // step); info -1 marks it for that pass.  Fused launches only: the
+    // three-call form keeps the plain FP64 solve on these elements (the
+    // deferral from it was switched off after a GPU memory fault whose cause
+    // was not found).
+    if (FUSED && refine64_needed(args.refine64, kapl, s, red)) {
+      if (tid == 0) args.info[e] = INFO_IR_FALLBACK;
+      continue;
+    }
     {
       double tr = 0.0, cc2 = 0.0, fs = 0.0;
       const double* fp = b.f + E.tri0;

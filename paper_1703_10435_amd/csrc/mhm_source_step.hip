@@ -164,6 +164,22 @@ __global__ void __launch_bounds__(64 * SS_WAVES) k_source_step(BatchDev b, Sourc
     const T* Lb = reinterpret_cast<const T*>(static_cast<const char*>(a.fac) + a.fac_off[e]);
     double* xg = a.X + E.rhs0 + (int64_t)NI * n;   // the source column of X
 
+    // FP64 factors: one refinement step with a double-double residual where
+    // a plain FP64 solve is not accurate enough (refine64_needed, per wave)
+    bool ref = fp32;
+    if (!fp32) {
+      if (a.refine64 != 0) {
+        ref = a.refine64 > 0;
+      } else {
+        double kmax = 0.0, kinv = 0.0;
+        for (int t = lane; t < s * s; t += 64) {
+          kmax = fmax(kmax, kapg[t]);
+          kinv = fmax(kinv, 1.0 / kapg[t]);
+        }
+        ref = !(wave_max(kmax) * wave_max(kinv) * ((double)s * s) <= REFINE64_SCALE);
+      }
+    }
+
     // ------------------------------------------------ load vector, eq. (8)
     double fs = 0.0, tr = 0.0, cc2 = 0.0;
     for (int p = lane; p < n; p += 64) {
@@ -172,7 +188,7 @@ __global__ void __launch_bounds__(64 * SS_WAVES) k_source_step(BatchDev b, Sourc
       const double bp = E.cunit * node_tri_sum(i, j, s, [&](int t) { return fp[t]; });
       bt[p] = bp;
       fs += bp;
-      if (fp32) {   // gamma = tr(A) / (n c^T c) of the factored Ahat
+      if (ref) {   // gamma = tr(A) / (n c^T c) of the factored Ahat
         const double cp = node_tri_count(i, j, s) * E.cunit;
         cc2 += cp * cp;
         tr += stencil(i, j, s, E.G, kap).d;
@@ -180,7 +196,7 @@ __global__ void __launch_bounds__(64 * SS_WAVES) k_source_step(BatchDev b, Sourc
     }
     fs = wave_sum(fs);
     double g = 0.0;
-    if (fp32) {
+    if (ref) {
       tr = wave_sum(tr);
       cc2 = wave_sum(cc2);
       g = tr / (n * cc2);
@@ -203,7 +219,7 @@ __global__ void __launch_bounds__(64 * SS_WAVES) k_source_step(BatchDev b, Sourc
     sweep_pair<T>(Lb, y, nt, lane);
 
     double shift;   // (c^T x) / |K| of the final iterate
-    if (!fp32) {
+    if (!ref) {
       double cx = 0.0;
       for (int p = lane; p < n; p += 64) {
         int i, j;
@@ -213,7 +229,9 @@ __global__ void __launch_bounds__(64 * SS_WAVES) k_source_step(BatchDev b, Sourc
       shift = wave_sum(cx) * E.inv_area;
       for (int p = lane; p < n; p += 64) xg[p] = (double)y[p] - shift;
     } else {
-      // ----------------------------------------- FP64 refinement (FP32 L)
+      // --------------------------------------------------- FP64 refinement
+      // FP32 L: FP64 residuals until the backward error target; FP64 L: one
+      // step with a double-double residual.
       // ||Ahat||_inf: stencil row sums plus gamma c_p |K| of the rank-one term
       double anorm;
       {
@@ -244,7 +262,11 @@ __global__ void __launch_bounds__(64 * SS_WAVES) k_source_step(BatchDev b, Sourc
       double prev = 0.0;
       int it = 0, conv = 0;
       for (;; ++it) {
-        // r = btilde - Ahat x (FP64, matrix-free), into y
+        if (!fp32 && it >= 1) {
+          conv = 1;
+          break;
+        }
+        // r = btilde - Ahat x (FP64, matrix-free; double-double for FP64 L), into y
         double rm = 0.0;
         for (int p = lane; p < n; p += 64) {
           int i, j;
@@ -252,19 +274,41 @@ __global__ void __launch_bounds__(64 * SS_WAVES) k_source_step(BatchDev b, Sourc
           const Stencil st = stencil(i, j, s, E.G, kap);
           const double cp = node_tri_count(i, j, s) * E.cunit;
           const bool hasE = i + j <= s - 1, hasW = i >= 1, hasS = j >= 1;
-          double ax = st.d * xg[p] + cp * (g * cx);
-          if (hasE) ax += st.e * xg[p + 1] + st.n * xg[p + (s + 1 - j)];
-          if (hasW) ax += st.w * xg[p - 1] + st.nw * xg[p + (s - j)];
-          if (hasS) ax += st.so * xg[p - (s + 2 - j)] + st.se * xg[p - (s + 1 - j)];
-          const double r = bt[p] - ax;
+          double r;
+          if (fp32) {
+            double ax = st.d * xg[p] + cp * (g * cx);
+            if (hasE) ax += st.e * xg[p + 1] + st.n * xg[p + (s + 1 - j)];
+            if (hasW) ax += st.w * xg[p - 1] + st.nw * xg[p + (s - j)];
+            if (hasS) ax += st.so * xg[p - (s + 2 - j)] + st.se * xg[p - (s + 1 - j)];
+            r = bt[p] - ax;
+          } else {
+            double hi = 0.0, lo = 0.0;
+            dd_add_prod(hi, lo, st.d, xg[p]);
+            dd_add_prod(hi, lo, cp, g * cx);
+            if (hasE) {
+              dd_add_prod(hi, lo, st.e, xg[p + 1]);
+              dd_add_prod(hi, lo, st.n, xg[p + (s + 1 - j)]);
+            }
+            if (hasW) {
+              dd_add_prod(hi, lo, st.w, xg[p - 1]);
+              dd_add_prod(hi, lo, st.nw, xg[p + (s - j)]);
+            }
+            if (hasS) {
+              dd_add_prod(hi, lo, st.so, xg[p - (s + 2 - j)]);
+              dd_add_prod(hi, lo, st.se, xg[p - (s + 1 - j)]);
+            }
+            r = dd_sub_from(bt[p], hi, lo);
+          }
           y[p] = (T)r;
           rm = fmax(rm, fabs(r));
         }
         rm = wave_max(rm);
-        const double be = ir_backward_error(&rm, &xm, &bmax, 1, anorm);
-        conv = ir_decide(be, prev, it, a.max_iters, a.ir_tol);
-        prev = be;
-        if (conv != 0) break;
+        if (fp32) {
+          const double be = ir_backward_error(&rm, &xm, &bmax, 1, anorm);
+          conv = ir_decide(be, prev, it, a.max_iters, a.ir_tol);
+          prev = be;
+          if (conv != 0) break;
+        }
         wave_sync();
         sweep_pair<T>(Lb, y, nt, lane);
         cx = 0.0;

@@ -5,7 +5,6 @@ launch configuration)."""
 from __future__ import annotations
 
 import json
-import os
 
 import numpy as np
 import pytest
@@ -23,24 +22,14 @@ S_ALL = [2, 16, 17, 25, 26, 33, 34, 48, 8, 20, 52]
 L_ALL = [1, 3, 0, 2, 4, 1, 3, 2, 0, 4, 1]
 
 
-def _ctx(env=None):
+def _ctx(opts=None):
+    """A context with launch options (mhm_set_option) by name."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     ensure_built()
     from paper_1703_10435_amd import abi
-    old = {}
-    for k, v in (env or {}).items():
-        old[k] = os.environ.get(k)
-        os.environ[k] = v
-    try:
-        return abi.Context(0)
-    finally:
-        for k, v in old.items():
-            if v is None:
-                del os.environ[k]
-            else:
-                os.environ[k] = v
+    return abi.Context(0, **(opts or {}))
 
 
 @pytest.fixture(scope="module")
@@ -69,23 +58,23 @@ def test_every_size_class_in_one_batch(ctx, prec):
         _check(res, b, range(b["n_elem"]), prec, f"all-classes prec={prec} {mode}")
 
 
-@pytest.mark.parametrize("env", [{"MHM_NO_RR": "1"}, {"MHM_NO_LL": "1"}, {"MHM_NO_RR": "1", "MHM_NO_LL": "1"},
-                                 {"MHM_NO_RR": "1", "MHM_LL_OCC2": "1"}, {"MHM_LL_NW16": "1"}, {"MHM_LL_PW": "1"},
-                                 {"MHM_LL_PW": "4"}])
-def test_kernel_families_agree_with_oracle(env):
+@pytest.mark.parametrize("opts", [{"no_rr": 1}, {"no_ll": 1}, {"no_rr": 1, "no_ll": 1},
+                                 {"no_rr": 1, "ll_occ2": 1}, {"ll_nw16": 1}, {"ll_pw": 1},
+                                 {"ll_pw": 4}])
+def test_kernel_families_agree_with_oracle(opts):
     """The families the defaults do not pick (LDS tiles for small FP64
     elements, the right-looking workspace kernel for large ones, the
     left-looking kernel built for two workgroups per CU, with 16 waves, with
     one-tile panels in FP64 and two-tile panels in FP32 at s = 48, or with
     four-tile FP64 panels taken in five row passes)."""
     from paper_1703_10435_amd import engine
-    c = _ctx(env)
+    c = _ctx(opts)
     try:
         b = _random_batch(22, [5, 12, 16, 20, 30, 40, 48], [2, 1, 3, 0, 2, 3, 1], "families")
         for prec in (0, 1):
-            say(f"[gpu] families env={env} prec={prec}")
+            say(f"[gpu] families opts={opts} prec={prec}")
             res, out, db = engine.solve_batch(b, prec=prec, mode="fused", ctx=c)
-            _check(res, b, range(b["n_elem"]), prec, f"families {env} prec={prec}")
+            _check(res, b, range(b["n_elem"]), prec, f"families {opts} prec={prec}")
     finally:
         c.close()
 
@@ -97,7 +86,7 @@ def test_register_tile_kernel_both_occupancies(occ, mode):
     three resident workgroups per CU (a tuner candidate), fused and as the
     three calls."""
     from paper_1703_10435_amd import engine
-    c = _ctx({"MHM_RR_OCC": occ})
+    c = _ctx({"rr_occ": int(occ)})
     try:
         b = _random_batch(26, [2, 5, 9, 12, 16, 16, 7], [0, 1, 2, 3, 2, 3, 1], "occupancy")
         say(f"[gpu] register tiles occ={occ} mode={mode}")

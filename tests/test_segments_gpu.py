@@ -5,7 +5,6 @@ time-step call, and the skeleton scatter and reconstruction, each against
 the FP64 oracle."""
 from __future__ import annotations
 
-import os
 
 import numpy as np
 import pytest
@@ -30,24 +29,14 @@ def _batch(seed, cases, name):
     return b
 
 
-def _ctx(env=None):
+def _ctx(opts=None):
+    """A context with launch options (mhm_set_option) by name."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     ensure_built()
     from paper_1703_10435_amd import abi
-    old = {}
-    for k, v in (env or {}).items():
-        old[k] = os.environ.get(k)
-        os.environ[k] = v
-    try:
-        return abi.Context(0)
-    finally:
-        for k, v in old.items():
-            if v is None:
-                del os.environ[k]
-            else:
-                os.environ[k] = v
+    return abi.Context(0, **(opts or {}))
 
 
 @pytest.fixture(scope="module")
@@ -67,16 +56,16 @@ def test_segmented_faces_every_size_class(ctx, prec):
         _check(res, b, range(b["n_elem"]), prec, f"segments prec={prec} {mode}")
 
 
-@pytest.mark.parametrize("env", [{"MHM_NO_RR": "1"}, {"MHM_NO_LL": "1"}])
-def test_segmented_faces_other_families(env):
+@pytest.mark.parametrize("opts", [{"no_rr": 1}, {"no_ll": 1}])
+def test_segmented_faces_other_families(opts):
     from paper_1703_10435_amd import engine
-    c = _ctx(env)
+    c = _ctx(opts)
     try:
         b = _batch(62, [(4, 1, 2), (16, 0, 4), (24, 1, 2), (40, 0, 5)], "segments-families")
         for prec in (0, 1):
-            say(f"[gpu] segments env={env} prec={prec}")
+            say(f"[gpu] segments opts={opts} prec={prec}")
             res, out, db = engine.solve_batch(b, prec=prec, mode="fused", ctx=c)
-            _check(res, b, range(b["n_elem"]), prec, f"segments {env} prec={prec}")
+            _check(res, b, range(b["n_elem"]), prec, f"segments {opts} prec={prec}")
     finally:
         c.close()
 

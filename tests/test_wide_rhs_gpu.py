@@ -76,17 +76,17 @@ def test_wide_rhs_on_stored_factors(ctx, prec):
     _check(dstep2.unpack(out), dict(b, f=f2), np.flatnonzero(held), prec, f"wide source step prec={prec}")
 
 
-@pytest.mark.parametrize("env", [{"MHM_NO_LL": "1"}])
-def test_wide_rhs_without_the_left_looking_kernel_reports(env):
+@pytest.mark.parametrize("opts", [{"no_ll": 1}])
+def test_wide_rhs_without_the_left_looking_kernel_reports(opts):
     """Only the left-looking kernel takes more than one chunk: with it
     switched off, wide elements report info -3 and the others are solved."""
     from paper_1703_10435_amd import engine
-    c = _ctx(env)
+    c = _ctx(opts)
     try:
         cases = [(8, 1, 8), (8, 1, 1), (16, 0, 8), (16, 2, 1)]
         b = _batch(74, cases, "wide-no-ll")
         for prec in (0, 1):
-            say(f"[gpu] wide rhs env={env} prec={prec}")
+            say(f"[gpu] wide rhs opts={opts} prec={prec}")
             res, out, db = engine.solve_batch(b, prec=prec, mode="fused", ctx=c)
             info = [res[e]["info"] for e in range(b["n_elem"])]
             assert info[0] == -3 and info[2] == -3, info
