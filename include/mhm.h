@@ -224,6 +224,28 @@ mhm_status mhm_local_batch_run(mhm_ctx ctx, const mhm_batch* batch, mhm_prec pre
                                double* X, double* M, double* E, double* B, double* F,
                                int32_t* info, int32_t* ir_iters, int max_iters);
 
+/* No-allocation variant of mhm_local_batch_run, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same work, contract and
+ * results (bit for bit, on the same kernels), with every scratch buffer (the
+ * size-class lists of a ragged batch and the per-workgroup workspace slots
+ * of large elements) in a device array that the library holds on each GPU
+ * it runs on, MHM_NOALLOC_SCRATCH_BYTES in size, until the process ends; the
+ * call itself performs no allocation of any kind.  The size classes run one
+ * after another on the context's stream, and a launch whose workgroups need
+ * slots runs as many workgroups as slots fit in the array (fewer than
+ * mhm_local_batch_run for the largest elements: slower, same results).
+ * Nothing in the array needs to start at zero.  Every call on one GPU uses
+ * that GPU's one array: calls that overlap on a GPU (other streams, other
+ * contexts or threads) race and give wrong results; serialise them.
+ * Returns MHM_E_ARG, without enqueuing anything, for a batch whose class
+ * lists (4 (5 n_elem + 5) bytes) or one workspace slot of its largest
+ * elements do not fit in the array. */
+#define MHM_NOALLOC_SCRATCH_BYTES (256u << 20)
+mhm_status mhm_local_batch_run_noalloc(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec,
+                                       double* X, double* M, double* E, double* B, double* F,
+                                       int32_t* info, int32_t* ir_iters, int max_iters);
+
 /* Around the path: the assembly of the skeleton system eq. (6) from the
  * element contributions (the reduce step of reduceLocalProblems,
  * Algorithm 1) and computeSolution, eq. (4).  The global numbering is the

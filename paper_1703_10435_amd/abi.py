@@ -23,7 +23,7 @@ EXPORTS = (
     "mhm_local_assemble", "mhm_local_factor_solve", "mhm_skeleton_contrib", "mhm_local_batch_run",
     "mhm_autotune", "mhm_tune_report", "mhm_graph_create", "mhm_graph_launch", "mhm_graph_destroy",
     "mhm_factor_bytes", "mhm_local_batch_run_cached", "mhm_skeleton_scatter", "mhm_reconstruct",
-    "mhm_local_source_step", "mhm_skeleton_solve", "mhm_set_option",
+    "mhm_local_source_step", "mhm_skeleton_solve", "mhm_set_option", "mhm_local_batch_run_noalloc",
 )
 
 # Context options (mhm_set_option)
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
         "mhm_local_factor_solve": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, i32]),
         "mhm_skeleton_contrib": (i32, [vp, bp, vp, vp, vp, vp, vp, vp]),
         "mhm_local_batch_run": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, i32]),
+        "mhm_local_batch_run_noalloc": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, i32]),
         "mhm_autotune": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, i32]),
         "mhm_tune_report": (ctypes.c_size_t, [vp, ctypes.c_char_p, ctypes.c_size_t]),
         "mhm_graph_create": (i32, [vp, bp, i32, vp, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(vp)]),
@@ -178,6 +179,11 @@ class Context:
         self._check(self.lib.mhm_local_batch_run(self.h, ctypes.byref(batch.desc), prec, _ptr(X), _ptr(M),
                                                  _ptr(E), _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters),
                                                  max_iters))
+
+    def local_batch_run_noalloc(self, batch, prec, X, M, E, B, F, info, ir_iters=None, max_iters: int = 10):
+        self._check(self.lib.mhm_local_batch_run_noalloc(self.h, ctypes.byref(batch.desc), prec, _ptr(X), _ptr(M),
+                                                         _ptr(E), _ptr(B), _ptr(F), _ptr(info), _ptr(ir_iters),
+                                                         max_iters))
 
     def autotune(self, batch, prec, X, M, E, B, F, info, ir_iters=None, max_iters: int = 10):
         self._check(self.lib.mhm_autotune(self.h, ctypes.byref(batch.desc), prec, _ptr(X), _ptr(M), _ptr(E),

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -53,6 +54,38 @@ struct Choice {
 
 }  // namespace
 
+// Device scratch of mhm_local_batch_run_noalloc (class lists and workspace
+// slots), one copy per GPU for the life of the process.  In host code the
+// name is a stand-in, not a device address: every use goes through the
+// address hipGetSymbolAddress returned for the device (scratch_ptr below).
+static __device__ __align__(256) char scratch[MHM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on `device` (which is current), looked up
+// once per device; null on failure.
+void* scratch_ptr(int device, hipError_t* err) {
+  *err = hipSuccess;
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_ptr[device] = p;
+  }
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 struct mhm_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -66,6 +99,7 @@ struct mhm_ctx_s {
   int ll_pw = 0;               // left-looking default panel width (1, 2, 4), where built
   int rr_occ = 0;              // register-tile kernel default workgroups per CU (2, 3)
   int refine64 = 0;            // FP64 refinement: 0 where needed, 1 every element, -1 none
+  void* scratch = nullptr;     // this device's scratch array (mhm_local_batch_run_noalloc)
   void* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t aux[kNumClasses] = {};   // class streams of ragged runs
@@ -425,7 +459,7 @@ mhm::BinClasses bin_classes() {
 // then the classes, the largest on `st` and the others forked onto the
 // context's class streams and joined back.
 mhm_status enqueue_run(mhm_ctx c, const RunPlan& rp, const mhm_batch* b, const RunIO& io, void* ws_v, hipStream_t st,
-                       bool fallback_only = false) {
+                       bool fallback_only = false, bool one_stream = false) {
   char* ws = static_cast<char*>(ws_v);
   int32_t* lists = reinterpret_cast<int32_t*>(ws);
   int32_t* counts = lists + (size_t)kNumClasses * b->n_elem;
@@ -433,7 +467,7 @@ mhm_status enqueue_run(mhm_ctx c, const RunPlan& rp, const mhm_batch* b, const R
     hipError_t e = mhm::launch_bin(b, bin_classes(), lists, counts, st);
     if (e != hipSuccess) return hip_fail(c, e, "k_bin launch");
   }
-  const bool fork = rp.n_runs > 1;
+  const bool fork = rp.n_runs > 1 && !one_stream;
   if (fork) {
     mhm_status s0 = ensure_streams(c);
     if (s0 != MHM_OK) return s0;
@@ -448,7 +482,7 @@ mhm_status enqueue_run(mhm_ctx c, const RunPlan& rp, const mhm_batch* b, const R
     const ClassRun& r = rp.run[i];
     const int32_t* el = rp.listed ? lists + (size_t)r.cls * b->n_elem : nullptr;
     const int32_t* ec = rp.listed ? counts + r.cls : nullptr;
-    mhm_status s1 = enqueue_class(c, r, b, io, ws, el, ec, i == 0 ? st : c->aux[i], fallback_only);
+    mhm_status s1 = enqueue_class(c, r, b, io, ws, el, ec, i == 0 || !fork ? st : c->aux[i], fallback_only);
     if (s1 != MHM_OK) return s1;
   }
   if (fork) {
@@ -580,6 +614,13 @@ mhm_status mhm_create(mhm_ctx* out, int device, void* hip_stream) {
   mhm_ctx c = new mhm_ctx_s();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  // the no-allocation entry point's scratch array on this device (set-up
+  // time: the lookup loads the code object on the device)
+  c->scratch = scratch_ptr(device, &e);
+  if (!c->scratch) {
+    delete c;
+    return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+  }
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0) c->n_cu = v;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && v > 0)
@@ -702,6 +743,50 @@ mhm_status mhm_local_batch_run(mhm_ctx c, const mhm_batch* b, mhm_prec prec, dou
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   return run_local(c, b, prec, true, fused_io(X, M, E, B, F, info, ir_iters, max_iters));
+}
+
+mhm_status mhm_local_batch_run_noalloc(mhm_ctx c, const mhm_batch* b, mhm_prec prec, double* X, double* M,
+                                       double* E, double* B, double* F, int32_t* info, int32_t* ir_iters,
+                                       int max_iters) {
+  mhm_status st = check_fused(c, b, prec, X, M, E, B, F, info);
+  if (st != MHM_OK || b->n_elem == 0) return st;
+  if (!c->scratch) return fail(c, MHM_E_DEVICE, "the scratch array of this device was not found at mhm_create");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  // The plan of mhm_local_batch_run, fitted into the scratch array: the
+  // classes run one after another on the context's stream (no forked
+  // streams), each from the end of the class lists, and a launch whose
+  // workgroups each need a workspace slot gets only as many workgroups as
+  // slots fit (the kernels are persistent, so fewer workgroups only take
+  // longer).
+  const bool fp32 = prec == MHM_FP32_IR;
+  RunPlan rp = make_run_plan(c, b, fp32, true, nullptr);
+  const size_t cap = MHM_NOALLOC_SCRATCH_BYTES;
+  if (rp.list_bytes >= cap)
+    return fail(c, MHM_E_ARG, "batch too large for mhm_local_batch_run_noalloc: its class lists need " +
+                                  std::to_string(rp.list_bytes) + " of the " + std::to_string(cap) +
+                                  " scratch bytes");
+  const size_t avail = cap - rp.list_bytes;
+  auto fit = [&](Plan& p, size_t tsz) -> bool {
+    if (p.ws_slot <= 0) return true;
+    const size_t per = (size_t)p.ws_slot * tsz;
+    const size_t g = avail / per;
+    if (g < 1) return false;
+    p.grid = (int)std::min<size_t>((size_t)p.grid, g);
+    p.ws_need = align_up((size_t)p.grid * per);
+    return true;
+  };
+  for (int i = 0; i < rp.n_runs; ++i) {
+    ClassRun& r = rp.run[i];
+    const bool ok = fit(r.main, fp32 ? sizeof(float) : sizeof(double)) && (!r.has_fb || fit(r.fb, sizeof(double)));
+    if (!ok)
+      return fail(c, MHM_E_ARG, "elements with s up to " + std::to_string(r.s_cap) +
+                                    " need a workspace slot larger than the scratch array's " +
+                                    std::to_string(avail) + " bytes after the class lists");
+    r.ws_off = rp.list_bytes;
+  }
+  return enqueue_run(c, rp, b, fused_io(X, M, E, B, F, info, ir_iters, max_iters), c->scratch, c->stream, false,
+                     true);
 }
 
 mhm_status mhm_reconstruct(mhm_ctx c, const mhm_batch* b, const double* X, const int32_t* gdof, const int32_t* erow,
