@@ -159,6 +159,15 @@ mhm_status mhm_set_stream(mhm_ctx ctx, void* hip_stream);
  *  MHM_OPT_LL_NW16   1: left-looking default with 16 waves, where built
  *  MHM_OPT_LL_PW     0, 1, 2, 4: left-looking default panel width, where built
  *  MHM_OPT_RR_OCC    0, 2, 3: register-tile kernel's workgroups per CU
+ *  MHM_OPT_CONCURRENT_CLASSES  1: run the size classes of a ragged batch
+ *                    concurrently, on forked streams, instead of one after
+ *                    another on the context's stream (on C4 in FP64 the
+ *                    concurrent form took 82 against 78 ms)
+ *  MHM_OPT_CLASS_TIMING  1: record HIP timing events on each size class's
+ *                    stream around its main kernel launch (not the binning or
+ *                    the FP64 pass) in later mhm_local_batch_run and
+ *                    mhm_local_factor_solve calls; mhm_class_times reads them.
+ *                    Not for use under stream capture.
  * Returns MHM_E_ARG for an unknown option or value.  Applies to later calls
  * (a captured graph keeps the configuration of its capture). */
 typedef enum {
@@ -168,9 +177,18 @@ typedef enum {
   MHM_OPT_LL_OCC2 = 3,
   MHM_OPT_LL_NW16 = 4,
   MHM_OPT_LL_PW = 5,
-  MHM_OPT_RR_OCC = 6
+  MHM_OPT_RR_OCC = 6,
+  MHM_OPT_CLASS_TIMING = 7,
+  MHM_OPT_CONCURRENT_CLASSES = 8
 } mhm_option;
 mhm_status mhm_set_option(mhm_ctx ctx, int option, int value);
+
+/* With MHM_OPT_CLASS_TIMING on: the size classes of the last timed call,
+ * largest first, and the duration of each class's main kernel launch in
+ * milliseconds (it waits for them).  s_cap[k] is the upper s of class k's
+ * launch.  Returns the number of classes (at most max), or -1 when the option
+ * is off or no call has been timed. */
+int mhm_class_times(mhm_ctx ctx, int32_t* s_cap, float* ms, int max);
 /* Text of the last call-level error on this context ("" if none); with a
  * NULL context, the last error of a context-less call (mhm_create) on the
  * calling thread. */
@@ -387,7 +405,8 @@ mhm_status mhm_autotune(mhm_ctx ctx, const mhm_batch* batch, mhm_prec prec,
 size_t mhm_tune_report(mhm_ctx ctx, char* buf, size_t len);
 
 /* Batching: capture the whole mhm_local_batch_run of this batch (binning,
- * one persistent launch per size class on forked streams, FP64 fallback
+ * one persistent launch per size class, one after another (or on forked
+ * streams with MHM_OPT_CONCURRENT_CLASSES), FP64 fallback
  * passes) into a HIP graph that owns its own workspace.  The batch arrays
  * and outputs are bound at capture; their contents may change between
  * launches, their addresses and the host fields of the batch may not.

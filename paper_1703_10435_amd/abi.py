@@ -24,14 +24,16 @@ EXPORTS = (
     "mhm_autotune", "mhm_tune_report", "mhm_graph_create", "mhm_graph_launch", "mhm_graph_destroy",
     "mhm_factor_bytes", "mhm_local_batch_run_cached", "mhm_skeleton_scatter", "mhm_reconstruct",
     "mhm_local_source_step", "mhm_skeleton_solve", "mhm_set_option", "mhm_local_batch_run_noalloc",
+    "mhm_class_times",
 )
 
 # Context options (mhm_set_option)
-MHM_OPT_REFINE64, MHM_OPT_NO_RR, MHM_OPT_NO_LL, MHM_OPT_LL_OCC2, MHM_OPT_LL_NW16, MHM_OPT_LL_PW, MHM_OPT_RR_OCC = \
-    range(7)
+(MHM_OPT_REFINE64, MHM_OPT_NO_RR, MHM_OPT_NO_LL, MHM_OPT_LL_OCC2, MHM_OPT_LL_NW16, MHM_OPT_LL_PW, MHM_OPT_RR_OCC,
+ MHM_OPT_CLASS_TIMING, MHM_OPT_CONCURRENT_CLASSES) = range(9)
 OPTION_NAMES = {"refine64": MHM_OPT_REFINE64, "no_rr": MHM_OPT_NO_RR, "no_ll": MHM_OPT_NO_LL,
                 "ll_occ2": MHM_OPT_LL_OCC2, "ll_nw16": MHM_OPT_LL_NW16, "ll_pw": MHM_OPT_LL_PW,
-                "rr_occ": MHM_OPT_RR_OCC}
+                "rr_occ": MHM_OPT_RR_OCC, "class_timing": MHM_OPT_CLASS_TIMING,
+                "concurrent_classes": MHM_OPT_CONCURRENT_CLASSES}
 
 
 class mhm_batch(ctypes.Structure):
@@ -72,6 +74,7 @@ def load(path: str = LIB_PATH):
         "mhm_destroy": (i32, [vp]),
         "mhm_set_stream": (i32, [vp, vp]),
         "mhm_set_option": (i32, [vp, i32, i32]),
+        "mhm_class_times": (i32, [vp, vp, vp, i32]),
         "mhm_last_error": (ctypes.c_char_p, [vp]),
         "mhm_sync": (i32, [vp]),
         "mhm_workspace_bytes": (ctypes.c_size_t, [vp, bp, i32]),
@@ -221,6 +224,14 @@ class Context:
     def reconstruct(self, batch, X, gdof, erow, sol, n_rows, u, info=None):
         self._check(self.lib.mhm_reconstruct(self.h, ctypes.byref(batch.desc), _ptr(X), _ptr(gdof), _ptr(erow),
                                              _ptr(sol), int(n_rows), _ptr(u), _ptr(info)))
+
+    def class_times(self):
+        """[(s_cap, ms)] of the last call timed with the class_timing option,
+        largest class first; None when nothing was timed."""
+        cap = (ctypes.c_int32 * 8)()
+        ms = (ctypes.c_float * 8)()
+        k = int(self.lib.mhm_class_times(self.h, cap, ms, 8))
+        return None if k < 0 else [(int(cap[i]), float(ms[i])) for i in range(k)]
 
     def tune_report(self) -> str:
         n = int(self.lib.mhm_tune_report(self.h, None, 0))

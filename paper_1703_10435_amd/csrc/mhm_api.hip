@@ -105,6 +105,12 @@ struct mhm_ctx_s {
   hipStream_t aux[kNumClasses] = {};   // class streams of ragged runs
   hipEvent_t fork = nullptr;
   hipEvent_t join[kNumClasses] = {};
+  // MHM_OPT_CLASS_TIMING: events around each class's main launch
+  bool class_timing = false;
+  bool concurrent_classes = false;   // MHM_OPT_CONCURRENT_CLASSES: size classes on forked streams
+  hipEvent_t t_beg[kNumClasses] = {}, t_end[kNumClasses] = {};
+  int timed_n = -1;
+  int timed_cap[kNumClasses] = {};
   Choice tuned[kNumClasses][2][2];     // [class][fp32][fused], from mhm_autotune
   std::string tune_log;
   std::string err;
@@ -411,12 +417,22 @@ mhm::LocalArgs local_args(const mhm_ctx c, const Plan& p, const RunIO& io, void*
 // refinement did not converge, or of those an FP64 register-tile launch
 // deferred to a kernel with the refinement step.
 mhm_status enqueue_class(mhm_ctx c, const ClassRun& r, const mhm_batch* b, const RunIO& io, char* ws,
-                         const int32_t* elist, const int32_t* ecount, hipStream_t st, bool fallback_only = false) {
+                         const int32_t* elist, const int32_t* ecount, hipStream_t st, bool fallback_only = false,
+                         int timing_slot = -1) {
   hipError_t e = hipSuccess;
   if (!fallback_only) {
     mhm::LocalArgs a = local_args(c, r.main, io, ws + r.ws_off, elist, ecount);
+    if (timing_slot >= 0) {
+      e = hipEventRecord(c->t_beg[timing_slot], st);
+      if (e != hipSuccess) return hip_fail(c, e, "hipEventRecord");
+    }
     e = launch_plan(r.main, b, a, st);
     if (e != hipSuccess) return hip_fail(c, e, "local kernel launch");
+    if (timing_slot >= 0) {
+      e = hipEventRecord(c->t_end[timing_slot], st);
+      if (e != hipSuccess) return hip_fail(c, e, "hipEventRecord");
+      c->timed_cap[timing_slot] = r.s_cap;
+    }
   }
   if (r.has_fb && r.main.fp32) {
     RunIO f = io;
@@ -456,8 +472,9 @@ mhm::BinClasses bin_classes() {
 }
 
 // Enqueue a whole run on stream `st` (also under stream capture): binning,
-// then the classes, the largest on `st` and the others forked onto the
-// context's class streams and joined back.
+// then the classes, largest first, one after another on `st` (with
+// MHM_OPT_CONCURRENT_CLASSES: the largest on `st` and the others forked onto
+// the context's class streams and joined back).
 mhm_status enqueue_run(mhm_ctx c, const RunPlan& rp, const mhm_batch* b, const RunIO& io, void* ws_v, hipStream_t st,
                        bool fallback_only = false, bool one_stream = false) {
   char* ws = static_cast<char*>(ws_v);
@@ -467,7 +484,7 @@ mhm_status enqueue_run(mhm_ctx c, const RunPlan& rp, const mhm_batch* b, const R
     hipError_t e = mhm::launch_bin(b, bin_classes(), lists, counts, st);
     if (e != hipSuccess) return hip_fail(c, e, "k_bin launch");
   }
-  const bool fork = rp.n_runs > 1 && !one_stream;
+  const bool fork = rp.n_runs > 1 && !one_stream && c->concurrent_classes;
   if (fork) {
     mhm_status s0 = ensure_streams(c);
     if (s0 != MHM_OK) return s0;
@@ -482,9 +499,11 @@ mhm_status enqueue_run(mhm_ctx c, const RunPlan& rp, const mhm_batch* b, const R
     const ClassRun& r = rp.run[i];
     const int32_t* el = rp.listed ? lists + (size_t)r.cls * b->n_elem : nullptr;
     const int32_t* ec = rp.listed ? counts + r.cls : nullptr;
-    mhm_status s1 = enqueue_class(c, r, b, io, ws, el, ec, i == 0 || !fork ? st : c->aux[i], fallback_only);
+    const int slot = c->class_timing && !fallback_only ? i : -1;
+    mhm_status s1 = enqueue_class(c, r, b, io, ws, el, ec, i == 0 || !fork ? st : c->aux[i], fallback_only, slot);
     if (s1 != MHM_OK) return s1;
   }
+  if (c->class_timing && !fallback_only) c->timed_n = rp.n_runs;
   if (fork) {
     for (int i = 1; i < rp.n_runs; ++i) {
       hipError_t e = hipEventRecord(c->join[i], c->aux[i]);
@@ -641,6 +660,10 @@ mhm_status mhm_destroy(mhm_ctx c) {
     if (c->join[k]) (void)hipEventDestroy(c->join[k]);
   }
   if (c->fork) (void)hipEventDestroy(c->fork);
+  for (int k = 0; k < kNumClasses; ++k) {
+    if (c->t_beg[k]) (void)hipEventDestroy(c->t_beg[k]);
+    if (c->t_end[k]) (void)hipEventDestroy(c->t_end[k]);
+  }
   if (c->ws) (void)hipFree(c->ws);
   delete c;
   return MHM_OK;
@@ -670,8 +693,40 @@ mhm_status mhm_set_option(mhm_ctx c, int option, int value) {
       if (value != 0 && value != 2 && value != 3) return fail(c, MHM_E_ARG, "MHM_OPT_RR_OCC takes 0, 2 or 3");
       c->rr_occ = value;
       return MHM_OK;
+    case MHM_OPT_CONCURRENT_CLASSES: {
+      if (value != 0 && value != 1) return fail(c, MHM_E_ARG, "MHM_OPT_CONCURRENT_CLASSES takes 0 or 1");
+      c->concurrent_classes = value != 0;
+      return MHM_OK;
+    }
+    case MHM_OPT_CLASS_TIMING: {
+      if (value != 0 && value != 1) return fail(c, MHM_E_ARG, "MHM_OPT_CLASS_TIMING takes 0 or 1");
+      if (value && !c->t_beg[0]) {
+        hipError_t e = hipSetDevice(c->device);
+        for (int k = 0; k < kNumClasses && e == hipSuccess; ++k) {
+          e = hipEventCreate(&c->t_beg[k]);
+          if (e == hipSuccess) e = hipEventCreate(&c->t_end[k]);
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+      }
+      c->class_timing = value != 0;
+      c->timed_n = -1;
+      return MHM_OK;
+    }
     default: return fail(c, MHM_E_ARG, "unknown option " + std::to_string(option));
   }
+}
+
+int mhm_class_times(mhm_ctx c, int32_t* s_cap, float* ms, int max) {
+  if (!c || !c->class_timing || c->timed_n < 0 || max < 0) return -1;
+  const int n = std::min(c->timed_n, max);
+  for (int k = 0; k < n; ++k) {
+    float t = 0.0f;
+    if (hipEventSynchronize(c->t_end[k]) != hipSuccess || hipEventElapsedTime(&t, c->t_beg[k], c->t_end[k]) != hipSuccess)
+      return -1;
+    if (s_cap) s_cap[k] = c->timed_cap[k];
+    if (ms) ms[k] = t;
+  }
+  return n;
 }
 
 mhm_status mhm_set_stream(mhm_ctx c, void* hip_stream) {
@@ -1000,7 +1055,10 @@ mhm_status mhm_graph_create(mhm_ctx c, const mhm_batch* b, mhm_prec prec, double
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
   if (e == hipSuccess) {
+    const bool timing = c->class_timing;   // no timing events inside a captured graph
+    c->class_timing = false;
     st = enqueue_run(c, rp, b, fused_io(X, M, E, B, F, info, ir_iters, max_iters), g->ws, cs);
+    c->class_timing = timing;
     const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
     if (st == MHM_OK && e2 != hipSuccess) st = hip_fail(c, e2, "hipStreamEndCapture");
     if (st == MHM_OK) {

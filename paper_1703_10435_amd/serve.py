@@ -133,7 +133,10 @@ class Server:
             raise abi.MhmError(st, self.lib.mhm_server_last_error(self.h).decode())
         return list(tickets)
 
-    def poll(self, max_n: int = 4096, copy_arrays: bool = True) -> list:
+    def poll(self, max_n: int = 4096, copy_arrays: bool = True, copy_tickets=None) -> list:
+        """Finished results; their arrays (X, M, E, B) are copied when
+        copy_arrays is set or the ticket is in copy_tickets (the library's
+        buffers are reused by the next poll)."""
         out = (Result * max_n)()
         k = self.lib.mhm_server_poll(self.h, out, max_n)
         res = []
@@ -142,7 +145,7 @@ class Server:
             d = dict(ticket=int(r.ticket), info=int(r.info), ir_iters=int(r.ir_iters), cache_hit=bool(r.cache_hit),
                      s=int(r.s), l=int(r.l), n=int(r.n), r=int(r.r), t_arrival=float(r.t_arrival),
                      t_done=float(r.t_done), F=float(r.F))
-            if copy_arrays:
+            if copy_arrays or (copy_tickets is not None and int(r.ticket) in copy_tickets):
                 ni = r.r - 1
                 d["X"] = np.ctypeslib.as_array(r.X, shape=(r.n * r.r,)).reshape(r.r, r.n).T.copy()
                 d["M"] = np.ctypeslib.as_array(r.M, shape=(ni * ni,)).reshape(ni, ni).T.copy()
@@ -169,9 +172,12 @@ class Server:
 
 
 def run_open_loop(server: Server, reqs: list, arrivals, copy_arrays: bool = False, timeout_s: float = 120.0,
-                  progress=None) -> dict:
+                  progress=None, keep=None) -> dict:
     """Submit reqs[k] at server clock t0 + arrivals[k] (open loop), collect
-    every result; returns per-request latency and throughput."""
+    every result; returns per-request latency and throughput.  Result arrays
+    are kept for every request (copy_arrays) or for the indices in keep."""
+    keep = set() if keep is None else set(int(k) for k in keep)
+    keep_tickets = set()
     arrivals = np.asarray(arrivals, dtype=np.float64)
     n = len(reqs)
     t0 = server.now() + 0.01
@@ -188,8 +194,10 @@ def run_open_loop(server: Server, reqs: list, arrivals, copy_arrays: bool = Fals
             tk = server.submit(reqs[i:j])
             for a, t in enumerate(tk):
                 tick_of[t] = i + a
+                if i + a in keep:
+                    keep_tickets.add(int(t))
             i = j
-        got = server.poll(copy_arrays=copy_arrays)
+        got = server.poll(copy_arrays=copy_arrays, copy_tickets=keep_tickets)
         for r in got:
             results[tick_of[r["ticket"]]] = r
         if not got and j == i:

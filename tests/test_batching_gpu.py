@@ -206,3 +206,24 @@ def test_bucketed_alone_vs_mixed_bitwise(ctx):
         alone, _, _ = engine.solve_batch(sb, prec=0, mode="fused", ctx=ctx)
         np.testing.assert_array_equal(alone[1]["X"], full[e]["X"])
         np.testing.assert_array_equal(alone[1]["M"], full[e]["M"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_concurrent_classes_match_serial_bitwise(ctx, prec):
+    """The size classes on forked streams (MHM_OPT_CONCURRENT_CLASSES) give
+    the same bits as the default, one class after another."""
+    from paper_1703_10435_amd import engine
+    b = _random_batch(27, S_ALL, L_ALL, "concurrent")
+    say(f"[gpu] concurrent classes prec={prec}")
+    # fresh contexts: the module's context carries an earlier test's tuning
+    c0, c = _ctx(), _ctx({"concurrent_classes": 1})
+    try:
+        serial, _, _ = engine.solve_batch(b, prec=prec, mode="fused", ctx=c0)
+        conc, _, _ = engine.solve_batch(b, prec=prec, mode="fused", ctx=c)
+    finally:
+        c.close()
+        c0.close()
+    for e in range(b["n_elem"]):
+        for k in ("X", "M", "E", "B"):
+            np.testing.assert_array_equal(conc[e][k], serial[e][k])
+        assert conc[e]["info"] == serial[e]["info"]
