@@ -350,6 +350,11 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  // c - a b: on gfx950 the last immediate of the FP64 instruction is its
+  // negate modifier (bit 0: operand A), so the sign costs no instruction
+  static __device__ __forceinline__ v4 op_sub(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 1);
+  }
   static __host__ __device__ constexpr int row(int g, int v) { return g + 4 * v; }
   static __host__ __device__ constexpr int grp(int r) { return r & 3; }
   static __host__ __device__ constexpr int item(int r) { return r >> 2; }
@@ -358,6 +363,9 @@ template <> struct Mfma<float> {
   typedef float v4 __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ v4 op_sub(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(-a, b, c, 0, 0, 0);
   }
   static __host__ __device__ constexpr int row(int g, int v) { return 4 * g + v; }
   static __host__ __device__ constexpr int grp(int r) { return r >> 2; }

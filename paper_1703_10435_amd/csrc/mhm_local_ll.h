@@ -10,9 +10,9 @@
 //       operator (Ahat = A + gamma c c^T is never stored) and the right-hand
 //       sides, rows of 16 distributed over the waves (wave w owns rows
 //       j0 + w + 8 ri);
-//   (b) every earlier tile column m is applied, C_ij -= L_im L_jm^T, with the
-//       B operands (the PW tiles L_jm) staged in LDS and the A operands L_im
-//       loaded from the workspace (L2 / Infinity Cache resident);
+//   (b) every earlier tile column m is applied, C_ij -= L_im L_jm^T, each
+//       wave streaming its A operands L_im and the panel's B tiles L_jm from
+//       the workspace into registers, with no barrier between columns;
 //   (c) the panel is factored in place (diagonal tile by one wave in LDS,
 //       panel solve and in-panel updates in registers) and written once.
 // Each tile of L is therefore written once and read once per later block
@@ -36,6 +36,11 @@ namespace ll {
 template <typename T> struct Vec4U;
 template <> struct Vec4U<float> { typedef float t __attribute__((ext_vector_type(4), aligned(4))); };
 template <> struct Vec4U<double> { typedef double t __attribute__((ext_vector_type(4), aligned(8))); };
+template <typename T>
+__device__ __forceinline__ typename Mfma<T>::v4 ld_row4v(const T* t, int lane) {
+  const typename Vec4U<T>::t v = *reinterpret_cast<const typename Vec4U<T>::t*>(t + (lane & 15) * TST + 4 * (lane >> 4));
+  return typename Mfma<T>::v4{v[0], v[1], v[2], v[3]};
+}
 template <typename T>
 __device__ __forceinline__ void ld_row4(const T* t, int lane, T (&o)[4]) {
   const typename Vec4U<T>::t v = *reinterpret_cast<const typename Vec4U<T>::t*>(t + (lane & 15) * TST + 4 * (lane >> 4));
@@ -201,7 +206,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
   // wider than 80 accumulator registers per lane (two FP32 or one FP64 tile
   // per row) would not fit next to the operands, so the rows are updated and
   // solved in passes of five or two; with 16 waves (128 registers) the limit
-  // is 40, passes of one row.  The earlier columns' B tiles are staged once
+  // is 40, passes of one row.  The earlier columns' B tiles are loaded once
   // per pass, the A tiles (the bulk of the reads) still once per panel.
   constexpr int ACC = PW * 4 * (int)(sizeof(T) / 4);   // accumulator registers per row
   constexpr int RS = (MC || OCC != 1)            ? 1
@@ -257,8 +262,8 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
     double* c = dyn;
     double* bf = c + args.n_cap;
     double* ft = bf + args.n_cap;
-    T* stage = reinterpret_cast<T*>(ft + args.f_cap);  // 2 x PW tiles
-    T* Wt = stage + 2 * PW * TILE;                       // the panel's PW diagonal inverses
+    T* stage = reinterpret_cast<T*>(ft + args.f_cap);  // 2 tiles
+    T* Wt = stage + 2 * TILE;                            // the panel's PW diagonal inverses
     T* pub = Wt + PW * TILE;                             // PW x PW published panel tiles
     T* scr = pub + PW * PW * TILE + wave * TILE;         // this wave's scratch tile
     T* ws = reinterpret_cast<T*>(args.ws) + (int64_t)blockIdx.x * args.ws_slot;
@@ -416,6 +421,10 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
       const int pw = nt - j0 < PW ? nt - j0 : PW;
 #pragma unroll 1
       for (int h = 0; h < RS; ++h) {
+        // the rows of pass h start at j0 + NW RH h: past the last row no wave
+        // holds any (nor in the later passes), so the pass and its sweep over
+        // the earlier columns are skipped (the same for every wave)
+        if (h > 0 && j0 + NW * RH * h >= (MC ? nrows : nt + 1)) break;
         // rows of this pass: slots h RH .. h RH + RH - 1 of the wave
         auto row_of = [&](int ri) { return j0 + wave + NW * (h * RH + ri); };
         V4 acc[RH][PW];
@@ -431,50 +440,39 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
 #pragma unroll
           for (int k = 0; k < PW; ++k) acc[ri][k] = V4{0, 0, 0, 0};
         }
-        // (b) earlier tile columns.  The operands of column m + 1 (A operands
-        // in registers, B tiles for the LDS stage) are loaded while the MFMAs
-        // of column m run; one barrier per column (stage buffers alternate).
-        if (j0 > 0) {
-          constexpr int SPT = (PW * TILE + NTHREADS - 1) / NTHREADS;
-          // operand buffers (prefetch depth) within a register estimate
+        // (b) earlier tile columns, C_ij -= L_im L_jm^T for m < j0.  Each wave
+        // loads its own operands for column m, the A tiles L_im of its rows
+        // and the panel's B tiles L_jm (the same for every wave: they come
+        // from the L1 / L2 after the first wave), straight into registers,
+        // NB columns ahead.  There is no barrier in this loop (the tiles of
+        // earlier panels were published by the barrier that ended each pass),
+        // so the waves of a SIMD overlap one another's load latency, and a
+        // wave without rows in this pass skips it.
+        if (j0 > 0 && held_i(row_of(0))) {
           constexpr int W = (int)sizeof(T) / 4;
-          // (budgets for 256 registers per lane, or 128 with 16 waves)
-          constexpr int B3 = NW == 16 ? 72 : 144, B2 = NW == 16 ? 96 : 160;
-          constexpr int NB = OCC == 2                                            ? 1
-                             : RH * PW * 4 * W + 3 * (RH * 4 + SPT) * W <= B3 ? 3
-                             : RH * PW * 4 * W + 2 * (RH * 4 + SPT) * W <= B2 ? 2
-                                                                              : 1;
-          T ab[NB][RH][4];
-          T sb[NB][SPT];
-          auto fetch = [&](int m, T (&a)[RH][4], T (&sv)[SPT]) {
+          // operand buffers (prefetch depth) within a register estimate:
+          // accumulators plus NB stages of RH A rows and PW B tiles (256
+          // registers per lane, or 128 with 16 waves or two workgroups per CU;
+          // less where the row passes keep more state live across the loop,
+          // which the compiler would otherwise spill inside it)
+          constexpr int ACCR = RH * PW * 4 * W, STG = (RH + PW) * 4 * W;
+          constexpr int BUD = (NW == 16 || OCC == 2) ? 88 : 150;
+          constexpr int NB = ACCR + 3 * STG <= BUD ? 3 : ACCR + 2 * STG <= BUD ? 2 : 1;
+          // (operands as 4-vectors: a row's values stay one register group)
+          V4 ab[NB][RH];
+          V4 bb[NB][PW];
+          auto fetch = [&](int m, V4 (&a)[RH], V4 (&bt)[PW]) {
             if (m >= j0) return;
 #pragma unroll
             for (int ri = 0; ri < RH; ++ri) {
               const int i = row_of(ri);
-              if (held_i(i)) ll::ld_row4(tl(i, m), lane, a[ri]);
+              if (held_i(i)) a[ri] = ll::ld_row4v(tl(i, m), lane);
             }
 #pragma unroll
-            for (int q = 0; q < SPT; ++q) {
-              const int idx = tid + q * NTHREADS;
-              if (idx < pw * TILE) sv[q] = tl(j0 + idx / TILE, m)[idx % TILE];
-            }
+            for (int jj = 0; jj < PW; ++jj)
+              if (jj < pw) bt[jj] = ll::ld_row4v(tl(j0 + jj, m), lane);
           };
-          auto apply = [&](int m, const T (&a)[RH][4], const T (&sv)[SPT]) {
-            T* st = stage + (m & 1) * PW * TILE;
-#pragma unroll
-            for (int q = 0; q < SPT; ++q) {
-              const int idx = tid + q * NTHREADS;
-              if (idx < pw * TILE) st[idx] = sv[q];
-            }
-            __syncthreads();
-            // B operands (the staged tiles L_jm): in FP32 read once and used by
-            // every row (registers to spare); in FP64 read per row
-            constexpr bool HOIST = sizeof(T) == 4;
-            T bo[PW][4];
-            if constexpr (HOIST) {
-#pragma unroll
-              for (int jj = 0; jj < PW; ++jj) ll::ld_row4(st + jj * TILE, lane, bo[jj]);
-            }
+          auto apply = [&](const V4 (&a)[RH], const V4 (&bt)[PW]) {
 #pragma unroll
             for (int ri = 0; ri < RH; ++ri) {
               const int i = row_of(ri);
@@ -484,10 +482,7 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
                   if (jj < pw && (rhs_i(i) || i >= j0 + jj)) {
                     V4 x = acc[ri][jj];
 #pragma unroll
-                    for (int cch = 0; cch < 4; ++cch)
-                      x = Mfma<T>::op(
-                          -a[ri][cch], HOIST ? bo[jj][cch] : st[jj * TILE + (lane & 15) * TST + 4 * (lane >> 4) + cch],
-                          x);
+                    for (int cch = 0; cch < 4; ++cch) x = Mfma<T>::op_sub(a[ri][cch], bt[jj][cch], x);
                     acc[ri][jj] = x;
                   }
                 }
@@ -495,19 +490,20 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
             }
           };
           if constexpr (NB == 1) {
+#pragma unroll 1
             for (int m = 0; m < j0; ++m) {
-              fetch(m, ab[0], sb[0]);
-              apply(m, ab[0], sb[0]);
+              fetch(m, ab[0], bb[0]);
+              apply(ab[0], bb[0]);
             }
           } else {
 #pragma unroll
-            for (int q = 0; q < NB; ++q) fetch(q, ab[q], sb[q]);
+            for (int q = 0; q < NB; ++q) fetch(q, ab[q], bb[q]);
             for (int m = 0; m < j0; m += NB) {
 #pragma unroll
               for (int q = 0; q < NB; ++q) {
                 if (m + q < j0) {
-                  apply(m + q, ab[q], sb[q]);
-                  fetch(m + q + NB, ab[q], sb[q]);
+                  apply(ab[q], bb[q]);
+                  fetch(m + q + NB, ab[q], bb[q]);
                 }
               }
             }

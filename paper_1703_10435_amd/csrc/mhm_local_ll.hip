@@ -47,7 +47,7 @@ bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw, bool mc) {
 
 size_t local_ll_lds_bytes(bool fp32, int pw, int n_cap, int f_cap, int nw) {
   return sizeof(double) * (2 * (size_t)n_cap + (size_t)f_cap) +
-         (size_t)(2 * pw + pw + pw * pw + nw) * TILE * (fp32 ? sizeof(float) : sizeof(double));
+         (size_t)(2 + pw + pw * pw + nw) * TILE * (fp32 ? sizeof(float) : sizeof(double));
 }
 
 hipError_t launch_local_ll(bool fp32, bool fused, int pw, int occ, int nw, bool mc, bool ref, int nt_max,
