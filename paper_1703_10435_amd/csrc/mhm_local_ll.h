@@ -224,7 +224,9 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
   __shared__ double part_s[32 * (NTHREADS / 256)];
   __shared__ double rmax[16], xmax[16], bmax[16];
   extern __shared__ double dyn[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform: held in a scalar register, so the per-row
+  // conditions below are scalar branches
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int NImax = nimax(b);
   const bool fp32 = sizeof(T) == 4;
 
@@ -490,10 +492,57 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
             }
           };
           if constexpr (NB == 1) {
+            // one operand set: row ri's A tile of column m + 1 is loaded
+            // right after the MFMAs of column m that read it, so it has the
+            // other rows' MFMAs to arrive; the B tiles are double-buffered.
+            // Every load is unconditional (a row or tile outside the pass,
+            // and the step past the last column, load a valid tile again),
+            // so the waits count the loads exactly.
+            V4 (&a)[RH] = ab[0];
+            V4 bq0[PW], bq1[PW];
+            const int r0 = row_of(0);
+            auto ld_a = [&](int ri, int m) {
+              const int i = row_of(ri);
+              return ll::ld_row4v(tl(held_i(i) ? i : r0, m), lane);
+            };
+            auto ld_b = [&](int jj, int m) { return ll::ld_row4v(tl(j0 + (jj < pw ? jj : 0), m), lane); };
+#pragma unroll
+            for (int ri = 0; ri < RH; ++ri) a[ri] = ld_a(ri, 0);
+#pragma unroll
+            for (int jj = 0; jj < PW; ++jj) {
+              bq0[jj] = ld_b(jj, 0);
+              bq1[jj] = ld_b(jj, j0 > 1 ? 1 : 0);
+            }
+            auto step = [&](int m, V4 (&bc)[PW]) {
+              const int mn = m + 1 < j0 ? m + 1 : m, mb = m + 2 < j0 ? m + 2 : m;
+#pragma unroll
+              for (int ri = 0; ri < RH; ++ri) {
+                const int i = row_of(ri);
+                if (held_i(i)) {
+#pragma unroll
+                  for (int jj = 0; jj < PW; ++jj) {
+                    if (jj < pw && (rhs_i(i) || i >= j0 + jj)) {
+                      V4 x = acc[ri][jj];
+#pragma unroll
+                      for (int cch = 0; cch < 4; ++cch) x = Mfma<T>::op_sub(a[ri][cch], bc[jj][cch], x);
+                      acc[ri][jj] = x;
+                    }
+                  }
+                }
+                a[ri] = ld_a(ri, mn);
+              }
+#pragma unroll
+              for (int jj = 0; jj < PW; ++jj) bc[jj] = ld_b(jj, mb);
+            };
 #pragma unroll 1
             for (int m = 0; m < j0; ++m) {
-              fetch(m, ab[0], bb[0]);
-              apply(ab[0], bb[0]);
+              step(m, bq0);
+#pragma unroll
+              for (int jj = 0; jj < PW; ++jj) {
+                const V4 t = bq0[jj];
+                bq0[jj] = bq1[jj];
+                bq1[jj] = t;
+              }
             }
           } else {
 #pragma unroll

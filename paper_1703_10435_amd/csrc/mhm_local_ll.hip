@@ -21,13 +21,14 @@ int local_ll_rows_per_wave(int nt, int nw) {
   return -1;
 }
 
-// FP32: width 4.  FP64: width 2.  With ten rows per wave (the largest
-// elements) both take the rows in two passes (s = 48, 1024 elements: FP64
-// 33 ms against 52 ms with one-tile panels, FP32 23 against 24 ms with
-// two-tile panels).
+// FP32: width 4.  FP64: width 2, and 4 for the largest elements (ten rows
+// per wave, taken in five passes of two rows): every earlier tile column is
+// then read once per four panel columns instead of two, which halves the
+// factor traffic that bounds these elements (C4's s = 48 class, 2048
+// elements: 38 ms against 50 ms with two-tile panels).
 int local_ll_default_panel(bool fp32, int nt) {
-  (void)nt;
-  return fp32 ? 4 : 2;
+  if (fp32) return 4;
+  return local_ll_rows_per_wave(nt, 8) == 10 ? 4 : 2;
 }
 
 bool local_ll_has(bool fp32, int pw, int nt, int occ, int nw, bool mc) {
