@@ -625,9 +625,8 @@ def main():
     from paper_1703_10435_amd import abi, engine
     from paper_1703_10435_amd.batch import DeviceBatch
 
-    if not os.path.exists(abi.LIB_PATH):
-        from paper_1703_10435_amd import build as _b
-        _b.build()
+    from paper_1703_10435_amd import build as _b
+    _b.ensure()   # rebuilt only if missing or built from other sources
     if args.copy_calib:
         src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)

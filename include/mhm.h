@@ -193,6 +193,10 @@ int mhm_class_times(mhm_ctx ctx, int32_t* s_cap, float* ms, int max);
  * NULL context, the last error of a context-less call (mhm_create) on the
  * calling thread. */
 const char* mhm_last_error(mhm_ctx ctx);
+/* SHA-256 (64 hex digits) of the sources and compile flags this library was
+ * built from, for checking that a built library matches its sources; a
+ * static string owned by the library ("unstamped" when built without it). */
+const char* mhm_source_hash(void);
 /* Block until all work enqueued by this context has finished. */
 mhm_status mhm_sync(mhm_ctx ctx);
 /* Device workspace (bytes) the context allocates for a batch and precision

@@ -24,7 +24,7 @@ EXPORTS = (
     "mhm_autotune", "mhm_tune_report", "mhm_graph_create", "mhm_graph_launch", "mhm_graph_destroy",
     "mhm_factor_bytes", "mhm_local_batch_run_cached", "mhm_skeleton_scatter", "mhm_reconstruct",
     "mhm_local_source_step", "mhm_skeleton_solve", "mhm_set_option", "mhm_local_batch_run_noalloc",
-    "mhm_class_times",
+    "mhm_class_times", "mhm_source_hash",
 )
 
 # Context options (mhm_set_option)
@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH):
         "mhm_set_option": (i32, [vp, i32, i32]),
         "mhm_class_times": (i32, [vp, vp, vp, i32]),
         "mhm_last_error": (ctypes.c_char_p, [vp]),
+        "mhm_source_hash": (ctypes.c_char_p, []),
         "mhm_sync": (i32, [vp]),
         "mhm_workspace_bytes": (ctypes.c_size_t, [vp, bp, i32]),
         "mhm_local_assemble": (i32, [vp, bp, vp, vp, vp, vp, i64p]),

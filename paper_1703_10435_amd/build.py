@@ -1,10 +1,15 @@
 """Build ``libmhm.so`` (the C-ABI library) in-tree with hipcc for gfx950.
 
-Usage: ``python -m paper_1703_10435_amd.build``.  Compiles every time it is
-called (a stale library is never reused silently).
+Usage: ``python -m paper_1703_10435_amd.build``.  ``build()`` compiles every
+time it is called.  The library carries the SHA-256 of the sources and flags
+it was built from (``mhm_source_hash()``, and the same text in the file), so
+``ensure()`` rebuilds a library whose sources have changed since: a stale
+library is never reused silently.
 """
 from __future__ import annotations
 
+import glob
+import hashlib
 import os
 import shutil
 import subprocess
@@ -18,6 +23,8 @@ SOURCES = ["mhm_kernels.hip", "mhm_local_rr.hip", "mhm_local_ll.hip", "mhm_local
            "mhm_local_ll_f64r.hip",
            "mhm_source_step.hip", "mhm_skeleton_solve.hip", "mhm_api.hip", "mhm_server.hip"]
 ARCH = "gfx950"
+INCLUDE = os.path.join(os.path.dirname(HERE), "include", "mhm.h")
+STAMP_TAG = b"MHM_SOURCE_SHA256="   # followed by 64 hex digits in the built library
 
 
 def hipcc() -> str:
@@ -36,12 +43,54 @@ def compile_flags() -> list:
     ]
 
 
+def stamped_files() -> list:
+    """Every file the library is built from: the HIP sources and headers and
+    the public header."""
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h"))) + [INCLUDE]
+
+
+def source_hash() -> str:
+    """SHA-256 over the file names and contents of stamped_files() and the
+    compile flags."""
+    h = hashlib.sha256()
+    for path in stamped_files():
+        h.update(os.path.basename(path).encode() + b"\0")
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(compile_flags()).encode())
+    return h.hexdigest()
+
+
+def stamp_of(path: str = LIB):
+    """The source hash a built library carries (None: no library, or none)."""
+    if not os.path.exists(path):
+        return None
+    with open(path, "rb") as fh:
+        data = fh.read()
+    k = data.find(STAMP_TAG)
+    if k < 0:
+        return None
+    return data[k + len(STAMP_TAG):k + len(STAMP_TAG) + 64].decode("ascii", "replace")
+
+
+def is_current(path: str = LIB) -> bool:
+    return stamp_of(path) == source_hash()
+
+
+def ensure(verbose: bool = False) -> str:
+    """The library, rebuilt first if it is missing or its sources changed."""
+    if not is_current(LIB):
+        build(verbose)
+    return LIB
+
+
 def build(verbose: bool = False) -> str:
     cc = hipcc()
     objs = [os.path.join(CSRC, src.replace(".hip", ".o")) for src in SOURCES]
+    stamp = f'-DMHM_SOURCE_HASH="{source_hash()}"'
 
     def compile_one(i):
-        cmd = [cc, *compile_flags(), "-c", os.path.join(CSRC, SOURCES[i]), "-o", objs[i]]
+        cmd = [cc, *compile_flags(), stamp, "-c", os.path.join(CSRC, SOURCES[i]), "-o", objs[i]]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -737,6 +737,15 @@ mhm_status mhm_set_stream(mhm_ctx c, void* hip_stream) {
 
 const char* mhm_last_error(mhm_ctx c) { return c ? c->err.c_str() : g_err.c_str(); }
 
+// The build passes the SHA-256 of the sources it compiles; the tag makes the
+// same text findable in the library file without loading it.
+#ifndef MHM_SOURCE_HASH
+#define MHM_SOURCE_HASH "unstamped"
+#endif
+__attribute__((used)) static const char kSourceStamp[] = "MHM_SOURCE_SHA256=" MHM_SOURCE_HASH;
+
+const char* mhm_source_hash(void) { return kSourceStamp + sizeof("MHM_SOURCE_SHA256=") - 1; }
+
 mhm_status mhm_sync(mhm_ctx c) {
   if (!c) return MHM_E_ARG;
   hipError_t e = hipStreamSynchronize(c->stream);

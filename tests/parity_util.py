@@ -10,9 +10,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def ensure_built():
+    """The library, rebuilt when it is missing or was built from other sources
+    (its stamped source hash differs from the tree's)."""
     from paper_1703_10435_amd import abi, build
-    if not os.path.exists(abi.LIB_PATH):
-        build.build()
+    build.ensure()
     return abi.LIB_PATH
 
 

@@ -136,3 +136,20 @@ def test_skeleton_numbering_and_pattern(N, l, l_max, m):
     diag[erow, erow] = True
     np.testing.assert_array_equal(mask & ~diag, K != 0)
     assert rp.dtype == np.int32 and ci.dtype == np.int32
+
+
+def test_library_carries_the_hash_of_its_sources(tmp_path):
+    """The built library is stamped with the SHA-256 of the sources it was
+    built from; a library with another stamp (or none) counts as stale and
+    ensure() would rebuild it."""
+    from paper_1703_10435_amd import build
+    path = ensure_built()
+    h = build.source_hash()
+    assert len(h) == 64 and build.stamp_of(path) == h and build.is_current(path)
+    assert abi.load().mhm_source_hash().decode() == h
+    stale = tmp_path / "stale.so"
+    stale.write_bytes(b"\0" * 64 + build.STAMP_TAG + b"0" * 64 + b"\0")
+    assert build.stamp_of(str(stale)) == "0" * 64 and not build.is_current(str(stale))
+    (tmp_path / "none.so").write_bytes(b"\0" * 128)
+    assert build.stamp_of(str(tmp_path / "none.so")) is None
+    assert not build.is_current(str(tmp_path / "missing.so"))
