@@ -59,6 +59,9 @@
  *          the element is written
  *     -3   the element is larger than the launched kernel supports
  *     -4   (mhm_local_source_step) no stored factor for the element
+ *     -5   (mhm_server results) the launch that carried the request failed
+ *          (mhm_server_last_error says why): no output was computed, the
+ *          result's arrays are NaN, and no factor of that launch is reused
  */
 #ifndef MHM_H
 #define MHM_H
@@ -71,6 +74,7 @@ extern "C" {
 #endif
 
 #define MHM_S_LIMIT 64   /* largest s per element          */
+#define MHM_INFO_LAUNCH_FAILED (-5)   /* server result of a failed launch */
 #define MHM_L_LIMIT 4    /* largest l per element                          */
 #define MHM_P_LIMIT 16   /* largest m (l + 1), face DoFs per face (r <= 49):
                             a batch with p_max (or l_max + 1) above 5, that is

@@ -30,22 +30,17 @@
 #include <vector>
 
 #include "../../include/mhm.h"
+#include "mhm_server_core.h"
 
 namespace {
+
+using mhm_srv::Key;
+using mhm_srv::n_of;
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
-int n_of(int s) { return (s + 1) * (s + 2) / 2; }
 size_t up256(size_t x) { return (x + 255) / 256 * 256; }
-
-struct Key {
-  uint64_t hi, lo;
-  bool operator==(const Key& o) const { return hi == o.hi && lo == o.lo; }
-};
-struct KeyHash {
-  size_t operator()(const Key& k) const { return k.hi * 0x9E3779B97F4A7C15ull ^ k.lo; }
-};
 
 struct Req {
   uint64_t ticket;
@@ -56,88 +51,6 @@ struct Req {
   int8_t sigma[3], flip[3];
   std::vector<double> kappa, f;
   double t_arrival;
-};
-
-// Factor arena: first-fit free list with coalescing, LRU over unpinned entries.
-struct Entry {
-  size_t off, bytes;
-  int pins = 0;
-  bool valid = false;
-  std::list<Key>::iterator lru;
-};
-struct Cache {
-  size_t cap = 0;
-  std::map<size_t, size_t> free_;   // offset -> bytes
-  std::unordered_map<Key, Entry, KeyHash> map;
-  std::list<Key> lru;               // front = most recently used
-  size_t used = 0;
-  uint64_t evictions = 0;
-
-  void init(size_t bytes) {
-    cap = bytes;
-    free_.clear();
-    if (bytes) free_[0] = bytes;
-  }
-  void release(size_t off, size_t bytes) {
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-    used -= bytes;
-  }
-  bool take(size_t bytes, size_t& off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        off = it->first;
-        const size_t rest = it->second - bytes;
-        free_.erase(it);
-        if (rest) free_[off + bytes] = rest;
-        used += bytes;
-        return true;
-      }
-    }
-    return false;
-  }
-  void erase(const Key& k) {
-    auto it = map.find(k);
-    if (it == map.end()) return;
-    release(it->second.off, it->second.bytes);
-    lru.erase(it->second.lru);
-    map.erase(it);
-  }
-  // room for `bytes`, evicting least recently used unpinned factors
-  bool alloc(size_t bytes, size_t& off) {
-    if (bytes > cap) return false;
-    while (!take(bytes, off)) {
-      auto victim = lru.end();
-      for (auto it = lru.rbegin(); it != lru.rend(); ++it) {
-        if (map[*it].pins == 0) {
-          victim = std::prev(it.base());
-          break;
-        }
-      }
-      if (victim == lru.end()) return false;
-      const Key k = *victim;
-      erase(k);
-      ++evictions;
-    }
-    return true;
-  }
-  void touch(const Key& k) {
-    Entry& e = map[k];
-    lru.erase(e.lru);
-    lru.push_front(k);
-    e.lru = lru.begin();
-  }
 };
 
 // Host (pinned) and device buffers of one launch slot, sized for the
@@ -151,8 +64,7 @@ struct Slot {
   char* d = nullptr;   // device copy
   size_t in_bytes = 0, out_bytes = 0;
   std::vector<Req> reqs;
-  std::vector<int8_t> state;
-  std::vector<Key> pinned;
+  mhm_srv::Admitted adm;   // factor state, offset and entry of each request
   // layout (byte offsets into h / d)
   size_t o_s, o_l, o_vert, o_sig, o_flip, o_kap, o_f, o_tri, o_rhs, o_foff, o_fst;
   size_t o_X, o_M, o_E, o_B, o_F, o_info, o_it;
@@ -166,7 +78,7 @@ struct mhm_server_s {
   int device = 0;
   std::vector<Slot> slots;
   char* arena = nullptr;
-  Cache cache;
+  mhm_srv::Cache cache;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Req> queue;
@@ -219,73 +131,43 @@ void layout(Slot& sl, int B, int64_t cap_tri, int64_t cap_rhs, int NI) {
   sl.out_bytes = o - sl.in_bytes;
 }
 
+// Every request of a launch that could not run completes at once with info
+// MHM_INFO_LAUNCH_FAILED and NaN outputs; the factors it created are
+// dropped, never marked valid.  Caller holds the lock.
+void fail_launch(mhm_server srv, Slot& sl) {
+  (void)hipStreamSynchronize(sl.stream);   // the staging buffer may still be read by a copy
+  (void)hipGetLastError();
+  const double t = now_s();
+  for (size_t k = 0; k < sl.reqs.size(); ++k) {
+    const Req& q = sl.reqs[k];
+    const int n = n_of(q.s), ni = 3 * (q.l + 1), r = ni + 1;
+    mhm_result res;
+    std::memset(&res, 0, sizeof(res));
+    res.ticket = q.ticket;
+    res.info = MHM_INFO_LAUNCH_FAILED;
+    res.cache_hit = sl.adm.state[k] == 1;
+    res.s = q.s;
+    res.l = q.l;
+    res.n = n;
+    res.r = r;
+    res.t_arrival = q.t_arrival;
+    res.t_done = t;
+    srv->done.push_back(res);
+    srv->done_data.emplace_back((size_t)n * r + (size_t)ni * ni + 2 * ni + 1, __builtin_nan(""));
+    mhm_srv::settle(srv->cache, sl.adm, k, false, res.info);
+    srv->stats.completed++;
+  }
+  sl.reqs.clear();
+  sl.busy = false;
+}
+
 // Launch the queued requests on a free slot.  Caller holds the lock.
 bool launch(mhm_server srv, Slot& sl) {
   const mhm_server_config& c = srv->cfg;
-  sl.reqs.clear();
-  sl.state.clear();
-  sl.pinned.clear();
-  std::vector<size_t> foff;
-  int64_t tri = 0, rhs = 0;
-  std::unordered_map<Key, int, KeyHash> in_batch;
-  for (auto it = srv->queue.begin(); it != srv->queue.end() && (int)sl.reqs.size() < c.max_batch;) {
-    const Req& q = *it;
-    const int n = n_of(q.s), r = 3 * (q.l + 1) + 1;
-    if (tri + (int64_t)q.s * q.s > srv->cap_tri || rhs + (int64_t)n * r > srv->cap_rhs) break;
-    int8_t st = 0;
-    size_t off = 0;
-    bool take = true;
-    if (c.reuse && q.keyed) {
-      auto e = srv->cache.map.find(q.key);
-      if (in_batch.count(q.key)) {
-        take = false;   // same key already factored by this launch: next launch reuses it
-      } else if (e != srv->cache.map.end()) {
-        if (!e->second.valid) {
-          take = false;   // its factorisation is still running
-        } else {
-          st = 1;
-          off = e->second.off;
-          e->second.pins++;
-          srv->cache.touch(q.key);
-        }
-      } else {
-        const size_t bytes = mhm_factor_bytes(q.s, (mhm_prec)c.prec);
-        if (!srv->cache.alloc(bytes, off)) break;   // no memory: wait for running launches
-        Entry en;
-        en.off = off;
-        en.bytes = bytes;
-        en.pins = 1;
-        srv->cache.lru.push_front(q.key);
-        en.lru = srv->cache.lru.begin();
-        srv->cache.map[q.key] = en;
-      }
-    } else {
-      // unkeyed (or reuse off): a scratch factor region, freed at completion
-      const size_t bytes = mhm_factor_bytes(q.s, (mhm_prec)c.prec);
-      Key tmp{~0ull, q.ticket};
-      if (!srv->cache.alloc(bytes, off)) break;
-      Entry en;
-      en.off = off;
-      en.bytes = bytes;
-      en.pins = 1;
-      srv->cache.lru.push_front(tmp);
-      en.lru = srv->cache.lru.begin();
-      srv->cache.map[tmp] = en;
-    }
-    if (!take) {
-      ++it;
-      continue;
-    }
-    if (st == 1) srv->stats.cache_hits++;
-    sl.pinned.push_back(c.reuse && q.keyed ? q.key : Key{~0ull, q.ticket});
-    if (c.reuse && q.keyed && st == 0) in_batch[q.key] = 1;
-    sl.state.push_back(st);
-    foff.push_back(off);
-    tri += (int64_t)q.s * q.s;
-    rhs += (int64_t)n * r;
-    sl.reqs.push_back(std::move(*it));
-    it = srv->queue.erase(it);
-  }
+  const mhm_srv::Limits lim{c.max_batch, srv->cap_tri, srv->cap_rhs, c.reuse != 0};
+  mhm_srv::admit(srv->cache, srv->queue, lim, [&](int s) { return mhm_factor_bytes(s, (mhm_prec)c.prec); },
+                 sl.reqs, sl.adm);
+  srv->stats.cache_hits += sl.adm.hits;
   const int B = (int)sl.reqs.size();
   if (B == 0) return false;
   // pack
@@ -315,8 +197,8 @@ bool launch(mhm_server srv, Slot& sl) {
     std::memcpy(hf + htri[e], q.f.data(), sizeof(double) * q.s * q.s);
     htri[e + 1] = htri[e] + (int64_t)q.s * q.s;
     hrhs[e + 1] = hrhs[e] + (int64_t)n_of(q.s) * (3 * (q.l + 1) + 1);
-    hfo[e] = (int64_t)foff[e];
-    hst[e] = sl.state[e];
+    hfo[e] = (int64_t)sl.adm.foff[e];
+    hst[e] = sl.adm.state[e];
     s_max = std::max(s_max, q.s);
     s_min = std::min(s_min, q.s);
     l_max = std::max(l_max, q.l);
@@ -356,14 +238,16 @@ bool launch(mhm_server srv, Slot& sl) {
   if (e == hipSuccess && st == MHM_OK)
     e = hipMemcpyAsync(h + sl.o_M, d + sl.o_M, sl.in_bytes + sl.out_bytes - sl.o_M, hipMemcpyDeviceToHost,
                        sl.stream);
-  if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+  if (e == hipSuccess && st == MHM_OK) e = hipEventRecord(sl.done, sl.stream);
+  srv->stats.launches++;
+  srv->stats.max_batch_seen = std::max<int64_t>(srv->stats.max_batch_seen, B);
   if (e != hipSuccess || st != MHM_OK) {
     srv->err = st != MHM_OK ? std::string(mhm_last_error(sl.ctx)) : std::string(hipGetErrorString(e));
     srv->stats.errors++;
+    fail_launch(srv, sl);
+    return true;
   }
   sl.busy = true;
-  srv->stats.launches++;
-  srv->stats.max_batch_seen = std::max<int64_t>(srv->stats.max_batch_seen, B);
   return true;
 }
 
@@ -388,7 +272,7 @@ void harvest(mhm_server srv, Slot& sl) {
     res.ticket = q.ticket;
     res.info = info[k];
     res.ir_iters = its[k];
-    res.cache_hit = sl.state[k] == 1;
+    res.cache_hit = sl.adm.state[k] == 1;
     res.s = q.s;
     res.l = q.l;
     res.n = n;
@@ -407,18 +291,7 @@ void harvest(mhm_server srv, Slot& sl) {
     m[ni * ni + 2 * ni] = F[k];
     srv->done.push_back(res);
     srv->done_data.push_back(std::move(data));
-    // factor bookkeeping
-    const Key pk = sl.pinned[k];
-    auto it = srv->cache.map.find(pk);
-    if (it != srv->cache.map.end()) {
-      it->second.pins--;
-      const bool keyed = !(pk.hi == ~0ull && pk.lo == q.ticket);
-      if (!keyed || res.info != 0) {
-        if (it->second.pins == 0) srv->cache.erase(pk);
-      } else {
-        it->second.valid = true;
-      }
-    }
+    mhm_srv::settle(srv->cache, sl.adm, k, true, res.info);
     srv->stats.completed++;
     if (res.info == -1) srv->stats.ir_fallbacks++;
   }
