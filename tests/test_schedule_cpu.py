@@ -77,3 +77,26 @@ def test_model_finds_a_barrier_only_some_waves_pass():
     logs, meta = m.simulate(inst, Launch.for_class(48, 3), 48, 3)
     logs[3].barriers.pop(10)
     assert any("barrier sequence" in p for p in check(logs, meta))
+
+
+# ---------------------------------------------------------------- k_local
+@pytest.mark.parametrize("s,l,fp32,fused,three_call", [
+    (4, 1, True, True, False), (16, 2, True, True, False), (16, 2, False, True, False),
+    (12, 2, False, False, True), (16, 2, True, False, True), (25, 3, True, True, False)])
+def test_local_kernel_schedule_has_no_race(s, l, fp32, fused, three_call):
+    """The right-looking tile kernel (LDS or workspace tiles): fill, panel,
+    trailing update with the look-ahead diagonal factorisation, sweeps,
+    refinement; the three-call form reads all of Ahat before writing L."""
+    from tests.local_schedule_model import simulate as lsim
+    logs, meta = lsim(s, l, fp32, fused, three_call=three_call)
+    assert not check(logs, meta)
+
+
+def test_local_model_finds_planted_mistakes():
+    from tests.local_schedule_model import simulate as lsim
+    logs, meta = lsim(16, 2, True, True, trail_skip_first=False)   # waves 1-3 also take tile (k+1, k+1)
+    assert any("look-ahead" in p or "diagonal factor" in p for p in check(logs, meta))
+    logs, meta = lsim(16, 2, True, True, drop=("panel",))
+    assert any("panel" in p and "trailing" in p for p in check(logs, meta))
+    logs, meta = lsim(16, 2, True, True, drop=("fill a",))
+    assert any("stencil add" in p for p in check(logs, meta))
