@@ -141,27 +141,189 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
   }
 }
 
+// --------------------------------------------------------------- k_contrib
+// One DPP step of a wave reduction on a double (both halves moved alike);
+// lanes of a masked-off row get 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_step(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over the 64 lanes of a wave (all lanes active), in every lane: lane
+// xor 1 and xor 2 (quad permutes), the mirrored lane of each half row and of
+// each row of 16 (every lane then holds its row's sum), lane 15 of rows 0 and
+// 2 into rows 1 and 3, lane 31 into rows 2 and 3; lane 63 has the total.
+__device__ __forceinline__ double wave_sum_rows(double v) {
+  v += dpp_step<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+  v += dpp_step<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+  v += dpp_step<0x141, 0xf>(v);   // row_half_mirror
+  v += dpp_step<0x140, 0xf>(v);   // row_mirror
+  v += dpp_step<0x142, 0xa>(v);   // row_bcast:15 into rows 1, 3
+  v += dpp_step<0x143, 0xc>(v);   // row_bcast:31 into rows 2, 3
+  return readlane(v, 63);
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)v), hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+// Orders one wave's LDS accesses around it (a wavefront-scope fence pair).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The face loads R(a, k) of lattice node k on face ef for every DoF a of that
+// face, written to ft[a (s + 1) + k]: the quantity face_load gives entry by
+// entry (eq. (9)), taken here node by node so that the Gauss points of the
+// node's two sub-edges and their Legendre values are computed once for all
+// the DoFs.  The Legendre recurrence q P_q = (2q - 1) t P_(q-1) - (q - 1)
+// P_(q-2) runs with its coefficients folded at compile time (q <= 4).
+__device__ __forceinline__ void face_node_loads(const Elem& E, int ef, int k, double* ft) {
+  constexpr int QN = MHM_L_LIMIT + 1;
+  const double r15 = 0.38729833462074168852;  // sqrt(15)/10
+  const double xg[3] = {0.5 - r15, 0.5, 0.5 + r15};
+  const double wg[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  const int s = E.s, lp1 = E.l + 1, m = E.m, per = s / m, sp1 = s + 1;
+  const bool fl = E.flip[ef] != 0;
+  double acc[2][QN];
+  int sg[2];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+#pragma unroll
+    for (int q = 0; q < QN; ++q) acc[side][q] = 0.0;
+    const int seg = side == 0 ? k - 1 : k;   // node k ends sub-edge k-1 and starts sub-edge k
+    sg[side] = -1;
+    if (seg < 0 || seg >= s) continue;
+    const int sgf = (fl ? s - 1 - seg : seg) / per;   // the segment (of the m) holding the sub-edge
+    sg[side] = sgf;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      const double tau = (seg + xg[g]) * E.inv_s;
+      const double gp = fl ? 1.0 - tau : tau;
+      const double t = 2.0 * (m * gp - sgf) - 1.0;
+      const double w = wg[g] * (side == 0 ? xg[g] : 1.0 - xg[g]);
+      double p0 = 1.0, p1 = t;
+      acc[side][0] += w;
+      acc[side][1] += w * t;
+#pragma unroll
+      for (int q = 2; q < QN; ++q) {
+        const double p2 = ((2.0 * q - 1.0) / q) * t * p1 - ((q - 1.0) / q) * p0;
+        acc[side][q] += w * p2;
+        p0 = p1;
+        p1 = p2;
+      }
+    }
+  }
+  const double scale = -(double)E.sigma[ef] * E.flen[ef] * E.inv_s;
+  double* col = ft + (size_t)ef * E.P * sp1 + k;
+  for (int segf = 0; segf < m; ++segf) {
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+      if (q < lp1) {
+        const double v = (sg[0] == segf ? acc[0][q] : 0.0) + (sg[1] == segf ? acc[1][q] : 0.0);
+        col[(size_t)(segf * lp1 + q) * sp1] = scale * v;
+      }
+    }
+  }
+}
+
+// Step a6 alone (the three-call form), eq. (6): the element's blocks
+//   M[a][b] = -sum_k R(a,k) X[node(ef,k)][b]  (b < NI),
+//   E[a]    =  sum_k R(a,k) X[node(ef,k)][NI],   B[a] = -sum_k R(a,k),
+// F = the integral of f, for the face DoFs a (face ef = a / P), k = 0..s
+// over the face's lattice nodes, R(a,k) the face load.  One wave per element
+// and no workgroup barriers: lane 0 decodes the element into the wave's LDS
+// slot; the lanes build the wave's table of R, one lane per face node; then,
+// per chunk of ccmax columns of X, the wave copies the face rows of
+// those columns into LDS - one load per (column, face node), so a load
+// instruction covers 64 entries instead of the few distinct nodes of a lane
+// per (a, b) pair - and each lane sums over k for its (a, b) pairs from LDS,
+// a fastest, so the stores of M run along its columns.  Dynamic LDS per wave
+// (`cap` doubles): the R table (NImax (s_max + 1)), the staged face rows
+// (ccmax 3 (s_max + 1)) and the 3 (s_max + 1) face-node offsets.
 __global__ void __launch_bounds__(NTHREADS) k_contrib(BatchDev b, const double* X, double* M, double* Ev,
-                                                       double* Bv, double* F, const int32_t* info) {
-  __shared__ Elem E;
-  __shared__ int ok;
-  __shared__ double red[48];
-  __shared__ double fsum;
-  extern __shared__ double ft[];   // NI(s+1)
+                                                       double* Bv, double* F, const int32_t* info, int cap,
+                                                       int ccmax) {
+  __shared__ Elem Ew[NWAVES];
+  extern __shared__ double ctab[];
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
   const int NImax = nimax(b);
-  for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
-    __syncthreads();
-    if (threadIdx.x == 0) ok = (info == nullptr || info[e] == 0 || info[e] == INFO_IR_FALLBACK) &&
-                               load_elem(b, e, E) && E.rhs0 >= 0;
-    __syncthreads();
-    if (!ok) continue;
-    face_table(E, ft);
-    double fs = 0.0, z1 = 0.0, z2 = 0.0;
-    for (int t = threadIdx.x; t < E.s * E.s; t += NTHREADS) fs += b.f[E.tri0 + t];
-    block_sum3(fs, z1, z2, red);   // barriers: ft visible afterwards
-    if (threadIdx.x == 0) fsum = fs * (E.area / ((double)E.s * E.s));
-    __syncthreads();
-    contrib_element(E, X + E.rhs0, ft, fsum, NImax, M, Ev, Bv, F, e);
+  Elem& E = Ew[wave];
+  double* ft = ctab + (size_t)wave * cap;
+  double* xs = ft + (size_t)NImax * (b.s_max + 1);
+  int* fnode = (int*)(xs + (size_t)ccmax * 3 * (b.s_max + 1));
+  for (int e = blockIdx.x * nw + wave; e < b.n_elem; e += gridDim.x * nw) {
+    if (info != nullptr && info[e] != 0 && info[e] != INFO_IR_FALLBACK) continue;
+    int ok = 0;
+    wave_sync();   // the previous element's reads of E and of the tables are done
+    if (lane == 0) ok = load_elem(b, e, E) && E.rhs0 >= 0;
+    wave_sync();
+    if (__builtin_amdgcn_readlane(ok, 0) == 0) continue;
+    // the element's sizes are the same in every lane: keep them scalar
+    const int s = uni(E.s), n = uni(E.n), r = uni(E.r), NI = uni(E.NI), P = uni(E.P), sp1 = s + 1;
+    const int nf = 3 * sp1;   // face nodes, face by face (a corner appears on two faces)
+    double* Me = M + (int64_t)e * NImax * NImax;
+    double* Ee = Ev + (int64_t)e * NImax;
+    double* Be = Bv + (int64_t)e * NImax;
+    {
+      double fs = 0.0;
+      const double* fe = b.f + uni64(E.tri0);
+#pragma unroll 8
+      for (int t = lane; t < s * s; t += 64) fs += fe[t];
+      fs = wave_sum_rows(fs);
+      if (lane == 0) F[e] = fs * (E.area / ((double)s * s));
+    }
+    for (int idx = lane; idx < nf; idx += 64) {
+      const int ef = idx / sp1, k = idx - ef * sp1;
+      face_node_loads(E, ef, k, ft);
+      fnode[idx] = 8 * face_node(ef, k, s);   // byte offset in a column of X
+    }
+    // padding of the blocks beyond NI (to NImax)
+    for (int idx = lane; idx < NImax * NImax; idx += 64) {
+      const int a = idx % NImax, bb = idx / NImax;
+      if (a >= NI || bb >= NI) Me[idx] = 0.0;
+    }
+    for (int a = NI + lane; a < NImax; a += 64) {
+      Ee[a] = 0.0;
+      Be[a] = 0.0;
+    }
+    wave_sync();
+    for (int a = lane; a < NI; a += 64) {
+      double v = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < sp1; ++k) v += ft[a * sp1 + k];
+      Be[a] = -v;
+    }
+    const char* Xc = (const char*)(X + uni64(E.rhs0));
+    for (int b0 = 0; b0 < r; b0 += ccmax) {
+      const int cc = r - b0 < ccmax ? r - b0 : ccmax;
+      // stage: xs[c nf + j] = X[b0 + c][node j]; byte offsets stay below
+      // 2^32 (r n 8 <= 49 * 2145 * 8)
+#pragma unroll 8
+      for (int idx = lane; idx < cc * nf; idx += 64) {
+        const int c = idx / nf, j = idx - c * nf;
+        xs[idx] = *(const double*)(Xc + (8u * (uint32_t)((b0 + c) * n) + (uint32_t)fnode[j]));
+      }
+      wave_sync();
+      for (int idx = lane; idx < NI * cc; idx += 64) {
+        const int c = idx / NI, a = idx - c * NI;
+        const double* Ra = ft + a * sp1;
+        const double* xa = xs + c * nf + (a / P) * sp1;
+        double v = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < sp1; ++k) v += Ra[k] * xa[k];
+        const int bb = b0 + c;
+        if (bb < NI) Me[(int64_t)bb * NImax + a] = -v;
+        else Ee[a] = v;
+      }
+      wave_sync();   // the reads of xs are done before the next chunk overwrites it
+    }
   }
 }
 
@@ -533,7 +695,7 @@ __global__ void __launch_bounds__(NTHREADS) k_reconstruct(BatchDev b, const doub
     }
     __syncthreads();
     const int n = E.n, NI = E.NI;
-    const double* Xe = X + E.rhs0;
+    const double* Xe = X + uni64(E.rhs0);
     for (int p = tid; p < n; p += NTHREADS) {
       double v = u0 + Xe[(int64_t)NI * n + p];
       for (int a = 0; a < NI; ++a) v += Xe[(int64_t)a * n + p] * lam[a];
@@ -713,10 +875,25 @@ hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, doub
 
 hipError_t launch_contrib(const mhm_batch* bt, const double* X, double* M, double* E, double* B, double* F,
                           const int32_t* info, int grid, hipStream_t st) {
-  const size_t lds = sizeof(double) * local_face_cap(bt);
+  // one wave per element.  LDS bounds how many elements run at once on a CU
+  // (160 KB): the staged columns per chunk (ccmax, 16 down to 1) are the
+  // most that keep a wave's tables within 10 KB (four workgroups of four
+  // waves per CU), as many waves per workgroup (up to four) as fit their
+  // tables in 64 KB, a workgroup for every nw elements (capped: the waves
+  // loop over the rest)
+  (void)grid;
+  const int fcap = local_face_cap(bt), nf = 3 * (bt->s_max + 1), ncap = (nf + 1) / 2;
+  int ccmax = 16;
+  while (ccmax > 1 && (size_t)(fcap + ccmax * nf + ncap) * sizeof(double) > 10240) ccmax /= 2;
+  const int cap = fcap + ccmax * nf + ncap;
+  int nw = (int)(65536 / (sizeof(double) * (size_t)cap));
+  nw = nw < 1 ? 1 : nw > NWAVES ? NWAVES : nw;
+  const size_t lds = sizeof(double) * (size_t)cap * nw;
   hipError_t err = hipFuncSetAttribute((const void*)k_contrib, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_contrib, dim3(grid), dim3(NTHREADS), lds, st, to_dev(bt), X, M, E, B, F, info);
+  const int64_t need = ((int64_t)bt->n_elem + nw - 1) / nw;
+  const int g = (int)(need < 65535 ? (need > 0 ? need : 1) : 65535);
+  hipLaunchKernelGGL(k_contrib, dim3(g), dim3(64 * nw), lds, st, to_dev(bt), X, M, E, B, F, info, cap, ccmax);
   return hipGetLastError();
 }
 
