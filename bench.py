@@ -204,6 +204,13 @@ def class_timing(torch, ctx, db, prec, out, reps):
             "dominant_tflops": tf, "dominant_frac_mfma_peak": tf / peak, "peak_tflops": peak}
 
 
+def _assemble_bytes(db):
+    """Algorithmic bytes of steps a2-a3 alone: kappa and f in; Ahat, Btilde,
+    c and the area out."""
+    n_, r_, s_ = db.n.astype(np.float64), db.r.astype(np.float64), db.s.astype(np.float64)
+    return float(np.sum(16 * s_ ** 2 + 8 * n_ ** 2 + 8 * n_ * r_ + 8 * n_ + 8))
+
+
 def _contrib_bytes(db):
     """Algorithmic bytes of step a6 alone: the face rows of X (3 s nodes, r
     columns) and f in; M, E, B, F out."""
@@ -249,13 +256,18 @@ def _batched_leg(torch, ctx, name, checks, sample_idx, reps=3):
     ms3 = _ms(torch, lambda: engine.run_three_call_bucketed(ctx, subs, abi.MHM_FP64, outs), reps)
     leg["fp64_three_call_per_bucket_ms"] = ms3
     leg["fp64_three_call_problems_per_s"] = E / (ms3 * 1e-3)
-    # step a6 alone (k_contrib) on the three-call outputs, bucket by bucket
-    ms_c, by_c = 0.0, 0.0
+    # steps a2-a3 (k_assemble) and a6 (k_contrib) alone on the three-call
+    # buffers, bucket by bucket (assembly last: it rewrites Ahat)
+    ms_c, by_c, ms_a, by_a = 0.0, 0.0, 0.0, 0.0
     for d, o in zip(subs, outs):
         ms_c += _ms(torch, lambda: ctx.skeleton_contrib(d, o["X"], o["M"], o["E"], o["B"], o["F"], o["info"]), reps)
         by_c += _contrib_bytes(d)
+        ms_a += _ms(torch, lambda: ctx.local_assemble(d, o["Ahat"], o["Btil"], o["c"], o["area"], o["info"]), reps)
+        by_a += _assemble_bytes(d)
     leg.update({"contrib_ms": ms_c, "contrib_GBps": by_c / (ms_c * 1e-3) / 1e9,
-                "contrib_frac_hbm": by_c / (ms_c * 1e-3) / 8e12})
+                "contrib_frac_hbm": by_c / (ms_c * 1e-3) / 8e12,
+                "assemble_ms": ms_a, "assemble_GBps": by_a / (ms_a * 1e-3) / 1e9,
+                "assemble_frac_hbm": by_a / (ms_a * 1e-3) / 8e12})
     leg["fp32_ir_graph_vs_plain_fp64_three_call"] = ms3 / leg["fp32_ir_graph_ms"]
     leg["fp32_ir_graph_vs_fp64_graph"] = leg["fp64_graph_ms"] / leg["fp32_ir_graph_ms"]
     leg["sample"] = f"{len(sample_idx)} elements against the FP64 oracle"
@@ -520,9 +532,7 @@ def _c2_leg(torch, ctx, args, checks):
     engine.run_three_call(ctx, db, abi.MHM_FP64, o3)
     ms_c = _ms(torch, lambda: ctx.skeleton_contrib(db, o3["X"], o3["M"], o3["E"], o3["B"], o3["F"], o3["info"]),
                args.steps)
-    n_, r_, s_ = db.n.astype(np.float64), db.r.astype(np.float64), db.s.astype(np.float64)
-    # assemble: kappa, f in; Ahat, Btilde, c, area out
-    by_a = float(np.sum(16 * s_ ** 2 + 8 * n_ ** 2 + 8 * n_ * r_ + 8 * n_ + 8))
+    by_a = _assemble_bytes(db)
     by_c = _contrib_bytes(db)
     leg.update({"assemble_ms": ms_a, "assemble_GBps": by_a / (ms_a * 1e-3) / 1e9,
                 "assemble_frac_hbm": by_a / (ms_a * 1e-3) / 8e12,
