@@ -20,6 +20,8 @@ constexpr int NTHREADS = 256;
 constexpr int NWAVES = NTHREADS / 64;
 
 // =============================================================== k_assemble
+constexpr int ASM_TAB = 256;   // elements of up to this many nodes use the stencil table
+template <bool TAB>
 __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat, double* Btil, double* cout,
                                                         double* area, int32_t* info) {
   __shared__ Elem E;
@@ -27,9 +29,15 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
   __shared__ double red[48];
   __shared__ double colsum[R_MAX];
   __shared__ double gam;
-  extern __shared__ double dyn[];   // kappa[s^2] | c[n] | bf[n] | ft[NI(s+1)] | stencil[7][n] | j[n]
+  // kappa[s^2] | c[n] | bf[n] | ft[NI(s+1)] | stencil[7][tn] | j[tn].  TAB: a
+  // stencil table for every element (tn = n_max); otherwise (where that
+  // would not fit in LDS) tn = min(n_max, 256): the table serves the
+  // elements of at most 256 nodes, and larger ones take each column's
+  // stencil where its wave writes the column (more registers)
+  extern __shared__ double dyn[];
   const int tid = threadIdx.x;
   const int smax = b.s_max, nmax = (smax + 1) * (smax + 2) / 2;
+  const int tn = TAB || nmax < ASM_TAB ? nmax : ASM_TAB;
   for (int e = blockIdx.x; e < b.n_elem; e += gridDim.x) {
     __syncthreads();
     if (tid == 0) {
@@ -43,8 +51,9 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
     double* c = kap + smax * smax;
     double* bf = c + nmax;
     double* ft = bf + nmax;
-    double* sd = ft + nimax(b) * (smax + 1);        // the seven stencil values of node q at sd[k nmax + q]
-    int* sj = reinterpret_cast<int*>(sd + 7 * nmax);  // lattice row j of node q
+    double* sd = ft + nimax(b) * (smax + 1);      // the seven stencil values of node q at sd[k tn + q]
+    int* sj = reinterpret_cast<int*>(sd + 7 * tn);  // lattice row j of node q
+    const bool tab = TAB || n <= ASM_TAB;
     for (int t = tid; t < T; t += NTHREADS) kap[t] = b.kappa[E.tri0 + t];
     face_table(E, ft);
     __syncthreads();
@@ -58,14 +67,16 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
       const double bp = E.cunit * node_tri_sum(i, j, s, [&](int t) { return fp[t]; });
       c[p] = cp;
       bf[p] = bp;
-      sd[p] = st.d;
-      sd[nmax + p] = st.e;
-      sd[2 * nmax + p] = st.w;
-      sd[3 * nmax + p] = st.n;
-      sd[4 * nmax + p] = st.so;
-      sd[5 * nmax + p] = st.nw;
-      sd[6 * nmax + p] = st.se;
-      sj[p] = j;
+      if (tab) {
+        sd[p] = st.d;
+        sd[tn + p] = st.e;
+        sd[2 * tn + p] = st.w;
+        sd[3 * tn + p] = st.n;
+        sd[4 * tn + p] = st.so;
+        sd[5 * tn + p] = st.nw;
+        sd[6 * tn + p] = st.se;
+        sj[p] = j;
+      }
       tr += st.d;
       cc2 += cp * cp;
       fs += bp;
@@ -82,15 +93,36 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
     // of n^2 values, consecutive threads on consecutive entries (full cache
     // lines; a column of a few lanes' width would leave most of a wave's last
     // store idle), each from the stencil table of its column q.  Larger ones:
-    // wave w writes columns q = w, w+4, ... with the column's stencil in
-    // registers, lanes sweeping rows.
+    // wave w writes columns q = w, w+4, ... with the column's stencil (from
+    // the table, or from kappa in LDS, the same in every lane) in registers,
+    // lanes sweeping rows.
     double* A = Ahat + E.mat0;
-    if (n > 256) {
+    if (n > ASM_TAB) {
       const int w = tid >> 6, lane = tid & 63;
       for (int q = w; q < n; q += NWAVES) {
-        const int j = sj[q];
-        const double d = sd[q], ve = sd[nmax + q], vw = sd[2 * nmax + q], vn = sd[3 * nmax + q],
-                     vs = sd[4 * nmax + q], vnw = sd[5 * nmax + q], vse = sd[6 * nmax + q];
+        int j;
+        double d, ve, vw, vn, vs, vnw, vse;
+        if (tab) {
+          j = sj[q];
+          d = sd[q];
+          ve = sd[tn + q];
+          vw = sd[2 * tn + q];
+          vn = sd[3 * tn + q];
+          vs = sd[4 * tn + q];
+          vnw = sd[5 * tn + q];
+          vse = sd[6 * tn + q];
+        } else {
+          int i;
+          node_ij(q, s, i, j);
+          const Stencil sq = stencil(i, j, s, E.G, [&](int t) { return kap[t]; });
+          d = sq.d;
+          ve = sq.e;
+          vw = sq.w;
+          vn = sq.n;
+          vs = sq.so;
+          vnw = sq.nw;
+          vse = sq.se;
+        }
         const int pE = q + 1, pW = q - 1, pN = q + (s + 1 - j), pS = q - (s + 2 - j), pNW = q + (s - j),
                   pSE = q - (s + 1 - j);
         const double gcq = g * c[q];
@@ -114,12 +146,12 @@ __global__ void __launch_bounds__(NTHREADS) k_assemble(BatchDev b, double* Ahat,
         const int j = sj[q], off = p - q;
         double v = g * c[q] * c[p];
         v += off == 0 ? sd[q] : 0.0;
-        v += off == 1 ? sd[nmax + q] : 0.0;
-        v += off == -1 ? sd[2 * nmax + q] : 0.0;
-        v += off == s + 1 - j ? sd[3 * nmax + q] : 0.0;
-        v += off == -(s + 2 - j) ? sd[4 * nmax + q] : 0.0;
-        v += off == s - j ? sd[5 * nmax + q] : 0.0;
-        v += off == -(s + 1 - j) ? sd[6 * nmax + q] : 0.0;
+        v += off == 1 ? sd[tn + q] : 0.0;
+        v += off == -1 ? sd[2 * tn + q] : 0.0;
+        v += off == s + 1 - j ? sd[3 * tn + q] : 0.0;
+        v += off == -(s + 2 - j) ? sd[4 * tn + q] : 0.0;
+        v += off == s - j ? sd[5 * tn + q] : 0.0;
+        v += off == -(s + 1 - j) ? sd[6 * tn + q] : 0.0;
         A[idx] = v;
         p += dp;
         q += dq;
@@ -865,26 +897,34 @@ hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, doub
                            int grid, hipStream_t st) {
   const int smax = bt->s_max;
   const int nmax = (smax + 1) * (smax + 2) / 2;
-  const size_t lds = sizeof(double) * ((size_t)smax * smax + 9 * (size_t)nmax + local_face_cap(bt)) +
-                     sizeof(int) * (size_t)nmax;
-  hipError_t err = hipFuncSetAttribute((const void*)k_assemble, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  auto lds_of = [&](int tn) {
+    return sizeof(double) * ((size_t)smax * smax + 2 * (size_t)nmax + local_face_cap(bt) + 7 * (size_t)tn) +
+           sizeof(int) * (size_t)tn;
+  };
+  // the full stencil table where it fits in the CU's 160 KB of LDS (s_max <=
+  // 56 or so), else the table for the small elements only
+  const bool full = lds_of(nmax) <= 160 * 1024;
+  const size_t lds = lds_of(full || nmax < ASM_TAB ? nmax : ASM_TAB);
+  const void* kern = full ? (const void*)k_assemble<true> : (const void*)k_assemble<false>;
+  hipError_t err = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_assemble, dim3(grid), dim3(NTHREADS), lds, st, to_dev(bt), Ahat, Btil, c, area, info);
+  if (full) hipLaunchKernelGGL(k_assemble<true>, dim3(grid), dim3(NTHREADS), lds, st, to_dev(bt), Ahat, Btil, c, area, info);
+  else hipLaunchKernelGGL(k_assemble<false>, dim3(grid), dim3(NTHREADS), lds, st, to_dev(bt), Ahat, Btil, c, area, info);
   return hipGetLastError();
 }
 
 hipError_t launch_contrib(const mhm_batch* bt, const double* X, double* M, double* E, double* B, double* F,
                           const int32_t* info, int grid, hipStream_t st) {
   // one wave per element.  LDS bounds how many elements run at once on a CU
-  // (160 KB): the staged columns per chunk (ccmax, 16 down to 1) are the
+  // (160 KB): the staged columns per chunk (ccmax, 16 down to 4) are the
   // most that keep a wave's tables within 10 KB (four workgroups of four
-  // waves per CU), as many waves per workgroup (up to four) as fit their
-  // tables in 64 KB, a workgroup for every nw elements (capped: the waves
-  // loop over the rest)
+  // waves per CU) where that leaves at least four, as many waves per
+  // workgroup (up to four) as fit their tables in 64 KB, a workgroup for
+  // every nw elements (capped: the waves loop over the rest)
   (void)grid;
   const int fcap = local_face_cap(bt), nf = 3 * (bt->s_max + 1), ncap = (nf + 1) / 2;
   int ccmax = 16;
-  while (ccmax > 1 && (size_t)(fcap + ccmax * nf + ncap) * sizeof(double) > 10240) ccmax /= 2;
+  while (ccmax > 4 && (size_t)(fcap + ccmax * nf + ncap) * sizeof(double) > 10240) ccmax /= 2;
   const int cap = fcap + ccmax * nf + ncap;
   int nw = (int)(65536 / (sizeof(double) * (size_t)cap));
   nw = nw < 1 ? 1 : nw > NWAVES ? NWAVES : nw;

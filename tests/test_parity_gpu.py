@@ -164,10 +164,11 @@ def test_large_elements(ctx, prec):
     _check(res, b, range(2), prec, f"large prec={prec}")
 
 
-def test_maximum_size_element(ctx):
+@pytest.mark.parametrize("mode", ["fused", "three_call"])
+def test_maximum_size_element(ctx, mode):
     b = _random_batch(14, [64], [4], "s64")
-    res = _run(ctx, b, 0, "fused")
-    _check(res, b, [0], 0, "s=64 l=4 FP64")
+    res = _run(ctx, b, 0, mode)
+    _check(res, b, [0], 0, f"s=64 l=4 FP64 {mode}")
 
 
 # ------------------------------------------------------------ edge cases
