@@ -164,11 +164,12 @@ def test_large_elements(ctx, prec):
     _check(res, b, range(2), prec, f"large prec={prec}")
 
 
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("mode", ["fused", "three_call"])
-def test_maximum_size_element(ctx, mode):
+def test_maximum_size_element(ctx, mode, prec):
     b = _random_batch(14, [64], [4], "s64")
-    res = _run(ctx, b, 0, mode)
-    _check(res, b, [0], 0, f"s=64 l=4 FP64 {mode}")
+    res = _run(ctx, b, prec, mode)
+    _check(res, b, [0], prec, f"s=64 l=4 prec={prec} {mode}")
 
 
 # ------------------------------------------------------------ edge cases
