@@ -156,3 +156,30 @@ def test_source_step_without_factor_reports_and_skips(ctx):
     for e in (0, 2):
         ex, eb = rel_errors(res[e], local.solve_element(bs, e))
         assert ex <= TOL[0] and eb <= TOL[0], (e, ex, eb)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stored_factors_beyond_the_left_looking_range_are_refused(ctx, prec):
+    """Factors are stored only by the left-looking kernel (s <= 48): a batch
+    with a larger element is refused with MHM_E_UNSUPPORTED before anything
+    is launched, both for the factoring call and for a source step, and the
+    context stays usable."""
+    from paper_1703_10435_amd import abi, engine
+    from paper_1703_10435_amd.batch import DeviceBatch
+    b = _random_batch(39, [16, 52], [1, 1], "cached-too-large")
+    db = DeviceBatch(b)
+    fs = engine.FactorStore(db, prec)
+    say(f"[gpu] stored factors with s = 52 prec={prec} (refused on the host)")
+    with pytest.raises(abi.MhmError) as ei:
+        engine.run_cached(ctx, db, fs)
+    assert ei.value.status == abi.MHM_E_UNSUPPORTED
+    out = db.alloc_outputs(three_call=False)
+    with pytest.raises(abi.MhmError) as ei:
+        engine.source_step(ctx, db, fs, out)
+    assert ei.value.status == abi.MHM_E_UNSUPPORTED
+    ok = _random_batch(40, [16, 24], [1, 2], "cached-after-refusal")
+    dok = DeviceBatch(ok)
+    fok = engine.FactorStore(dok, prec)
+    res = dok.unpack(engine.run_cached(ctx, dok, fok))
+    ctx.sync()
+    _check_all(res, ok, prec, "after refusal")
