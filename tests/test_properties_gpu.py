@@ -10,7 +10,8 @@ element (the oracle checks a sample; these hold for any size):
 
 The helpers are pinned to the oracle on the CPU (``not gpu`` tests below),
 then applied to every element of C4 (fused, both precisions, the headline
-workload) and C3 (the three calls, both precisions)."""
+workload), C3 (the three calls, both precisions) and C3 with four segments
+per face (both forms and precisions)."""
 from __future__ import annotations
 
 import numpy as np
@@ -161,12 +162,18 @@ def ctx():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("cfg,mode", [("C4", "fused"), ("C3", "three_call")])
+@pytest.mark.parametrize("cfg,mode", [("C4", "fused"), ("C3", "three_call"), ("W", "fused"), ("W", "three_call")])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_every_element_of_the_benchmark_batches(ctx, cfg, mode, prec):
+    """W: C3's mesh and fields with m = 4 segments per face (N_I = 48, 49
+    right-hand sides in four 16-column chunks)."""
     from mhm_inputs import configs
     from paper_1703_10435_amd import engine
-    b = configs.make(cfg)
+    if cfg == "W":
+        b = configs.make("C3")
+        b["m"] = np.full(b["n_elem"], 4, dtype=np.int32)
+    else:
+        b = configs.make(cfg)
     say(f"[gpu] {cfg} all {b['n_elem']} elements prec={prec} mode={mode}")
     res, out, db = engine.solve_batch(b, prec=prec, mode=mode, ctx=ctx)
     check_properties(res, b, prec, f"{cfg} prec={prec} {mode}")
