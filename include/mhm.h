@@ -49,10 +49,13 @@
  *      0   success
  *      k>0 non-positive pivot at column k (1-based) of Ahat: the element's
  *          outputs are filled with NaN (LAPACK potrf convention)
- *     -1   the FP32 factorisation with FP64 refinement did not reach the
- *          tolerance (within max_iters steps, or its observed contraction
- *          said it would not); the element was recomputed with the FP64
- *          path and its outputs are valid
+ *     -1   the element's results come from the FP64 path, not from the
+ *          FP32 factorisation with FP64 refinement: the refinement did not
+ *          reach the tolerance (within max_iters steps, or its observed
+ *          contraction said it would not), or, in the fused one-launch
+ *          form without a factor store, the element's contrast times s^2
+ *          exceeded the bound of MHM_OPT_REFINE64 (s >= 17), so no FP32
+ *          attempt was made (ir_iters 0); its outputs are valid
  *     -2   the element's descriptor is inconsistent (s or l out of range,
  *          offsets that disagree with s and l or exceed the *_total sizes,
  *          sign/flip flags out of range, a non-positive area); nothing of
@@ -153,7 +156,11 @@ mhm_status mhm_set_stream(mhm_ctx ctx, void* hip_stream);
  *                    residual Btilde - Ahat X accumulated in double-double
  *                    (the solution then matches the exact one of the
  *                    assembled system to about 1e-15); 1: every element;
- *                    -1: none.  ir_iters reports the step (1).
+ *                    -1: none.  ir_iters reports the step (1).  With
+ *                    MHM_FP32_IR the same bound (unless -1) sends such an
+ *                    element of the fused form straight to the FP64 path
+ *                    (info -1): its FP32 refinement would contract slowly
+ *                    or stall.
  *  Launch configuration (the results do not depend on them, beyond
  *  rounding; used to exercise kernel families the defaults do not pick, and
  *  reproduced by mhm_autotune's timings):

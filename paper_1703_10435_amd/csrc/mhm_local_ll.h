@@ -337,6 +337,20 @@ __global__ void __launch_bounds__(64 * NWV, (NWV / 4) * OCC) k_local_ll(BatchDev
         continue;
       }
     }
+    // FP32: an element whose contrast s^2 exceeds the same bound would take
+    // many refinement steps (each one contracts the error by about the
+    // element's condition number times the FP32 unit roundoff) or stall; in
+    // the fused one-chunk form without a factor store it goes straight to the
+    // FP64 pass that follows this launch (info -1, no refinement steps
+    // counted), which factors it in FP64 with its refinement step.  (The
+    // chunked instances keep the FP32 attempt: with the test their update
+    // loop spills.)
+    if constexpr (sizeof(T) == 4 && FUSED && !MC) {
+      if (!args.fac && refine64_needed(args.refine64 < 0 ? -1 : 0, kapg, s, red)) {
+        if (tid == 0) args.info[e] = INFO_IR_FALLBACK;
+        continue;
+      }
+    }
     const bool ref64 = REF && need64;
     // factor output: the three-call form, and the FP64 refinement pass over
     // the elements such a call deferred (that pass works from kappa)

@@ -260,7 +260,7 @@ def simulate(inst: Instance, lau: Launch, s: int, l: int, ref64: bool = False, i
                 for k in range(s + 1):
                     lds_d("r", "ft", a * (s + 1) + k, "face colsums")
         g.bar("set-up end")
-        if not fp32:
+        if not fp32 or inst.fused:   # FP64: the refinement criterion; fused FP32: the deferral test
             g.bar("refine64 a")
             g.bar("refine64 b")
         # ------------------------------------------------ factorisation
