@@ -95,15 +95,37 @@ def test_c3_channel_elements_fp64(ctx, c3, mode):
 
 def test_c3_channel_elements_fp32_ir(ctx, c3):
     """FP32 factors with FP64 refinement on the whole C3 batch, compared on
-    the channel sample at the FP32 + refinement bar."""
+    the channel sample at the FP32 + refinement bar.  The channel elements
+    (contrast 1e4 at s = 32: contrast s^2 above 2^20) go straight to the FP64
+    pass (info -1, no FP32 refinement steps); the others refine in FP32."""
     b, chan, sample, back = c3
     res = _full(ctx, b, 1, "fused")
     info = np.array([r["info"] for r in res])
     its = np.array([r["ir_iters"] for r in res])
-    say(f"  C3 FP32+IR: fallbacks {int(np.sum(info == -1))} of {chan.size} channel elements, "
-        f"refinement steps on channel elements {np.bincount(its[chan]).tolist()}")
-    assert np.all((info == 0) | (info == -1))
+    rest = np.setdiff1d(np.arange(b["n_elem"]), chan)
+    say(f"  C3 FP32+IR: FP64 path on {int(np.sum(info == -1))} elements ({chan.size} channel elements), "
+        f"refinement steps elsewhere {np.bincount(its[rest]).tolist()}")
+    assert np.all(info[chan] == -1) and np.all(its[chan] == 0)
+    assert np.all(info[rest] == 0) and np.all(its[rest] >= 1)
     _check(res, b, np.concatenate([sample, back]), 1, "C3 channel FP32+IR fused")
+
+
+def test_fp32_attempt_on_channel_elements_without_the_bound(c3):
+    """MHM_OPT_REFINE64 = -1 also lifts the FP32 deferral: channel elements
+    then try the FP32 factor with refinement (several steps, or the FP64
+    recomputation after a stall) and still meet the bar."""
+    from paper_1703_10435_amd import abi, engine
+    b, chan, sample, back = c3
+    sub = configs.sub_batch(b, np.concatenate([sample[:6], back]))
+    c = abi.Context(0, refine64=-1)
+    try:
+        say("[gpu] C3 channel sample FP32+IR with refine64=-1")
+        res, out, db = engine.solve_batch(sub, prec=1, mode="fused", ctx=c)
+    finally:
+        c.close()
+    its = np.array([r["ir_iters"] for r in res])
+    assert np.all(its >= 1), its
+    _check(res, sub, range(sub["n_elem"]), 1, "C3 channel FP32+IR, no deferral")
 
 
 @pytest.mark.parametrize("mode", ["fused", "three_call"])
