@@ -48,6 +48,16 @@ def rows_per_wave(nt: int, nw: int) -> int:
     return -1
 
 
+def launch_rows(fp32: bool, pw: int, nt: int, ref: bool = False, mc: bool = False) -> int:
+    """Rows per wave of the instance the library launches (one workgroup per
+    CU, 8 waves): FP64 four-tile panels for five rows per wave run on the
+    ten-row instance."""
+    rpw = rows_per_wave(nt, 8)
+    if not fp32 and not ref and not mc and pw == 4 and rpw == 5:
+        return 10
+    return rpw
+
+
 @dataclass
 class Instance:
     """Template parameters of one k_local_ll instance (one-chunk forms)."""

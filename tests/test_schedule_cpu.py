@@ -10,13 +10,14 @@ from __future__ import annotations
 
 import pytest
 
-from tests.ll_schedule_model import Instance, Launch, check, rows_per_wave, simulate
+from tests.ll_schedule_model import Instance, Launch, check, launch_rows, simulate
 
 # (fp32, panel width, s of the launch class, l_max, elements' s, refining instance)
 CASES = [
     (False, 4, 48, 3, [48, 34], False),   # C4's s = 48 class (FP64 default)
     (False, 2, 48, 3, [48], True),        # the FP64 refinement pass at s = 48
-    (False, 2, 33, 3, [32, 26], False),   # s <= 33 class
+    (False, 4, 33, 3, [32, 26], False),   # s <= 33 class (FP64 default: four-tile panels, ten-row instance)
+    (False, 2, 33, 3, [32, 26], False),   # the same class with two-tile panels (the tuner's other choice)
     (False, 2, 33, 3, [32], True),
     (False, 2, 16, 2, [10, 12, 16], True),   # the refinement pass over small deferred elements
     (True, 4, 48, 3, [48, 40], False),    # FP32 + refinement
@@ -27,7 +28,7 @@ CASES = [
 
 def _run(fp32, pw, s_cap, l_max, s, ref, **kw):
     nt = ((s_cap + 1) * (s_cap + 2) // 2 + 15) // 16
-    inst = Instance(fp32=fp32, pw=pw, rpw=rows_per_wave(nt, 8), ref=ref, fused=not kw.get("three_call", False))
+    inst = Instance(fp32=fp32, pw=pw, rpw=launch_rows(fp32, pw, nt, ref), ref=ref, fused=not kw.get("three_call", False))
     logs, meta = simulate(inst, Launch.for_class(s_cap, l_max), s, l_max, ref64=ref, **kw)
     return check(logs, meta)
 
