@@ -33,7 +33,7 @@ def ctx():
 @pytest.fixture(scope="module")
 def c3():
     """The whole C3 batch and a seeded sample of its channel elements
-    (element 3452, the worst of the first round's bench sample, plus 32 more)
+    (element 3452, the least accurate of an earlier bench sample, plus 32 more)
     and two background elements."""
     b = configs.make("C3")
     to = b["tri_off"]
