@@ -901,9 +901,10 @@ hipError_t launch_assemble(const mhm_batch* bt, double* Ahat, double* Btil, doub
     return sizeof(double) * ((size_t)smax * smax + 2 * (size_t)nmax + local_face_cap(bt) + 7 * (size_t)tn) +
            sizeof(int) * (size_t)tn;
   };
-  // the full stencil table where it fits in the CU's 160 KB of LDS (s_max <=
-  // 56 or so), else the table for the small elements only
-  const bool full = lds_of(nmax) <= 160 * 1024;
+  // the full stencil table where it fits in the CU's 160 KB of LDS next to
+  // the kernel's static arrays (4 KB kept for them; s_max <= 53 at the
+  // largest p_max), else the table for the small elements only
+  const bool full = lds_of(nmax) + 4096 <= 160 * 1024;
   const size_t lds = lds_of(full || nmax < ASM_TAB ? nmax : ASM_TAB);
   const void* kern = full ? (const void*)k_assemble<true> : (const void*)k_assemble<false>;
   hipError_t err = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
